@@ -1,0 +1,212 @@
+/*
+ * wilson.h -- C ABI of the MI355X (gfx950) Wilson-Dirac stencil and Krylov
+ * solver library (libwilson.so).
+ *
+ * What it computes (Kanamori & Matsufuru, arXiv:1712.01505):
+ *   Sec. II-B, eq. (1): the Wilson fermion matrix on a 4-D lattice with SU(3)
+ *   links U_mu(x) and 4-spin x 3-colour fields, periodic or antiperiodic
+ *   boundaries.  The library uses the hopping-parameter normalisation
+ *       D = 1 - kappa H = 2 kappa D_W,   kappa = 1 / (2 m0 + 8),
+ *       (H psi)(x) = sum_mu [ s+ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                           + s- (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ],
+ *   where s+/s- are the boundary signs of hops that wrap around the lattice.
+ *   Sec. II-C: linear solves D x = b by BiCGStab and by CG on the normal
+ *   equations (CGNR); a mixed-precision solve whose inner solver runs in a
+ *   lower precision.
+ *   Sec. IV-A: the solver is offloaded from the host code to a separately
+ *   tuned library whose fields may take any data layout and type; here that
+ *   library is this C ABI, with caller-owned device buffers.
+ *
+ * Gamma matrices: chiral (DeGrand-Rossi) basis, Hermitian,
+ *   gamma_5 = gamma_x gamma_y gamma_z gamma_t = diag(1, 1, -1, -1).
+ *
+ * CONVENTIONS
+ *   dims = {Lx, Ly, Lz, Lt}, each >= 2; site index s = x + Lx*(y + Ly*(z + Lz*t));
+ *   V = Lx*Ly*Lz*Lt <= 2^31 - 1.  bc[mu] = +1 periodic, -1 antiperiodic
+ *   (default {1, 1, 1, -1}).
+ *   Canonical (caller) layouts, complex128 (re, im interleaved):
+ *     spinor  [nrhs][Lt][Lz][Ly][Lx][spin 4][colour 3]
+ *     gauge   [mu 4][Lt][Lz][Ly][Lx][row 3][col 3]   (links must be SU(3):
+ *             the library stores two rows and rebuilds the third as
+ *             conj(row0 x row1), which holds only for unitary det-1 links)
+ *   Packed (library) layouts, produced by wl_pack_* and sized by
+ *   wl_field_bytes; opaque to callers except for their size:
+ *     spinor  [nrhs][chunk][V] 16-byte chunks, site-contiguous per component
+ *             (WL_F64: 12 chunks of 1 complex; WL_F32: 6 chunks of 2 complex;
+ *              WL_BF16S / WL_F16S: 3 chunks of 4 complex of 16-bit reals, then
+ *              [nrhs][V] FP32 per-site scales = max |real| of the site).
+ *     gauge   [mu 4][V][2 rows x 3 cols] in the same site-contiguous form.
+ *
+ * MEMORY AND STREAMS
+ *   Every field pointer is a device pointer to a caller-owned allocation
+ *   (typically a torch tensor's data_ptr), 16-byte aligned.  `stream` is a
+ *   hipStream_t (NULL = the default stream).  wl_op borrows the packed-link
+ *   pointer: keep it alive and unchanged while the op exists.
+ *   Stencil, pack and force calls are asynchronous on `stream`.  Solvers
+ *   synchronise `stream` (they read convergence scalars) and return after
+ *   completion.
+ *
+ * ERRORS
+ *   0 = WL_OK.  Positive = completed, result usable, see stats.  Negative =
+ *   nothing was launched (argument error) or the HIP runtime reported an
+ *   error (WL_EHIP; wl_last_hip_error() returns the hipError_t).
+ */
+#ifndef WILSON_H
+#define WILSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    WL_OK = 0,
+    WL_NOT_CONVERGED = 1, /* maxiter reached; x is the last iterate */
+    WL_BREAKDOWN = 2,     /* BiCGStab rho, <r^,v> or omega vanished */
+    WL_STAGNATED = 3,     /* mixed solve stopped reducing the true residual */
+    WL_EINVAL = -1,       /* bad dims/bc/nrhs/NULL/flag */
+    WL_EALIGN = -2,       /* a pointer is not 16-byte aligned */
+    WL_EPREC = -3,        /* unsupported precision or precision pairing */
+    WL_EHIP = -4,         /* HIP runtime error */
+    WL_ENAN = -5,         /* NaN/Inf in a residual */
+    WL_EWORKSPACE = -6    /* workspace too small */
+};
+
+/* Storage precision of packed fields.  *S = 16-bit storage with an FP32
+ * per-site scale for spinors; arithmetic is FP64 for WL_F64, FP32 otherwise. */
+typedef enum { WL_F64 = 0, WL_F32 = 1, WL_BF16S = 2, WL_F16S = 3 } wl_prec;
+
+enum { WL_SPINOR = 0, WL_GAUGE = 1 };
+enum { WL_SOLVER_CGNR = 0, WL_SOLVER_BICGSTAB = 1 };
+
+typedef struct {
+    int32_t dims[4]; /* Lx, Ly, Lz, Lt */
+    int32_t bc[4];   /* +1 periodic, -1 antiperiodic */
+} wl_geom;
+
+typedef struct wl_op wl_op; /* geometry + kappa + precision + borrowed links */
+
+/* Bytes of a packed field of `kind` (WL_SPINOR with nrhs right-hand sides,
+ * or WL_GAUGE with nrhs ignored) in precision `prec`. */
+int wl_field_bytes(const wl_geom *g, int kind, int prec, int nrhs, size_t *out_bytes);
+
+/* Canonical complex128 gauge field -> packed links (two rows) in `prec`.
+ * Paper Sec. IV-A (data layout flexible per architecture). Async. */
+int wl_pack_gauge(const wl_geom *g, int prec, const void *U_canon, void *U_packed, void *stream);
+
+/* Canonical complex128 spinors -> packed spinors (round to nearest even).  Async. */
+int wl_pack_spinor(const wl_geom *g, int prec, int nrhs, const void *psi_canon, void *psi_packed, void *stream);
+
+/* Packed spinors -> canonical complex128.  Async. */
+int wl_unpack_spinor(const wl_geom *g, int prec, int nrhs, const void *psi_packed, void *psi_canon, void *stream);
+
+/* Packed -> packed precision conversion, out = in (both packed).  Async. */
+int wl_convert_spinor(const wl_geom *g, int prec_in, int prec_out, int nrhs, const void *in, void *out,
+                      void *stream);
+
+/* Create/destroy an operator.  `U_packed` must have been packed in `prec`. */
+int wl_op_create(const wl_geom *g, double kappa, int prec, const void *U_packed, wl_op **out);
+int wl_op_destroy(wl_op *op);
+
+/* out = H in (dagger = 0), or the hopping term of D^dag (dagger = 1); eq. (1)
+ * without the diagonal; 1320 flop/site per right-hand side.  `in` and `out`
+ * are packed spinors of the op's precision with nrhs right-hand sides and
+ * must not overlap.  Async. */
+int wilson_dslash(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream);
+
+/* out = D in = in - kappa H in (dagger = 1: D^dag in = gamma5 D gamma5 in);
+ * eq. (1) in the kappa normalisation; 1368 flop/site per right-hand side
+ * (paper Table I).  Same buffer rules as wilson_dslash.  Async. */
+int wilson_apply(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream);
+
+typedef struct {
+    double tol;           /* stop when ||b - D x|| <= tol ||b|| (true residual, FP64) */
+    int maxiter;          /* Krylov iterations (summed over inner solves when mixed) */
+    double inner_tol;     /* mixed: relative tolerance of each inner solve (0 = default) */
+    int max_outer;        /* mixed: maximum outer (refinement) cycles (0 = default 50) */
+    int reliable;         /* mixed: 0 = restart inner solve per cycle, 1 = reliable updates */
+    int check_every;      /* host convergence check period in iterations (0 = default) */
+    int use_x0;           /* 1 = x holds the initial guess on entry, 0 = start from x = 0 */
+    void *workspace;      /* device scratch, NULL = library allocates for the call */
+    size_t workspace_bytes;
+} wl_solve_params;
+
+typedef struct {
+    int iters;            /* Krylov iterations performed for this right-hand side */
+    int outer;            /* outer refinement cycles (mixed) */
+    int stencil_calls;    /* stencil applications (all precisions) */
+    int converged;        /* 1 if the final true relative residual <= tol */
+    double iter_rel_res;  /* final iterated (recursive) relative residual */
+    double true_rel_res;  /* final true relative residual ||b - D x|| / ||b|| (FP64) */
+    double seconds;       /* wall time of the whole call */
+} wl_solve_stats;
+
+/* Device workspace needed by a solve (hi op; lo op or NULL; solver id). */
+int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs, size_t *out_bytes);
+
+/* Solve D x = b for nrhs right-hand sides at once (per-right-hand-side
+ * scalars; converged columns are frozen).  x, b: packed spinors of hi's
+ * precision.  lo == NULL: plain solve in hi's precision (CGNR: Sec. II-C,
+ * CG on D^dag D; BiCGStab: Sec. II-C / V-C).  lo != NULL: mixed precision --
+ * FP64 outer true-residual refinement around an inner solve in lo's
+ * precision (Sec. II-C: the inner low-precision solver sets the speed).
+ * stats: array of nrhs entries (may be NULL).  Synchronises `stream`.
+ * Returns the worst status over right-hand sides. */
+int solve_cgnr(const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *p,
+               wl_solve_stats *stats, void *stream);
+int solve_bicgstab(const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *p,
+                   wl_solve_stats *stats, void *stream);
+
+/* Derivative of a solve with respect to the links, for x = D^{-1} b and the
+ * adjoint mu = D^{-dag} g (g = dL/dRe x + i dL/dIm x):
+ *   dL = Re sum_{x,mu} Tr[dU_mu(x) G_mu(x)],
+ *   G_mu(x) = kappa s_mu(x) [ sum_spin ((1 - g_mu) x(x+mu)) mu(x)^dag
+ *                           + sum_spin mu(x+mu) ((1 + g_mu) x(x))^dag ].
+ * project = 0: out = G^dag (the unconstrained complex gradient dL/dRe U + i dL/dIm U);
+ * project = 1: out = P = traceless Hermitian part of i U G (the su(3) force;
+ *              the tangent gradient is i P U).
+ * x, mu: packed spinors of the op's precision (WL_F64 or WL_F32), nrhs = 1.
+ * out: canonical complex128 gauge layout.  Async. */
+int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const void *mu, int project,
+                       void *stream);
+
+/* One persistent launch applying D (or D^dag) to several lattices of
+ * different sizes: entry i computes out_i = D_i in_i with nrhs right-hand
+ * sides.  All ops must share one precision.  Work is split into fixed-size
+ * site tiles drawn from one device-wide queue.  Async. */
+typedef struct {
+    const wl_op *op;
+    void *out;
+    const void *in;
+} wl_multi_desc;
+int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void *stream);
+
+/* Time the stencil launch candidates for (op geometry, precision, nrhs,
+ * dagger) with HIP events and keep the fastest; the choice is cached in
+ * memory and in the JSON file named by $WL_TUNE_CACHE (if set).  Synchronous. */
+int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
+
+/* Launch configuration currently used for (op, nrhs): block size, RHS per
+ * thread, XCD-aware tile order flag. */
+int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rhs_per_thread, int *xcd_remap);
+/* Force a launch configuration (block in {64,128,256,512}; rhs_per_thread in
+ * 1..4 dividing nrhs; xcd_remap 0/1).  Used by tests and the autotuner. */
+int wl_set_launch(wl_op *op, int nrhs, int block, int rhs_per_thread, int xcd_remap);
+
+/* Stencil timing: when enabled, every stencil launch is bracketed by HIP
+ * events on its stream; wl_prof_read synchronises and returns, for stencil
+ * launches of storage precision `prec`, the number of launches, their summed
+ * duration in ms and the summed sites x right-hand sides processed. */
+int wl_prof_enable(int on);
+int wl_prof_reset(void);
+int wl_prof_read(int prec, long *launches, double *total_ms, double *site_rhs);
+
+const char *wl_strerror(int code);
+int wl_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WILSON_H */

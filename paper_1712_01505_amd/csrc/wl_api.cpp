@@ -1,0 +1,594 @@
+// wl_api.cpp -- the C ABI (include/wilson.h): argument checking, operator
+// objects, launch-configuration choice and autotuning, stencil timing, and
+// the dispatch into the kernels and solver drivers.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "wl_internal.h"
+
+namespace wl {
+size_t solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs);
+int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *prm,
+          wl_solve_stats *stats, hipStream_t st);
+
+static thread_local int g_last_hip = 0;
+void set_last_hip_error(hipError_t e) { g_last_hip = (int)e; }
+
+// ---------------------------------------------------------------- argument checks
+static bool geom_ok(const wl_geom *g)
+{
+    if (!g)
+        return false;
+    uint64_t V = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (g->dims[i] < 2)
+            return false;
+        if (g->bc[i] != 1 && g->bc[i] != -1)
+            return false;
+        V *= (uint64_t)g->dims[i];
+    }
+    return V <= 0x7fffffffull;
+}
+static uint32_t vol(const wl_geom *g) { return (uint32_t)g->dims[0] * g->dims[1] * g->dims[2] * g->dims[3]; }
+static bool prec_ok(int p) { return p >= WL_F64 && p <= WL_F16S; }
+static bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+#define CHECK_HIP(expr)                                                                                        \
+    do {                                                                                                       \
+        hipError_t e_ = (expr);                                                                                \
+        if (e_ != hipSuccess) {                                                                                \
+            set_last_hip_error(e_);                                                                            \
+            return WL_EHIP;                                                                                    \
+        }                                                                                                      \
+    } while (0)
+
+// ---------------------------------------------------------------- stencil timing
+struct ProfRec {
+    int prec;
+    hipEvent_t a, b;
+    double sites;
+};
+static std::atomic<int> g_prof_on{0};
+static std::mutex g_prof_mu;
+static std::vector<ProfRec> g_prof_pending;
+static double g_prof_ms[4] = {0, 0, 0, 0}, g_prof_sites[4] = {0, 0, 0, 0};
+static long g_prof_n[4] = {0, 0, 0, 0};
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t take_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+static void drain_prof_locked()
+{
+    for (auto &r : g_prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_prof_ms[r.prec] += ms;
+            g_prof_sites[r.prec] += r.sites;
+            g_prof_n[r.prec] += 1;
+        }
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_prof_pending.clear();
+}
+
+hipError_t prof_stencil(int prec, const wl_op *op, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st)
+{
+    if (!g_prof_on.load(std::memory_order_relaxed))
+        return launch_stencil(prec, dagger, cfg, p, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof_pending.size() > 4096)
+        drain_prof_locked();
+    hipEvent_t a = take_event(), b = take_event();
+    if (!a || !b)
+        return launch_stencil(prec, dagger, cfg, p, st);
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess)
+        e = launch_stencil(prec, dagger, cfg, p, st);
+    if (e == hipSuccess)
+        e = hipEventRecord(b, st);
+    if (e == hipSuccess)
+        g_prof_pending.push_back(ProfRec{prec, a, b, (double)p.V * p.nrhs});
+    (void)op;
+    return e;
+}
+
+// ---------------------------------------------------------------- launch choice and autotune cache
+static std::mutex g_tune_mu;
+static std::map<std::string, LaunchCfg> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string n = prop.gcnArchName;
+    const size_t c = n.find(':');
+    return c == std::string::npos ? n : n.substr(0, c);
+}
+
+static std::string tune_key(const wl_op *op, int nrhs, int dagger)
+{
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s:%dx%dx%dx%d:p%d:n%d:d%d", arch_name().c_str(), op->g.dims[0], op->g.dims[1],
+             op->g.dims[2], op->g.dims[3], op->prec, nrhs, dagger);
+    return buf;
+}
+
+// Cache file: one line per entry, "key block rpt xcd".
+static void load_tune_cache_locked()
+{
+    if (g_tune_loaded)
+        return;
+    g_tune_loaded = true;
+    const char *path = getenv("WL_TUNE_CACHE");
+    if (!path)
+        return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string key;
+        LaunchCfg c;
+        if (is >> key >> c.block >> c.rpt >> c.xcd)
+            g_tune[key] = c;
+    }
+}
+
+static void save_tune_cache_locked()
+{
+    const char *path = getenv("WL_TUNE_CACHE");
+    if (!path)
+        return;
+    std::ofstream f(path, std::ios::trunc);
+    for (auto &kv : g_tune)
+        f << kv.first << " " << kv.second.block << " " << kv.second.rpt << " " << kv.second.xcd << "\n";
+}
+
+static LaunchCfg default_launch(int prec, int nrhs)
+{
+    LaunchCfg c;
+    c.block = 256;
+    c.xcd = 1;
+    c.rpt = 1;
+    if (prec != WL_F64) {
+        if (nrhs % 4 == 0)
+            c.rpt = 4;
+        else if (nrhs % 2 == 0)
+            c.rpt = 2;
+        else if (nrhs % 3 == 0)
+            c.rpt = 3;
+    } else if (nrhs % 2 == 0) {
+        c.rpt = 2;
+    }
+    return c;
+}
+
+LaunchCfg launch_for(const wl_op *op, int nrhs)
+{
+    wl_op *o = const_cast<wl_op *>(op);
+    {
+        std::lock_guard<std::mutex> lk(o->mu);
+        auto it = o->launch.find(nrhs);
+        if (it != o->launch.end())
+            return it->second;
+    }
+    LaunchCfg c = default_launch(op->prec, nrhs);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_cache_locked();
+        auto it = g_tune.find(tune_key(op, nrhs, 0));
+        if (it != g_tune.end())
+            c = it->second;
+    }
+    std::lock_guard<std::mutex> lk(o->mu);
+    o->launch[nrhs] = c;
+    return c;
+}
+
+static StencilParams base_params(const wl_op *op, void *out, const void *in, int nrhs, int apply)
+{
+    StencilParams p{};
+    p.U = op->U;
+    p.in = in;
+    p.out = out;
+    for (int i = 0; i < 4; ++i) {
+        p.L[i] = op->g.dims[i];
+        p.bc[i] = op->g.bc[i];
+    }
+    p.fx = make_fastdiv((uint32_t)p.L[0]);
+    p.fy = make_fastdiv((uint32_t)p.L[1]);
+    p.fz = make_fastdiv((uint32_t)p.L[2]);
+    p.V = op->V;
+    p.nrhs = nrhs;
+    p.kappa = op->kappa;
+    p.apply = apply;
+    p.red = RED_NONE;
+    return p;
+}
+
+}  // namespace wl
+
+using namespace wl;
+
+extern "C" {
+
+const char *wl_strerror(int code)
+{
+    switch (code) {
+    case WL_OK: return "ok";
+    case WL_NOT_CONVERGED: return "not converged (maxiter reached)";
+    case WL_BREAKDOWN: return "Krylov breakdown";
+    case WL_STAGNATED: return "mixed-precision refinement stagnated";
+    case WL_EINVAL: return "invalid argument";
+    case WL_EALIGN: return "pointer not 16-byte aligned";
+    case WL_EPREC: return "unsupported precision";
+    case WL_EHIP: return "HIP runtime error";
+    case WL_ENAN: return "NaN/Inf in residual";
+    case WL_EWORKSPACE: return "workspace too small";
+    default: return "unknown error";
+    }
+}
+
+int wl_last_hip_error(void) { return g_last_hip; }
+
+int wl_field_bytes(const wl_geom *g, int kind, int prec, int nrhs, size_t *out_bytes)
+{
+    if (!geom_ok(g) || !out_bytes || (kind != WL_SPINOR && kind != WL_GAUGE))
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    const uint32_t V = vol(g);
+    if (kind == WL_SPINOR) {
+        if (nrhs < 1)
+            return WL_EINVAL;
+        *out_bytes = (size_t)nrhs * V * spinor_site_bytes(prec);
+    } else {
+        *out_bytes = (size_t)4 * V * link_site_bytes(prec);
+    }
+    return WL_OK;
+}
+
+int wl_pack_gauge(const wl_geom *g, int prec, const void *U_canon, void *U_packed, void *stream)
+{
+    if (!geom_ok(g) || !U_canon || !U_packed)
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    if (!al16(U_canon) || !al16(U_packed))
+        return WL_EALIGN;
+    CHECK_HIP(launch_pack_gauge(prec, vol(g), U_canon, U_packed, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wl_pack_spinor(const wl_geom *g, int prec, int nrhs, const void *psi_canon, void *psi_packed, void *stream)
+{
+    if (!geom_ok(g) || !psi_canon || !psi_packed || nrhs < 1 || nrhs > 65535)
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    if (!al16(psi_canon) || !al16(psi_packed))
+        return WL_EALIGN;
+    CHECK_HIP(launch_pack_spinor(prec, vol(g), nrhs, psi_canon, psi_packed, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wl_unpack_spinor(const wl_geom *g, int prec, int nrhs, const void *psi_packed, void *psi_canon, void *stream)
+{
+    if (!geom_ok(g) || !psi_canon || !psi_packed || nrhs < 1 || nrhs > 65535)
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    if (!al16(psi_canon) || !al16(psi_packed))
+        return WL_EALIGN;
+    CHECK_HIP(launch_unpack_spinor(prec, vol(g), nrhs, psi_packed, psi_canon, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wl_convert_spinor(const wl_geom *g, int prec_in, int prec_out, int nrhs, const void *in, void *out, void *stream)
+{
+    if (!geom_ok(g) || !in || !out || nrhs < 1 || nrhs > 65535)
+        return WL_EINVAL;
+    if (!prec_ok(prec_in) || !prec_ok(prec_out))
+        return WL_EPREC;
+    if (!al16(in) || !al16(out))
+        return WL_EALIGN;
+    CHECK_HIP(launch_convert(prec_in, prec_out, vol(g), nrhs, in, out, nullptr, 0, 0, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wl_op_create(const wl_geom *g, double kappa, int prec, const void *U_packed, wl_op **out)
+{
+    if (!geom_ok(g) || !U_packed || !out || !std::isfinite(kappa))
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    if (!al16(U_packed))
+        return WL_EALIGN;
+    wl_op *op = new wl_op();
+    op->g = *g;
+    op->kappa = kappa;
+    op->prec = prec;
+    op->U = U_packed;
+    op->V = vol(g);
+    *out = op;
+    return WL_OK;
+}
+
+int wl_op_destroy(wl_op *op)
+{
+    delete op;
+    return WL_OK;
+}
+
+static int stencil_call(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream, int apply)
+{
+    if (!op || !out || !in || nrhs < 1 || nrhs > 65535 || (dagger != 0 && dagger != 1) || out == in)
+        return WL_EINVAL;
+    if (!al16(out) || !al16(in))
+        return WL_EALIGN;
+    LaunchCfg cfg = launch_for(op, nrhs);
+    if (nrhs % cfg.rpt != 0)
+        cfg.rpt = 1;
+    StencilParams p = base_params(op, out, in, nrhs, apply);
+    CHECK_HIP(prof_stencil(op->prec, op, dagger, cfg, p, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wilson_dslash(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream)
+{
+    return stencil_call(op, out, in, dagger, nrhs, stream, 0);
+}
+
+int wilson_apply(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream)
+{
+    return stencil_call(op, out, in, dagger, nrhs, stream, 1);
+}
+
+int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs, size_t *out_bytes)
+{
+    if (!hi || !out_bytes || nrhs < 1 || nrhs > 64 || (solver != WL_SOLVER_CGNR && solver != WL_SOLVER_BICGSTAB))
+        return WL_EINVAL;
+    *out_bytes = solver_workspace_bytes(hi, lo, solver, nrhs);
+    return WL_OK;
+}
+
+static int solve_entry(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
+                       const wl_solve_params *p, wl_solve_stats *stats, void *stream)
+{
+    if (!hi || !x || !b || !p || nrhs < 1 || nrhs > 64 || x == b || !(p->tol > 0) || p->maxiter < 1)
+        return WL_EINVAL;
+    if (!al16(x) || !al16(b))
+        return WL_EALIGN;
+    if (lo) {
+        if (hi->prec != WL_F64 || lo->prec == WL_F64)
+            return WL_EPREC;
+        for (int i = 0; i < 4; ++i)
+            if (lo->g.dims[i] != hi->g.dims[i] || lo->g.bc[i] != hi->g.bc[i])
+                return WL_EINVAL;
+        if (lo->kappa != hi->kappa)
+            return WL_EINVAL;
+    } else if (hi->prec != WL_F64 && hi->prec != WL_F32) {
+        return WL_EPREC;  // plain solves run in FP64 or FP32 storage
+    }
+    return solve(solver, hi, lo, x, b, nrhs, p, stats, (hipStream_t)stream);
+}
+
+int solve_cgnr(const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *p,
+               wl_solve_stats *stats, void *stream)
+{
+    return solve_entry(WL_SOLVER_CGNR, hi, lo, x, b, nrhs, p, stats, stream);
+}
+
+int solve_bicgstab(const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *p,
+                   wl_solve_stats *stats, void *stream)
+{
+    return solve_entry(WL_SOLVER_BICGSTAB, hi, lo, x, b, nrhs, p, stats, stream);
+}
+
+int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const void *mu, int project, void *stream)
+{
+    if (!op || !out_canon || !x || !mu || (project != 0 && project != 1))
+        return WL_EINVAL;
+    if (op->prec != WL_F64 && op->prec != WL_F32)
+        return WL_EPREC;
+    if (!al16(out_canon) || !al16(x) || !al16(mu))
+        return WL_EALIGN;
+    CHECK_HIP(launch_force(op->prec, op, out_canon, x, mu, project, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void *stream)
+{
+    if (!d || n < 1 || n > 1024 || (dagger != 0 && dagger != 1) || nrhs < 1 || nrhs > 65535)
+        return WL_EINVAL;
+    const int prec = d[0].op ? d[0].op->prec : -1;
+    for (int i = 0; i < n; ++i) {
+        if (!d[i].op || !d[i].out || !d[i].in || d[i].out == d[i].in)
+            return WL_EINVAL;
+        if (d[i].op->prec != prec)
+            return WL_EPREC;
+        if (!al16(d[i].out) || !al16(d[i].in))
+            return WL_EALIGN;
+    }
+    const int block = 256;
+    const int rpt = (prec != WL_F64 && nrhs % 4 == 0) ? 4 : (nrhs % 2 == 0) ? 2 : 1;  // multi kernel offers 1, 2, 4
+    std::vector<MultiEntry> E(n);
+    uint32_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        E[i].p = base_params(d[i].op, d[i].out, d[i].in, nrhs, 1);
+        E[i].p.nblk = (int)((d[i].op->V + block - 1) / block);
+        E[i].tile_begin = total;
+        const uint64_t t = (uint64_t)E[i].p.nblk * (uint64_t)(nrhs / rpt);
+        if ((uint64_t)total + t > 0xffffffffull)
+            return WL_EINVAL;
+        total += (uint32_t)t;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // descriptor table and queue counter live in one small device buffer
+    // owned by this call; it is released after the launch completes
+    const size_t bytes = sizeof(MultiEntry) * n + 256;
+    void *buf = nullptr;
+    CHECK_HIP(hipMallocAsync(&buf, bytes, st));
+    MultiEntry *dE = (MultiEntry *)buf;
+    unsigned *counter = (unsigned *)((char *)buf + (sizeof(MultiEntry) * n + 127) / 128 * 128);
+    hipError_t e = hipMemcpyAsync(dE, E.data(), sizeof(MultiEntry) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_fill_u32(counter, 0u, 1, st);
+    if (e == hipSuccess) {
+        int grid = multi_grid_size(prec, dagger, rpt, block);
+        if ((uint32_t)grid > total)
+            grid = (int)total;
+        e = launch_multi(prec, dagger, rpt, block, dE, n, total, counter, grid, st);
+    }
+    hipError_t e2 = hipFreeAsync(buf, st);
+    if (e == hipSuccess)
+        e = e2;
+    // the host copy of E must outlive the async H2D copy
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    CHECK_HIP(e);
+    return WL_OK;
+}
+
+int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rpt, int *xcd)
+{
+    if (!op || nrhs < 1 || !block || !rpt || !xcd)
+        return WL_EINVAL;
+    LaunchCfg c = launch_for(op, nrhs);
+    *block = c.block;
+    *rpt = c.rpt;
+    *xcd = c.xcd;
+    return WL_OK;
+}
+
+int wl_set_launch(wl_op *op, int nrhs, int block, int rpt, int xcd)
+{
+    if (!op || nrhs < 1 || block < 64 || block > 512 || block % 64 || rpt < 1 || rpt > max_rpt(op->prec) ||
+        nrhs % rpt || (xcd != 0 && xcd != 1))
+        return WL_EINVAL;
+    std::lock_guard<std::mutex> lk(op->mu);
+    op->launch[nrhs] = LaunchCfg{block, rpt, xcd};
+    return WL_OK;
+}
+
+int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
+{
+    if (!op || nrhs < 1 || nrhs > 64 || (dagger != 0 && dagger != 1))
+        return WL_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t vb = (size_t)nrhs * op->V * spinor_site_bytes(op->prec);
+    void *in = nullptr, *out = nullptr;
+    CHECK_HIP(hipMalloc(&in, vb));
+    if (hipMalloc(&out, vb) != hipSuccess) {
+        (void)hipFree(in);
+        return WL_EHIP;
+    }
+    hipError_t e = hipMemsetAsync(in, 0, vb, st);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess)
+        e = hipEventCreate(&a);
+    if (e == hipSuccess)
+        e = hipEventCreate(&b);
+    LaunchCfg best = default_launch(op->prec, nrhs);
+    float best_ms = INFINITY;
+    const int blocks[] = {64, 128, 256, 512};
+    for (int bi = 0; bi < 4 && e == hipSuccess; ++bi)
+        for (int rpt = 1; rpt <= max_rpt(op->prec) && e == hipSuccess; ++rpt) {
+            if (nrhs % rpt)
+                continue;
+            for (int xcd = 0; xcd <= 1 && e == hipSuccess; ++xcd) {
+                LaunchCfg c{blocks[bi], rpt, xcd};
+                StencilParams p = base_params(op, out, in, nrhs, 1);
+                for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                    e = launch_stencil(op->prec, dagger, c, p, st);
+                const int reps = 10;
+                if (e == hipSuccess)
+                    e = hipEventRecord(a, st);
+                for (int k = 0; k < reps && e == hipSuccess; ++k)
+                    e = launch_stencil(op->prec, dagger, c, p, st);
+                if (e == hipSuccess)
+                    e = hipEventRecord(b, st);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(b);
+                float ms = 0.f;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, a, b);
+                if (e == hipSuccess && ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        }
+    if (a)
+        (void)hipEventDestroy(a);
+    if (b)
+        (void)hipEventDestroy(b);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    CHECK_HIP(e);
+    {
+        wl_op *o = const_cast<wl_op *>(op);
+        std::lock_guard<std::mutex> lk(o->mu);
+        o->launch[nrhs] = best;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    g_tune[tune_key(op, nrhs, 0)] = best;
+    save_tune_cache_locked();
+    return WL_OK;
+}
+
+int wl_prof_enable(int on)
+{
+    g_prof_on.store(on ? 1 : 0);
+    return WL_OK;
+}
+
+int wl_prof_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drain_prof_locked();
+    for (int i = 0; i < 4; ++i) {
+        g_prof_ms[i] = 0;
+        g_prof_sites[i] = 0;
+        g_prof_n[i] = 0;
+    }
+    return WL_OK;
+}
+
+int wl_prof_read(int prec, long *launches, double *total_ms, double *site_rhs)
+{
+    if (!prec_ok(prec) || !launches || !total_ms || !site_rhs)
+        return WL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drain_prof_locked();
+    *launches = g_prof_n[prec];
+    *total_ms = g_prof_ms[prec];
+    *site_rhs = g_prof_sites[prec];
+    return WL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,443 @@
+// wl_blas.hip -- fused BLAS-1 updates, deterministic reductions and the
+// on-device scalar steps of CGNR and BiCGStab.
+//
+// The paper composes its solvers from a BLAS-like library (Sec. V-C) and
+// finds that these streaming updates and their global reductions, not the
+// stencil, limit the solver.  Here each solver step that touches vectors is
+// one fused kernel (several axpy-type updates plus the norms/dots the next
+// step needs), each reduction is a fixed-order two-stage sum (wavefront
+// shuffles and LDS into per-workgroup partials, then one workgroup sums the
+// partials in index order), and the scalar recurrences (alpha, beta, omega,
+// rho, convergence) run on the device so the host only polls occasionally.
+//
+// Inner product <a, b> = sum conj(a_i) b_i; norms and dots accumulate in FP64.
+#include "wl_internal.h"
+
+namespace wl {
+
+template <typename T>
+__device__ __forceinline__ double n2(const cx<T> (&v)[12])
+{
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        a = fma((double)v[k].re, (double)v[k].re, fma((double)v[k].im, (double)v[k].im, a));
+    return a;
+}
+template <typename T>
+__device__ __forceinline__ void dot(const cx<T> (&a)[12], const cx<T> (&b)[12], double &re, double &im)
+{
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        re = fma((double)a[k].re, (double)b[k].re, fma((double)a[k].im, (double)b[k].im, re));
+        im = fma((double)a[k].re, (double)b[k].im, fma(-(double)a[k].im, (double)b[k].re, im));
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void round_if_scaled(cx<typename Traits<P>::real> (&v)[12])
+{
+    if constexpr (Traits<P>::SCALED) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            cx<float> q = unpack2<P>(pack2<P>(v[k].re * inv, v[k].im * inv));
+            v[k] = cx<float>{q.re * m, q.im * m};
+        }
+    }
+}
+
+template <int P, int OP>
+__global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
+{
+    using T = typename Traits<P>::real;
+    __shared__ double lds[3 * 4];
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const uint32_t V = p.V;
+    const int nr = p.nrhs;
+    double red[3] = {0.0, 0.0, 0.0};
+    if (s < V) {
+        const Scalars &sc = p.sc[r];
+        if constexpr (OP == B_RES) {  // r = b - w
+            cx<T> b[12], w[12], o[12];
+            load_site<P>(p.a0, V, nr, s, r, b);
+            load_site<P>(p.a1, V, nr, s, r, w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                o[k] = cx<T>{b[k].re - w[k].re, b[k].im - w[k].im};
+            round_if_scaled<P>(o);
+            store_site<P>(p.y0, V, nr, s, r, o);
+            red[0] = n2(o);
+        } else if constexpr (OP == B_CG_XR) {  // x += a p ; r -= a w
+            const T a = (T)sc.alpha.x;
+            cx<T> x[12], rr[12], pp[12], w[12];
+            load_site<P>(p.y0, V, nr, s, r, x);
+            load_site<P>(p.y1, V, nr, s, r, rr);
+            load_site<P>(p.a0, V, nr, s, r, pp);
+            load_site<P>(p.a1, V, nr, s, r, w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                x[k] = rfma(a, pp[k], x[k]);
+                rr[k] = rfma(-a, w[k], rr[k]);
+            }
+            round_if_scaled<P>(rr);
+            store_site<P>(p.y0, V, nr, s, r, x);
+            store_site<P>(p.y1, V, nr, s, r, rr);
+            red[0] = n2(rr);
+        } else if constexpr (OP == B_CG_P) {  // p = z + beta p
+            const T b = (T)sc.beta.x;
+            cx<T> pp[12], z[12];
+            load_site<P>(p.y0, V, nr, s, r, pp);
+            load_site<P>(p.a0, V, nr, s, r, z);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                pp[k] = rfma(b, pp[k], z[k]);
+            store_site<P>(p.y0, V, nr, s, r, pp);
+        } else if constexpr (OP == B_BI_P) {  // p = r + beta (p - omega v)
+            const cx<T> b{(T)sc.beta.x, (T)sc.beta.y}, om{(T)sc.omega.x, (T)sc.omega.y};
+            cx<T> pp[12], rr[12], v[12];
+            load_site<P>(p.y0, V, nr, s, r, pp);
+            load_site<P>(p.a0, V, nr, s, r, rr);
+            load_site<P>(p.a1, V, nr, s, r, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                cx<T> d = cfma(cx<T>{-om.re, -om.im}, v[k], pp[k]);
+                pp[k] = cfma(b, d, rr[k]);
+            }
+            store_site<P>(p.y0, V, nr, s, r, pp);
+        } else if constexpr (OP == B_BI_S) {  // s = r - alpha v
+            const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y};
+            cx<T> rr[12], v[12];
+            load_site<P>(p.a0, V, nr, s, r, rr);
+            load_site<P>(p.a1, V, nr, s, r, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                rr[k] = cfma(cx<T>{-a.re, -a.im}, v[k], rr[k]);
+            round_if_scaled<P>(rr);
+            store_site<P>(p.y0, V, nr, s, r, rr);
+            red[0] = n2(rr);
+        } else if constexpr (OP == B_BI_XR) {  // x += alpha p + omega s ; r = s - omega t
+            const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
+            cx<T> x[12], pp[12], ss[12], t[12];
+            load_site<P>(p.y0, V, nr, s, r, x);
+            load_site<P>(p.a0, V, nr, s, r, pp);
+            load_site<P>(p.a1, V, nr, s, r, ss);
+            load_site<P>(p.a2, V, nr, s, r, t);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                x[k] = cfma(a, pp[k], x[k]);
+                x[k] = cfma(om, ss[k], x[k]);
+                ss[k] = cfma(cx<T>{-om.re, -om.im}, t[k], ss[k]);
+            }
+            round_if_scaled<P>(ss);
+            store_site<P>(p.y0, V, nr, s, r, x);
+            store_site<P>(p.y1, V, nr, s, r, ss);
+            red[0] = n2(ss);
+            cx<T> rh[12];
+            load_site<P>(p.a3, V, nr, s, r, rh);
+            dot(rh, ss, red[1], red[2]);
+        } else if constexpr (OP == B_COPY) {
+            cx<T> v[12];
+            load_site<P>(p.a0, V, nr, s, r, v);
+            store_site<P>(p.y0, V, nr, s, r, v);
+        } else if constexpr (OP == B_ZERO) {
+            cx<T> v[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                v[k] = cx<T>{T(0), T(0)};
+            store_site<P>(p.y0, V, nr, s, r, v);
+        } else if constexpr (OP == B_NORM) {
+            cx<T> v[12];
+            load_site<P>(p.a0, V, nr, s, r, v);
+            red[0] = n2(v);
+        }
+    }
+    constexpr int NV = (OP == B_RES || OP == B_CG_XR || OP == B_BI_S || OP == B_NORM) ? 1 : OP == B_BI_XR ? 3 : 0;
+    if constexpr (NV > 0) {
+        block_sum<3>(red, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                p.partials[((size_t)k * nr + r) * p.nblk + blockIdx.x] = red[k];
+        }
+    }
+}
+
+int blas_nval(int op)
+{
+    switch (op) {
+    case B_RES: case B_CG_XR: case B_BI_S: case B_NORM: return 1;
+    case B_BI_XR: return 3;
+    default: return 0;
+    }
+}
+
+template <int P>
+static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hipStream_t st)
+{
+    switch (op) {
+    case B_RES: hipLaunchKernelGGL((blas_kernel<P, B_RES>), g, b, 0, st, p); break;
+    case B_CG_XR: hipLaunchKernelGGL((blas_kernel<P, B_CG_XR>), g, b, 0, st, p); break;
+    case B_CG_P: hipLaunchKernelGGL((blas_kernel<P, B_CG_P>), g, b, 0, st, p); break;
+    case B_BI_P: hipLaunchKernelGGL((blas_kernel<P, B_BI_P>), g, b, 0, st, p); break;
+    case B_BI_S: hipLaunchKernelGGL((blas_kernel<P, B_BI_S>), g, b, 0, st, p); break;
+    case B_BI_XR: hipLaunchKernelGGL((blas_kernel<P, B_BI_XR>), g, b, 0, st, p); break;
+    case B_COPY: hipLaunchKernelGGL((blas_kernel<P, B_COPY>), g, b, 0, st, p); break;
+    case B_ZERO: hipLaunchKernelGGL((blas_kernel<P, B_ZERO>), g, b, 0, st, p); break;
+    case B_NORM: hipLaunchKernelGGL((blas_kernel<P, B_NORM>), g, b, 0, st, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_blas(int prec, int op, const BlasParams &p0, int block, hipStream_t st)
+{
+    BlasParams p = p0;
+    p.nblk = (int)((p.V + block - 1) / block);
+    dim3 g(p.nblk, p.nrhs), b(block);
+    switch (prec) {
+    case F64: return launch_blas_p<F64>(op, p, g, b, st);
+    case F32: return launch_blas_p<F32>(op, p, g, b, st);
+    case BF16S: return launch_blas_p<BF16S>(op, p, g, b, st);
+    case F16S: return launch_blas_p<F16S>(op, p, g, b, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// x64 += f[rhs] * e
+template <int PI>
+__global__ __launch_bounds__(256) void accum_kernel(uint32_t V, int nrhs, void *x64, const void *e, const double *f,
+                                                    int fstride)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= V)
+        return;
+    const double a = f[(size_t)r * fstride];
+    cx<typename Traits<PI>::real> ev[12];
+    cx<double> x[12];
+    load_site<PI>(e, V, nrhs, s, r, ev);
+    load_site<F64>(x64, V, nrhs, s, r, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        x[k] = cx<double>{fma(a, (double)ev[k].re, x[k].re), fma(a, (double)ev[k].im, x[k].im)};
+    store_site<F64>(x64, V, nrhs, s, r, x);
+}
+
+hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e, const double *s, int sstride,
+                        hipStream_t st)
+{
+    const int B = 256;
+    dim3 g((V + B - 1) / B, nrhs);
+    switch (pin) {
+    case F64: hipLaunchKernelGGL(accum_kernel<F64>, g, dim3(B), 0, st, V, nrhs, x64, e, s, sstride); break;
+    case F32: hipLaunchKernelGGL(accum_kernel<F32>, g, dim3(B), 0, st, V, nrhs, x64, e, s, sstride); break;
+    case BF16S: hipLaunchKernelGGL(accum_kernel<BF16S>, g, dim3(B), 0, st, V, nrhs, x64, e, s, sstride); break;
+    case F16S: hipLaunchKernelGGL(accum_kernel<F16S>, g, dim3(B), 0, st, V, nrhs, x64, e, s, sstride); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- finalize
+constexpr int FIN_THREADS = 256;
+constexpr int FIN_MAX = 3 * 64;  // values x right-hand sides per partial set
+
+// Sum partials[(v * nrhs + r) * nblk + b] over b in a fixed order.
+__device__ double fixed_sum(const double *part, int nblk, double *lds)
+{
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += FIN_THREADS)
+        a += part[b];
+    double v[1] = {a};
+    block_sum<1>(v, lds);
+    __shared__ double out;
+    if (threadIdx.x == 0)
+        out = v[0];
+    __syncthreads();
+    const double res = out;
+    __syncthreads();
+    return res;
+}
+
+__device__ __forceinline__ bool finite2(double a) { return isfinite(a); }
+
+__global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int op)
+{
+    __shared__ double lds[FIN_THREADS / 64];
+    __shared__ double sA[FIN_MAX], sB[FIN_MAX], sC[FIN_MAX];
+    const int nr = p.nrhs;
+    for (int i = 0; i < p.nvalA * nr; ++i) {
+        const double v = fixed_sum(p.A + (size_t)i * p.nblkA, p.nblkA, lds);
+        if (threadIdx.x == 0)
+            sA[i] = v;
+    }
+    for (int i = 0; i < p.nvalB * nr; ++i) {
+        const double v = fixed_sum(p.B + (size_t)i * p.nblkB, p.nblkB, lds);
+        if (threadIdx.x == 0)
+            sB[i] = v;
+    }
+    for (int i = 0; i < p.nvalC * nr; ++i) {
+        const double v = fixed_sum(p.C + (size_t)i * p.nblkC, p.nblkC, lds);
+        if (threadIdx.x == 0)
+            sC[i] = v;
+    }
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r >= nr)
+        return;
+    if (op == F_SUM) {
+        for (int v = 0; v < p.nvalA; ++v)
+            p.out[v * nr + r] = sA[v * nr + r];
+        return;
+    }
+    Scalars sc = p.sc[r];
+    const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+    switch (op) {
+    case F_INIT_CG: {
+        sc.rr = sA[r];
+        sc.zz = sB[r];
+        sc.bb = sC[r];
+        sc.tol2 = p.tol2;
+        sc.alpha = sc.beta = zero;
+        sc.flag = 0;
+        sc.conv_iter = 0;
+        if (!finite2(sc.rr) || !finite2(sc.zz) || !finite2(sc.bb))
+            sc.flag = 3;
+        else if (sc.rr <= sc.tol2 * sc.bb)
+            sc.flag = 1;
+        break;
+    }
+    case F_CG_ALPHA: {
+        const double ww = sA[r];
+        if (sc.flag == 0) {
+            if (!finite2(ww))
+                sc.flag = 3;
+            else if (ww > 0.0) {
+                sc.alpha = make_double2(sc.zz / ww, 0.0);
+                break;
+            } else
+                sc.flag = 2;
+        }
+        sc.alpha = zero;
+        break;
+    }
+    case F_CG_BETA: {
+        const double rr = sA[r], zz = sB[r];
+        if (sc.flag == 0) {
+            sc.rr = rr;
+            if (!finite2(rr) || !finite2(zz))
+                sc.flag = 3;
+            else if (rr <= sc.tol2 * sc.bb) {
+                sc.flag = 1;
+                sc.conv_iter = p.iter + 1;
+            } else if (sc.zz > 0.0) {
+                sc.beta = make_double2(zz / sc.zz, 0.0);
+                sc.zz = zz;
+                break;
+            } else
+                sc.flag = 2;
+        }
+        sc.beta = zero;
+        break;
+    }
+    case F_INIT_BI: {
+        sc.rr = sA[r];
+        sc.bb = sC[r];
+        sc.tol2 = p.tol2;
+        sc.rho = make_double2(sc.rr, 0.0);  // <rh, r0> with rh = r0
+        sc.alpha = sc.omega = one;
+        sc.beta = zero;  // p = v = 0 -> first p = r
+        sc.flag = 0;
+        sc.conv_iter = 0;
+        if (!finite2(sc.rr) || !finite2(sc.bb))
+            sc.flag = 3;
+        else if (sc.rr <= sc.tol2 * sc.bb)
+            sc.flag = 1;
+        break;
+    }
+    case F_BI_ALPHA: {
+        const double2 rv = make_double2(sA[r], sA[nr + r]);
+        if (sc.flag == 0) {
+            const double d = rv.x * rv.x + rv.y * rv.y;
+            if (!finite2(d))
+                sc.flag = 3;
+            else if (d > 0.0) {  // alpha = rho / <rh, v>
+                sc.alpha = make_double2((sc.rho.x * rv.x + sc.rho.y * rv.y) / d, (sc.rho.y * rv.x - sc.rho.x * rv.y) / d);
+                break;
+            } else
+                sc.flag = 2;
+        }
+        sc.alpha = zero;
+        break;
+    }
+    case F_BI_OMEGA: {
+        const double ss = sA[r];
+        const double st_re = sB[r], st_im = sB[nr + r], tt = sB[2 * nr + r];
+        sc.ss = ss;
+        if (sc.flag == 0) {
+            if (!finite2(ss) || !finite2(tt) || !finite2(st_re) || !finite2(st_im))
+                sc.flag = 3;
+            else if (ss <= sc.tol2 * sc.bb) {  // x += alpha p ; r = s  (omega = 0)
+                sc.flag = 1;
+                sc.conv_iter = p.iter + 1;
+            } else if (tt > 0.0) {  // omega = <t, s> / <t, t> = conj(<s, t>) / |t|^2
+                sc.omega = make_double2(st_re / tt, -st_im / tt);
+                break;
+            } else
+                sc.flag = 2;
+        } else
+            sc.alpha = zero;
+        sc.omega = zero;
+        break;
+    }
+    case F_BI_RHO: {
+        const double rr = sA[r];
+        const double2 rho_new = make_double2(sA[nr + r], sA[2 * nr + r]);
+        if (sc.flag == 0) {
+            sc.rr = rr;
+            const double om2 = sc.omega.x * sc.omega.x + sc.omega.y * sc.omega.y;
+            const double rho2 = sc.rho.x * sc.rho.x + sc.rho.y * sc.rho.y;
+            if (!finite2(rr) || !finite2(rho_new.x) || !finite2(rho_new.y))
+                sc.flag = 3;
+            else if (rr <= sc.tol2 * sc.bb) {
+                sc.flag = 1;
+                sc.conv_iter = p.iter + 1;
+            } else if (om2 > 0.0 && rho2 > 0.0 && (rho_new.x != 0.0 || rho_new.y != 0.0)) {
+                // beta = (rho_new / rho) (alpha / omega)
+                const double2 q1 = make_double2((rho_new.x * sc.rho.x + rho_new.y * sc.rho.y) / rho2,
+                                                (rho_new.y * sc.rho.x - rho_new.x * sc.rho.y) / rho2);
+                const double2 q2 = make_double2((sc.alpha.x * sc.omega.x + sc.alpha.y * sc.omega.y) / om2,
+                                                (sc.alpha.y * sc.omega.x - sc.alpha.x * sc.omega.y) / om2);
+                sc.beta = make_double2(q1.x * q2.x - q1.y * q2.y, q1.x * q2.y + q1.y * q2.x);
+                sc.rho = rho_new;
+                break;
+            } else
+                sc.flag = 2;
+        } else if (sc.flag == 1 && sc.conv_iter == p.iter + 1) {
+            sc.rr = rr;  // converged on |s| this iteration: r = s
+        }
+        sc.beta = zero;
+        sc.alpha = zero;
+        sc.omega = zero;
+        break;
+    }
+    default: break;
+    }
+    p.sc[r] = sc;
+}
+
+hipError_t launch_finalize(int op, const FinParams &p, hipStream_t st)
+{
+    if (p.nrhs > 64 || p.nvalA * p.nrhs > FIN_MAX || p.nvalB * p.nrhs > FIN_MAX || p.nvalC * p.nrhs > FIN_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, st, p, op);
+    return hipGetLastError();
+}
+
+}  // namespace wl

@@ -1,0 +1,321 @@
+// wl_common.h -- device-side building blocks shared by the gfx950 kernels:
+// storage traits of the packed layouts, site/link loads and stores with
+// precision conversion, complex arithmetic, fast integer division, the
+// XCD-aware tile order and deterministic wavefront/block reductions.
+//
+// Packed layouts (see include/wilson.h):
+//   spinor  [nrhs][chunk][V] of 16-byte chunks; component k = 3*spin + colour
+//           lives in chunk k / CPC at slot k % CPC (CPC = complex per chunk).
+//           16-bit formats append [nrhs][V] FP32 per-site scales.
+//   gauge   [mu][unit][V]; the two stored rows (6 complex) are split into
+//           LINK_UNITS units of LINK_CPU complex each.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wl {
+
+enum Prec { F64 = 0, F32 = 1, BF16S = 2, F16S = 3 };
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+
+// a*b + c
+template <typename T>
+__device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c)
+{
+    c.re = fma(a.re, b.re, c.re);
+    c.re = fma(-a.im, b.im, c.re);
+    c.im = fma(a.re, b.im, c.im);
+    c.im = fma(a.im, b.re, c.im);
+    return c;
+}
+// conj(a)*b + c
+template <typename T>
+__device__ __forceinline__ cx<T> cjfma(cx<T> a, cx<T> b, cx<T> c)
+{
+    c.re = fma(a.re, b.re, c.re);
+    c.re = fma(a.im, b.im, c.re);
+    c.im = fma(a.re, b.im, c.im);
+    c.im = fma(-a.im, b.re, c.im);
+    return c;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) { return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return cx<T>{a.re, -a.im}; }
+// s*a + c (real s)
+template <typename T>
+__device__ __forceinline__ cx<T> rfma(T s, cx<T> a, cx<T> c) { return cx<T>{fma(s, a.re, c.re), fma(s, a.im, c.im)}; }
+// s*(i a) + c (real s)
+template <typename T>
+__device__ __forceinline__ cx<T> ifma(T s, cx<T> a, cx<T> c) { return cx<T>{fma(-s, a.im, c.re), fma(s, a.re, c.im)}; }
+
+// ---------------------------------------------------------------- 16-bit reals
+__device__ __forceinline__ uint32_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return 0x7fc0u;  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ uint32_t f32_to_f16(float f)
+{
+    _Float16 h = (_Float16)f;  // round to nearest even
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_to_f32(uint32_t h) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(h & 0xffffu)); }
+
+template <int P>
+__device__ __forceinline__ uint32_t pack2(float re, float im)
+{
+    if constexpr (P == BF16S)
+        return f32_to_bf16(re) | (f32_to_bf16(im) << 16);
+    else
+        return f32_to_f16(re) | (f32_to_f16(im) << 16);
+}
+template <int P>
+__device__ __forceinline__ cx<float> unpack2(uint32_t w)
+{
+    if constexpr (P == BF16S)
+        return cx<float>{bf16_to_f32(w & 0xffffu), bf16_to_f32(w >> 16)};
+    else
+        return cx<float>{f16_to_f32(w & 0xffffu), f16_to_f32(w >> 16)};
+}
+
+// ---------------------------------------------------------------- traits
+template <int P>
+struct Traits;
+template <>
+struct Traits<F64> {
+    using real = double;
+    static constexpr int CPC = 1, NCH = 12, SCALED = 0;
+    static constexpr int LINK_UNITS = 6, LINK_CPU = 1, LINK_UNIT_BYTES = 16;
+};
+template <>
+struct Traits<F32> {
+    using real = float;
+    static constexpr int CPC = 2, NCH = 6, SCALED = 0;
+    static constexpr int LINK_UNITS = 3, LINK_CPU = 2, LINK_UNIT_BYTES = 16;
+};
+template <>
+struct Traits<BF16S> {
+    using real = float;
+    static constexpr int CPC = 4, NCH = 3, SCALED = 1;
+    static constexpr int LINK_UNITS = 3, LINK_CPU = 2, LINK_UNIT_BYTES = 8;
+};
+template <>
+struct Traits<F16S> {
+    using real = float;
+    static constexpr int CPC = 4, NCH = 3, SCALED = 1;
+    static constexpr int LINK_UNITS = 3, LINK_CPU = 2, LINK_UNIT_BYTES = 8;
+};
+
+// Bytes per site per right-hand side of a packed spinor / per direction of a link.
+__host__ __device__ constexpr int spinor_site_bytes(int p) { return p == F64 ? 192 : p == F32 ? 96 : 52; }
+__host__ __device__ constexpr int link_site_bytes(int p) { return p == F64 ? 96 : p == F32 ? 48 : 24; }
+
+// ---------------------------------------------------------------- spinor access
+// A packed spinor field: base pointer, volume, number of right-hand sides.
+struct Field {
+    void *p;
+    uint32_t V;
+    int nrhs;
+};
+struct CField {
+    const void *p;
+    uint32_t V;
+    int nrhs;
+};
+
+template <int P>
+__device__ __forceinline__ const float *scale_ptr(const void *base, uint32_t V, int nrhs)
+{
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + (size_t)nrhs * V * 48);
+}
+
+template <int P>
+__device__ __forceinline__ void load_site(const void *base, uint32_t V, int nrhs, uint32_t s, int rhs,
+                                          cx<typename Traits<P>::real> (&v)[12])
+{
+    const size_t off = (size_t)rhs * Traits<P>::NCH * V + s;
+    if constexpr (P == F64) {
+        const double2 *b = reinterpret_cast<const double2 *>(base) + off;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            double2 d = b[(size_t)k * V];
+            v[k] = cx<double>{d.x, d.y};
+        }
+    } else if constexpr (P == F32) {
+        const float4 *b = reinterpret_cast<const float4 *>(base) + off;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            float4 d = b[(size_t)k * V];
+            v[2 * k] = cx<float>{d.x, d.y};
+            v[2 * k + 1] = cx<float>{d.z, d.w};
+        }
+    } else {
+        const uint4 *b = reinterpret_cast<const uint4 *>(base) + off;
+        const float sc = scale_ptr<P>(base, V, nrhs)[(size_t)rhs * V + s];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 d = b[(size_t)k * V];
+            cx<float> a0 = unpack2<P>(d.x), a1 = unpack2<P>(d.y), a2 = unpack2<P>(d.z), a3 = unpack2<P>(d.w);
+            v[4 * k + 0] = cx<float>{a0.re * sc, a0.im * sc};
+            v[4 * k + 1] = cx<float>{a1.re * sc, a1.im * sc};
+            v[4 * k + 2] = cx<float>{a2.re * sc, a2.im * sc};
+            v[4 * k + 3] = cx<float>{a3.re * sc, a3.im * sc};
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void store_site(void *base, uint32_t V, int nrhs, uint32_t s, int rhs,
+                                           const cx<typename Traits<P>::real> (&v)[12])
+{
+    const size_t off = (size_t)rhs * Traits<P>::NCH * V + s;
+    if constexpr (P == F64) {
+        double2 *b = reinterpret_cast<double2 *>(base) + off;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            b[(size_t)k * V] = make_double2(v[k].re, v[k].im);
+    } else if constexpr (P == F32) {
+        float4 *b = reinterpret_cast<float4 *>(base) + off;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            b[(size_t)k * V] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    } else {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        uint4 *b = reinterpret_cast<uint4 *>(base) + off;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 d;
+            d.x = pack2<P>(v[4 * k + 0].re * inv, v[4 * k + 0].im * inv);
+            d.y = pack2<P>(v[4 * k + 1].re * inv, v[4 * k + 1].im * inv);
+            d.z = pack2<P>(v[4 * k + 2].re * inv, v[4 * k + 2].im * inv);
+            d.w = pack2<P>(v[4 * k + 3].re * inv, v[4 * k + 3].im * inv);
+            b[(size_t)k * V] = d;
+        }
+        float *scp = const_cast<float *>(scale_ptr<P>(base, V, nrhs));
+        scp[(size_t)rhs * V + s] = m;
+    }
+}
+
+// Load the two stored rows of U_mu(s) and rebuild row 2 = conj(row0 x row1)
+// (valid for SU(3): unitary with det 1).  u[3*row + col].
+template <int P>
+__device__ __forceinline__ void load_link(const void *U, uint32_t V, int mu, uint32_t s,
+                                          cx<typename Traits<P>::real> (&u)[9])
+{
+    using T = typename Traits<P>::real;
+    if constexpr (P == F64) {
+        const double2 *b = reinterpret_cast<const double2 *>(U) + (size_t)mu * 6 * V + s;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double2 d = b[(size_t)k * V];
+            u[k] = cx<double>{d.x, d.y};
+        }
+    } else if constexpr (P == F32) {
+        const float4 *b = reinterpret_cast<const float4 *>(U) + (size_t)mu * 3 * V + s;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float4 d = b[(size_t)k * V];
+            u[2 * k] = cx<float>{d.x, d.y};
+            u[2 * k + 1] = cx<float>{d.z, d.w};
+        }
+    } else {
+        const uint2 *b = reinterpret_cast<const uint2 *>(U) + (size_t)mu * 3 * V + s;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint2 d = b[(size_t)k * V];
+            u[2 * k] = unpack2<P>(d.x);
+            u[2 * k + 1] = unpack2<P>(d.y);
+        }
+    }
+    // row 2 = conj(row0 x row1)
+    cx<T> a0 = u[0], a1 = u[1], a2 = u[2], b0 = u[3], b1 = u[4], b2 = u[5];
+    cx<T> c0 = cmul(a1, b2), c1 = cmul(a2, b0), c2 = cmul(a0, b1);
+    c0 = cfma(cx<T>{-a2.re, -a2.im}, b1, c0);
+    c1 = cfma(cx<T>{-a0.re, -a0.im}, b2, c1);
+    c2 = cfma(cx<T>{-a1.re, -a1.im}, b0, c2);
+    u[6] = cconj(c0);
+    u[7] = cconj(c1);
+    u[8] = cconj(c2);
+}
+
+// ---------------------------------------------------------------- fast division
+// q = floor(n / d) for n < 2^31 via a 32-bit multiply-high (round-up magic
+// number, Granlund & Montgomery 1994).
+struct FastDiv {
+    uint32_t d, m, l;
+};
+static inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d)
+        ++l;
+    uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return FastDiv{d, (uint32_t)m, l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return (__umulhi(n, f.m) + n) >> f.l; }
+
+// ---------------------------------------------------------------- tile order
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  With remapping, XCD k processes one contiguous range of tiles, so the
+// +-x, +-y, +-z neighbours of a tile are mostly in the same L2.
+__device__ __forceinline__ uint32_t tile_of(uint32_t b, uint32_t nb, int xcd)
+{
+    if (!xcd)
+        return b;
+    const uint32_t q = nb >> 3, r = nb & 7u, k = b & 7u, j = b >> 3;
+    return k * q + (k < r ? k : r) + j;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block sum of N values per thread; thread 0 returns the sums.
+// `lds` must hold N * (blockDim.x / 64) doubles.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        v[i] = wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            lds[i * nw + w] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double a = 0.0;
+            for (int k = 0; k < nw; ++k)
+                a += lds[i * nw + k];
+            v[i] = a;
+        }
+    }
+}
+
+}  // namespace wl

@@ -1,0 +1,158 @@
+// wl_internal.h -- host-side internals shared by the library's translation
+// units: the operator object, kernel parameter blocks and the launch entry
+// points each .hip file exports to the host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "../../include/wilson.h"
+#include "wl_common.h"
+
+namespace wl {
+
+// Launch configuration of the stencil.
+struct LaunchCfg {
+    int block = 256;  // threads per workgroup (= sites per tile)
+    int rpt = 1;      // right-hand sides per thread
+    int xcd = 1;      // XCD-aware tile order
+};
+
+}  // namespace wl
+
+struct wl_op {
+    wl_geom g;
+    double kappa;
+    int prec;
+    const void *U;
+    uint32_t V;
+    std::mutex mu;
+    std::map<int, wl::LaunchCfg> launch;  // keyed by nrhs
+};
+
+namespace wl {
+
+// Reduction requested from a kernel epilogue (partials [nval][nrhs][nblk]).
+enum Red {
+    RED_NONE = 0,
+    RED_NORM = 1,      // |out|^2                           (1 value)
+    RED_DOTV = 2,      // <v, out> with v = aux              (2 values: re, im)
+    RED_DOTIN_NORM = 3 // <in, out> and |out|^2              (3 values)
+};
+
+struct StencilParams {
+    const void *U;
+    const void *in;
+    void *out;
+    const void *aux;   // RED_DOTV: the v of <v, out>
+    double *partials;  // per-block partial sums
+    FastDiv fx, fy, fz;
+    int L[4];
+    int bc[4];
+    uint32_t V;
+    int nrhs;
+    double kappa;
+    int apply;  // 1: out = in - kappa H in; 0: out = H in
+    int red;
+    int xcd;
+    int nblk;   // number of site tiles (gridDim.x)
+};
+
+// ---- stencil (wl_stencil.hip)
+hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st);
+int stencil_nval(int red);
+int max_rpt(int prec);  // largest right-hand sides per thread the stencil offers
+
+struct MultiEntry {
+    StencilParams p;
+    uint32_t tile_begin;  // prefix of tiles
+};
+hipError_t launch_multi(int prec, int dagger, int rpt, int block, const MultiEntry *dev_entries, int n,
+                        uint32_t total_tiles, unsigned *counter, int grid, hipStream_t st);
+int multi_grid_size(int prec, int dagger, int rpt, int block);
+
+hipError_t launch_force(int prec, const wl_op *op, void *out, const void *x, const void *mu, int project,
+                        hipStream_t st);
+
+// ---- pack (wl_pack.hip)
+hipError_t launch_pack_gauge(int prec, uint32_t V, const void *canon, void *packed, hipStream_t st);
+hipError_t launch_pack_spinor(int prec, uint32_t V, int nrhs, const void *canon, void *packed, hipStream_t st);
+hipError_t launch_unpack_spinor(int prec, uint32_t V, int nrhs, const void *packed, void *canon, hipStream_t st);
+// out = in * f(rhs) where f = 1 (mode 0), s[rhs] (mode 1) or 1/s[rhs] (mode 2, 0 if s == 0);
+// s[] is read from device memory with stride `sstride` doubles.
+hipError_t launch_convert(int pin, int pout, uint32_t V, int nrhs, const void *in, void *out, const double *s,
+                          int sstride, int mode, hipStream_t st);
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int n, hipStream_t st);
+
+// ---- BLAS-1 and solver scalars (wl_blas.hip)
+// Per-right-hand-side solver scalars, kept on the device.
+struct Scalars {
+    double bb;            // |b|^2 of the system being solved
+    double rr;            // |r|^2 (iterated)
+    double zz;            // CGNR |z|^2
+    double ss;            // BiCGStab |s|^2
+    double2 alpha, beta, omega, rho;
+    double tol2;          // converge when rr <= tol2 * bb
+    int flag;             // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
+    int conv_iter;
+    int pad[2];
+};
+
+enum BlasOp {
+    B_RES = 0,        // r = b - w                      ; |r|^2
+    B_CG_XR = 1,      // x += a p ; r -= a w            ; |r|^2
+    B_CG_P = 2,       // p = z + beta p
+    B_BI_P = 3,       // p = r + beta (p - omega v)
+    B_BI_S = 4,       // s = r - alpha v                ; |s|^2
+    B_BI_XR = 5,      // x += alpha p + omega s ; r = s - omega t ; |r|^2, <rh, r>  (a3 = rh)
+    B_COPY = 6,       // y = x
+    B_ZERO = 7,       // y = 0
+    B_NORM = 8        // |x|^2
+};
+struct BlasParams {
+    void *y0;          // first output / in-out vector
+    void *y1;          // second output / in-out vector
+    const void *a0, *a1, *a2, *a3;  // inputs
+    const Scalars *sc;
+    double *partials;
+    uint32_t V;
+    int nrhs;
+    int nblk;
+};
+hipError_t launch_blas(int prec, int op, const BlasParams &p, int block, hipStream_t st);
+int blas_nval(int op);
+
+// x64 += s[rhs] * e (e in precision pin); s read from device with stride.
+hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e, const double *s, int sstride,
+                        hipStream_t st);
+
+enum FinOp {
+    F_INIT_CG = 0,    // vals: |r|^2 (set A), |z|^2 (set B); bb from |b|^2 set C
+    F_CG_ALPHA = 1,   // vals: |w|^2
+    F_CG_BETA = 2,    // vals: |r|^2 (A), |z|^2 (B)
+    F_INIT_BI = 3,    // vals: |r|^2 (A), bb (C)
+    F_BI_ALPHA = 4,   // vals: <rh, v>
+    F_BI_OMEGA = 5,   // vals: |s|^2 (A), <s,t>, |t|^2 (B)
+    F_BI_RHO = 6,     // vals: |r|^2, <rh, r> (A)
+    F_SUM = 7         // just reduce set A into out[] (nval x nrhs)
+};
+struct FinParams {
+    const double *A;
+    const double *B;
+    const double *C;
+    int nblkA, nblkB, nblkC;
+    int nvalA, nvalB, nvalC;
+    Scalars *sc;
+    double *out;      // F_SUM destination [nval][nrhs]
+    int nrhs;
+    int iter;
+    double tol2;
+};
+hipError_t launch_finalize(int op, const FinParams &p, hipStream_t st);
+hipError_t launch_scalars_init(Scalars *sc, int nrhs, double tol2, hipStream_t st);
+
+}  // namespace wl

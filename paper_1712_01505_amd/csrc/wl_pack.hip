@@ -1,0 +1,214 @@
+// wl_pack.hip -- conversion between the caller's canonical complex128 layout
+// and the library's packed site-contiguous layouts, and between packed
+// precisions.  The paper keeps data layout and type flexible and converts at
+// the boundary of the offloaded solver (Sec. IV-A); here that boundary is the
+// pack/unpack step, off the per-iteration path.
+#include "wl_internal.h"
+
+namespace wl {
+
+// canonical gauge [mu][V][3][3] complex128 -> packed [mu][unit][V] (rows 0, 1)
+template <int P>
+__global__ void pack_gauge_kernel(uint32_t V, const double2 *__restrict__ canon, void *__restrict__ packed)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (s >= V)
+        return;
+    const double2 *c = canon + ((size_t)mu * V + s) * 9;
+    if constexpr (P == F64) {
+        double2 *o = reinterpret_cast<double2 *>(packed) + (size_t)mu * 6 * V + s;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            o[(size_t)k * V] = c[k];
+    } else if constexpr (P == F32) {
+        float4 *o = reinterpret_cast<float4 *>(packed) + (size_t)mu * 3 * V + s;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            o[(size_t)k * V] = make_float4((float)c[2 * k].x, (float)c[2 * k].y, (float)c[2 * k + 1].x,
+                                           (float)c[2 * k + 1].y);
+    } else {
+        uint2 *o = reinterpret_cast<uint2 *>(packed) + (size_t)mu * 3 * V + s;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            // round FP64 -> FP32 -> 16-bit (link entries satisfy |U_ij| <= 1; no scale)
+            uint2 d;
+            d.x = pack2<P>((float)c[2 * k].x, (float)c[2 * k].y);
+            d.y = pack2<P>((float)c[2 * k + 1].x, (float)c[2 * k + 1].y);
+            o[(size_t)k * V] = d;
+        }
+    }
+}
+
+// canonical spinor [rhs][V][4][3] complex128 <-> packed
+template <int P>
+__global__ void pack_spinor_kernel(uint32_t V, int nrhs, const double2 *__restrict__ canon, void *__restrict__ packed)
+{
+    using T = typename Traits<P>::real;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= V)
+        return;
+    const double2 *c = canon + ((size_t)r * V + s) * 12;
+    cx<T> v[12];
+    if constexpr (Traits<P>::SCALED) {
+        // the per-site scale is taken from the FP64 values
+        double m = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            m = fmax(m, fmax(fabs(c[k].x), fabs(c[k].y)));
+        const float sc = (float)m;
+        const double inv = m > 0.0 ? 1.0 / (double)sc : 0.0;
+        uint4 *o = reinterpret_cast<uint4 *>(packed) + (size_t)r * 3 * V + s;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 d;
+            d.x = pack2<P>((float)(c[4 * k + 0].x * inv), (float)(c[4 * k + 0].y * inv));
+            d.y = pack2<P>((float)(c[4 * k + 1].x * inv), (float)(c[4 * k + 1].y * inv));
+            d.z = pack2<P>((float)(c[4 * k + 2].x * inv), (float)(c[4 * k + 2].y * inv));
+            d.w = pack2<P>((float)(c[4 * k + 3].x * inv), (float)(c[4 * k + 3].y * inv));
+            o[(size_t)k * V] = d;
+        }
+        float *scp = reinterpret_cast<float *>(reinterpret_cast<char *>(packed) + (size_t)nrhs * V * 48);
+        scp[(size_t)r * V + s] = sc;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            v[k] = cx<T>{(T)c[k].x, (T)c[k].y};
+        store_site<P>(packed, V, nrhs, s, r, v);
+    }
+}
+
+template <int P>
+__global__ void unpack_spinor_kernel(uint32_t V, int nrhs, const void *__restrict__ packed, double2 *__restrict__ canon)
+{
+    using T = typename Traits<P>::real;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= V)
+        return;
+    cx<T> v[12];
+    load_site<P>(packed, V, nrhs, s, r, v);
+    double2 *c = canon + ((size_t)r * V + s) * 12;
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        c[k] = make_double2((double)v[k].re, (double)v[k].im);
+}
+
+// out = f(rhs) * in across precisions.
+template <int PI, int PO>
+__global__ void convert_kernel(uint32_t V, int nrhs, const void *__restrict__ in, void *__restrict__ out,
+                               const double *__restrict__ sarr, int sstride, int mode)
+{
+    using TI = typename Traits<PI>::real;
+    using TO = typename Traits<PO>::real;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= V)
+        return;
+    double f = 1.0;
+    if (mode == 1)
+        f = sarr[(size_t)r * sstride];
+    else if (mode == 2) {
+        const double d = sarr[(size_t)r * sstride];
+        f = d != 0.0 ? 1.0 / d : 0.0;
+    }
+    cx<TI> a[12];
+    load_site<PI>(in, V, nrhs, s, r, a);
+    cx<TO> b[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        b[k] = cx<TO>{(TO)((double)a[k].re * f), (TO)((double)a[k].im * f)};
+    store_site<PO>(out, V, nrhs, s, r, b);
+}
+
+__global__ void fill_u32_kernel(unsigned *p, unsigned v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+static inline dim3 grid_for(uint32_t V, int nrhs, int block) { return dim3((V + block - 1) / block, nrhs); }
+
+hipError_t launch_pack_gauge(int prec, uint32_t V, const void *canon, void *packed, hipStream_t st)
+{
+    const int B = 256;
+    dim3 g((V + B - 1) / B, 4);
+    const double2 *c = (const double2 *)canon;
+    switch (prec) {
+    case F64: hipLaunchKernelGGL(pack_gauge_kernel<F64>, g, dim3(B), 0, st, V, c, packed); break;
+    case F32: hipLaunchKernelGGL(pack_gauge_kernel<F32>, g, dim3(B), 0, st, V, c, packed); break;
+    case BF16S: hipLaunchKernelGGL(pack_gauge_kernel<BF16S>, g, dim3(B), 0, st, V, c, packed); break;
+    case F16S: hipLaunchKernelGGL(pack_gauge_kernel<F16S>, g, dim3(B), 0, st, V, c, packed); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_spinor(int prec, uint32_t V, int nrhs, const void *canon, void *packed, hipStream_t st)
+{
+    const int B = 256;
+    dim3 g = grid_for(V, nrhs, B);
+    const double2 *c = (const double2 *)canon;
+    switch (prec) {
+    case F64: hipLaunchKernelGGL(pack_spinor_kernel<F64>, g, dim3(B), 0, st, V, nrhs, c, packed); break;
+    case F32: hipLaunchKernelGGL(pack_spinor_kernel<F32>, g, dim3(B), 0, st, V, nrhs, c, packed); break;
+    case BF16S: hipLaunchKernelGGL(pack_spinor_kernel<BF16S>, g, dim3(B), 0, st, V, nrhs, c, packed); break;
+    case F16S: hipLaunchKernelGGL(pack_spinor_kernel<F16S>, g, dim3(B), 0, st, V, nrhs, c, packed); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_spinor(int prec, uint32_t V, int nrhs, const void *packed, void *canon, hipStream_t st)
+{
+    const int B = 256;
+    dim3 g = grid_for(V, nrhs, B);
+    double2 *c = (double2 *)canon;
+    switch (prec) {
+    case F64: hipLaunchKernelGGL(unpack_spinor_kernel<F64>, g, dim3(B), 0, st, V, nrhs, packed, c); break;
+    case F32: hipLaunchKernelGGL(unpack_spinor_kernel<F32>, g, dim3(B), 0, st, V, nrhs, packed, c); break;
+    case BF16S: hipLaunchKernelGGL(unpack_spinor_kernel<BF16S>, g, dim3(B), 0, st, V, nrhs, packed, c); break;
+    case F16S: hipLaunchKernelGGL(unpack_spinor_kernel<F16S>, g, dim3(B), 0, st, V, nrhs, packed, c); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int PI>
+static hipError_t convert_to(int pout, dim3 g, int B, uint32_t V, int nrhs, const void *in, void *out,
+                             const double *s, int ss, int mode, hipStream_t st)
+{
+    switch (pout) {
+    case F64: hipLaunchKernelGGL((convert_kernel<PI, F64>), g, dim3(B), 0, st, V, nrhs, in, out, s, ss, mode); break;
+    case F32: hipLaunchKernelGGL((convert_kernel<PI, F32>), g, dim3(B), 0, st, V, nrhs, in, out, s, ss, mode); break;
+    case BF16S: hipLaunchKernelGGL((convert_kernel<PI, BF16S>), g, dim3(B), 0, st, V, nrhs, in, out, s, ss, mode); break;
+    case F16S: hipLaunchKernelGGL((convert_kernel<PI, F16S>), g, dim3(B), 0, st, V, nrhs, in, out, s, ss, mode); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int pin, int pout, uint32_t V, int nrhs, const void *in, void *out, const double *s,
+                          int sstride, int mode, hipStream_t st)
+{
+    const int B = 256;
+    dim3 g = grid_for(V, nrhs, B);
+    switch (pin) {
+    case F64: return convert_to<F64>(pout, g, B, V, nrhs, in, out, s, sstride, mode, st);
+    case F32: return convert_to<F32>(pout, g, B, V, nrhs, in, out, s, sstride, mode, st);
+    case BF16S: return convert_to<BF16S>(pout, g, B, V, nrhs, in, out, s, sstride, mode, st);
+    case F16S: return convert_to<F16S>(pout, g, B, V, nrhs, in, out, s, sstride, mode, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int n, hipStream_t st)
+{
+    const int B = 256;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((n + B - 1) / B), dim3(B), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace wl

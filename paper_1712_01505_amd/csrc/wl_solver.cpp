@@ -1,0 +1,569 @@
+// wl_solver.cpp -- host drivers of the Krylov solvers: CGNR and BiCGStab
+// (paper Sec. II-C; BiCGStab for the Wilson matrix, CG on the normal
+// equations) and the mixed-precision refinement around a low-precision
+// inner solve (Sec. II-C: the inner solver sets the performance).
+//
+// Every vector operation is a kernel on the caller's stream; the scalar
+// recurrences live on the device (wl_blas.hip), so an iteration issues only
+// kernel launches and the host polls the per-right-hand-side status every
+// `check_every` iterations.  All right-hand sides run together; a converged
+// or broken-down column is frozen by zeroing its coefficients on the device.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "wl_internal.h"
+
+namespace wl {
+
+hipError_t prof_stencil(int prec, const wl_op *op, int dagger, const LaunchCfg &cfg, StencilParams p,
+                        hipStream_t st);  // wl_api.cpp
+LaunchCfg launch_for(const wl_op *op, int nrhs);  // wl_api.cpp
+void set_last_hip_error(hipError_t e);           // wl_api.cpp
+
+namespace {
+
+constexpr int BLAS_BLOCK = 256;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t vec_bytes(int prec, uint32_t V, int nrhs) { return (size_t)nrhs * V * spinor_site_bytes(prec); }
+
+// Largest number of per-workgroup partials any kernel here produces.
+size_t max_nblk(uint32_t V) { return (V + 63) / 64; }
+size_t partial_bytes(uint32_t V, int nrhs) { return align_up(3 * (size_t)nrhs * max_nblk(V) * sizeof(double)); }
+
+struct Arena {
+    char *base;
+    size_t cap, off = 0;
+    void *take(size_t n)
+    {
+        n = align_up(n);
+        if (off + n > cap)
+            return nullptr;
+        void *p = base + off;
+        off += n;
+        return p;
+    }
+};
+
+// Bytes of one Krylov engine for op precision `prec`.
+size_t engine_bytes(int solver, int prec, uint32_t V, int nrhs)
+{
+    const int nvec = solver == WL_SOLVER_CGNR ? 4 : 6;
+    return nvec * align_up(vec_bytes(prec, V, nrhs)) + 3 * partial_bytes(V, nrhs) +
+           align_up(sizeof(Scalars) * nrhs) + align_up(sizeof(double) * 3 * nrhs);
+}
+
+#define WL_TRY(expr)                                                                                           \
+    do {                                                                                                       \
+        hipError_t e_ = (expr);                                                                                \
+        if (e_ != hipSuccess) {                                                                                \
+            set_last_hip_error(e_);                                                                            \
+            return WL_EHIP;                                                                                    \
+        }                                                                                                      \
+    } while (0)
+
+// A Krylov solver instance on one operator (one precision), nrhs columns.
+struct Engine {
+    const wl_op *op;
+    int solver, nrhs, prec;
+    uint32_t V;
+    hipStream_t st;
+    int check_every;
+    void *v[6];
+    double *part[3];
+    int nblk[3] = {0, 0, 0}, nval[3] = {0, 0, 0};
+    Scalars *sc;
+    double *sums;
+    Scalars *sc_host;  // pinned
+    int stencil_calls = 0;
+
+    int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, Scalars *host_sc)
+    {
+        op = o;
+        solver = solv;
+        nrhs = n;
+        prec = o->prec;
+        V = o->V;
+        st = s;
+        sc_host = host_sc;
+        const int nvec = solver == WL_SOLVER_CGNR ? 4 : 6;
+        for (int i = 0; i < nvec; ++i)
+            if (!(v[i] = a.take(vec_bytes(prec, V, nrhs))))
+                return WL_EWORKSPACE;
+        for (int i = 0; i < 3; ++i)
+            if (!(part[i] = (double *)a.take(partial_bytes(V, nrhs))))
+                return WL_EWORKSPACE;
+        if (!(sc = (Scalars *)a.take(sizeof(Scalars) * nrhs)))
+            return WL_EWORKSPACE;
+        if (!(sums = (double *)a.take(sizeof(double) * 3 * nrhs)))
+            return WL_EWORKSPACE;
+        return WL_OK;
+    }
+
+    int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot)
+    {
+        StencilParams p{};
+        p.U = op->U;
+        p.in = in;
+        p.out = out;
+        p.aux = aux;
+        p.partials = slot >= 0 ? part[slot] : nullptr;
+        for (int i = 0; i < 4; ++i) {
+            p.L[i] = op->g.dims[i];
+            p.bc[i] = op->g.bc[i];
+        }
+        p.fx = make_fastdiv((uint32_t)p.L[0]);
+        p.fy = make_fastdiv((uint32_t)p.L[1]);
+        p.fz = make_fastdiv((uint32_t)p.L[2]);
+        p.V = V;
+        p.nrhs = nrhs;
+        p.kappa = op->kappa;
+        p.apply = 1;
+        p.red = red;
+        LaunchCfg cfg = launch_for(op, nrhs);
+        if (slot >= 0) {
+            nblk[slot] = (int)((V + cfg.block - 1) / cfg.block);
+            nval[slot] = stencil_nval(red);
+        }
+        ++stencil_calls;
+        WL_TRY(prof_stencil(prec, op, dagger, cfg, p, st));
+        return WL_OK;
+    }
+
+    int blas(int bop, void *y0, void *y1, const void *a0, const void *a1, const void *a2, const void *a3, int slot)
+    {
+        BlasParams p{};
+        p.y0 = y0;
+        p.y1 = y1;
+        p.a0 = a0;
+        p.a1 = a1;
+        p.a2 = a2;
+        p.a3 = a3;
+        p.sc = sc;
+        p.partials = slot >= 0 ? part[slot] : nullptr;
+        p.V = V;
+        p.nrhs = nrhs;
+        if (slot >= 0) {
+            nblk[slot] = (int)((V + BLAS_BLOCK - 1) / BLAS_BLOCK);
+            nval[slot] = blas_nval(bop);
+        }
+        WL_TRY(launch_blas(prec, bop, p, BLAS_BLOCK, st));
+        return WL_OK;
+    }
+
+    int fin(int fop, int a, int b, int c, int iter, double tol2)
+    {
+        FinParams p{};
+        if (a >= 0) {
+            p.A = part[a];
+            p.nblkA = nblk[a];
+            p.nvalA = nval[a];
+        }
+        if (b >= 0) {
+            p.B = part[b];
+            p.nblkB = nblk[b];
+            p.nvalB = nval[b];
+        }
+        if (c >= 0) {
+            p.C = part[c];
+            p.nblkC = nblk[c];
+            p.nvalC = nval[c];
+        }
+        p.sc = sc;
+        p.out = sums;
+        p.nrhs = nrhs;
+        p.iter = iter;
+        p.tol2 = tol2;
+        WL_TRY(launch_finalize(fop, p, st));
+        return WL_OK;
+    }
+
+    // Copy the per-RHS scalars to the host (synchronises the stream).
+    int poll()
+    {
+        WL_TRY(hipMemcpyAsync(sc_host, sc, sizeof(Scalars) * nrhs, hipMemcpyDeviceToHost, st));
+        WL_TRY(hipStreamSynchronize(st));
+        return WL_OK;
+    }
+
+    bool all_done() const
+    {
+        for (int r = 0; r < nrhs; ++r)
+            if (sc_host[r].flag == 0)
+                return false;
+        return true;
+    }
+
+    // Run the Krylov iteration for D x = b from x (zero_x: x := 0 first).
+    // Afterwards sc_host holds the final per-RHS scalars.  *iters_done is
+    // the number of iterations executed.
+    int run(void *x, const void *b, bool zero_x, double tol, int maxiter, int *iters_done)
+    {
+        const double tol2 = tol * tol;
+        int rc;
+        void *r = v[0];
+        if (zero_x) {
+            if ((rc = blas(B_ZERO, x, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = blas(B_COPY, r, nullptr, b, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = blas(B_NORM, nullptr, nullptr, r, nullptr, nullptr, nullptr, 0)))
+                return rc;
+        } else {
+            void *w = v[1];
+            if ((rc = stencil(w, x, 0, RED_NONE, nullptr, -1)))
+                return rc;
+            if ((rc = blas(B_RES, r, nullptr, b, w, nullptr, nullptr, 0)))
+                return rc;
+        }
+        if ((rc = blas(B_NORM, nullptr, nullptr, b, nullptr, nullptr, nullptr, 2)))
+            return rc;
+        int it = 0;
+        if (solver == WL_SOLVER_CGNR) {
+            void *z = v[1], *p = v[2], *w = v[3];
+            if ((rc = stencil(z, r, 1, RED_NORM, nullptr, 1)))
+                return rc;
+            if ((rc = fin(F_INIT_CG, 0, 1, 2, 0, tol2)))
+                return rc;
+            if ((rc = blas(B_COPY, p, nullptr, z, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = poll()))
+                return rc;
+            while (!all_done() && it < maxiter) {
+                if ((rc = stencil(w, p, 0, RED_NORM, nullptr, 0)))
+                    return rc;
+                if ((rc = fin(F_CG_ALPHA, 0, -1, -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_CG_XR, x, r, p, w, nullptr, nullptr, 0)))
+                    return rc;
+                if ((rc = stencil(z, r, 1, RED_NORM, nullptr, 1)))
+                    return rc;
+                if ((rc = fin(F_CG_BETA, 0, 1, -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_CG_P, p, nullptr, z, nullptr, nullptr, nullptr, -1)))
+                    return rc;
+                ++it;
+                if (it % check_every == 0 || it == maxiter)
+                    if ((rc = poll()))
+                        return rc;
+            }
+        } else {
+            void *rh = v[1], *p = v[2], *vv = v[3], *s = v[4], *t = v[5];
+            if ((rc = blas(B_COPY, rh, nullptr, r, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = blas(B_ZERO, p, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = blas(B_ZERO, vv, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = fin(F_INIT_BI, 0, -1, 2, 0, tol2)))
+                return rc;
+            if ((rc = poll()))
+                return rc;
+            while (!all_done() && it < maxiter) {
+                if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1)))
+                    return rc;
+                if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0)))
+                    return rc;
+                if ((rc = fin(F_BI_ALPHA, 0, -1, -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_BI_S, s, nullptr, r, vv, nullptr, nullptr, 0)))
+                    return rc;
+                if ((rc = stencil(t, s, 0, RED_DOTIN_NORM, nullptr, 1)))
+                    return rc;
+                if ((rc = fin(F_BI_OMEGA, 0, 1, -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_BI_XR, x, r, p, s, t, rh, 0)))
+                    return rc;
+                if ((rc = fin(F_BI_RHO, 0, -1, -1, it, tol2)))
+                    return rc;
+                ++it;
+                if (it % check_every == 0 || it == maxiter)
+                    if ((rc = poll()))
+                        return rc;
+            }
+        }
+        if (!all_done())
+            if ((rc = poll()))
+                return rc;
+        *iters_done = it;
+        return WL_OK;
+    }
+
+    // out[r] = |b - D x|^2 per right-hand side, into host array (synchronous).
+    int true_res2(void *x, const void *b, double *out_host)
+    {
+        int rc;
+        void *w = v[1], *r = v[0];
+        if ((rc = stencil(w, x, 0, RED_NONE, nullptr, -1)))
+            return rc;
+        if ((rc = blas(B_RES, r, nullptr, b, w, nullptr, nullptr, 0)))
+            return rc;
+        if ((rc = fin(F_SUM, 0, -1, -1, 0, 0.0)))
+            return rc;
+        WL_TRY(hipMemcpyAsync(out_host, sums, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+        WL_TRY(hipStreamSynchronize(st));
+        return WL_OK;
+    }
+
+    int norm2(const void *b, double *out_host)
+    {
+        int rc;
+        if ((rc = blas(B_NORM, nullptr, nullptr, b, nullptr, nullptr, nullptr, 2)))
+            return rc;
+        if ((rc = fin(F_SUM, 2, -1, -1, 0, 0.0)))
+            return rc;
+        WL_TRY(hipMemcpyAsync(out_host, sums, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+        WL_TRY(hipStreamSynchronize(st));
+        return WL_OK;
+    }
+};
+
+struct PinnedScalars {
+    Scalars *p = nullptr;
+    double *d = nullptr;
+    ~PinnedScalars()
+    {
+        if (p)
+            (void)hipHostFree(p);
+        if (d)
+            (void)hipHostFree(d);
+    }
+};
+
+struct OwnedWorkspace {
+    void *p = nullptr;
+    ~OwnedWorkspace()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+};
+
+int default_check_every(uint32_t V) { return V >= (1u << 20) ? 2 : V >= (1u << 16) ? 4 : 8; }
+
+int status_of(const wl_solve_stats &s, int flag)
+{
+    if (s.converged)
+        return WL_OK;
+    if (flag == 2)
+        return WL_BREAKDOWN;
+    return WL_NOT_CONVERGED;
+}
+
+// Plain solve in the op's own precision.
+int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, const wl_solve_params *prm,
+                wl_solve_stats *stats, hipStream_t st, Arena &arena)
+{
+    PinnedScalars pin;
+    if (hipHostMalloc((void **)&pin.p, sizeof(Scalars) * nrhs) != hipSuccess ||
+        hipHostMalloc((void **)&pin.d, sizeof(double) * 4 * nrhs) != hipSuccess)
+        return WL_EHIP;
+    Engine E{};
+    int rc = E.init(arena, op, solver, nrhs, st, pin.p);
+    if (rc)
+        return rc;
+    E.check_every = prm->check_every > 0 ? prm->check_every : default_check_every(op->V);
+    double *bb = pin.d, *rr = pin.d + nrhs;
+    if ((rc = E.norm2(b, bb)))
+        return rc;
+    std::vector<int> iters(nrhs, 0), flags(nrhs, 0);
+    std::vector<double> itres(nrhs, 0.0);
+    int total = 0;
+    bool zero_x = !prm->use_x0;
+    for (int attempt = 0; attempt < 4 && total < prm->maxiter; ++attempt) {
+        int done = 0;
+        if ((rc = E.run(x, b, zero_x, prm->tol, prm->maxiter - total, &done)))
+            return rc;
+        zero_x = false;
+        for (int r = 0; r < nrhs; ++r) {
+            const Scalars &s = E.sc_host[r];
+            iters[r] += s.flag == 1 ? s.conv_iter : done;
+            flags[r] = s.flag;
+            itres[r] = bb[r] > 0 ? std::sqrt(s.rr / bb[r]) : 0.0;
+            if (s.flag == 3)
+                return WL_ENAN;
+        }
+        total += done;
+        if ((rc = E.true_res2(x, b, rr)))
+            return rc;
+        bool all_ok = true;
+        for (int r = 0; r < nrhs; ++r) {
+            if (!std::isfinite(rr[r]))
+                return WL_ENAN;
+            if (!(rr[r] <= prm->tol * prm->tol * bb[r]))
+                all_ok = false;
+        }
+        if (all_ok)
+            break;
+        // recursive and true residual disagree, or breakdown: restart from x
+    }
+    int worst = WL_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        wl_solve_stats s{};
+        s.iters = iters[r];
+        s.outer = 0;
+        s.stencil_calls = E.stencil_calls;
+        s.true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
+        s.iter_rel_res = itres[r];
+        s.converged = s.true_rel_res <= prm->tol;
+        const int code = status_of(s, flags[r]);
+        if (code > worst)
+            worst = code;
+        if (stats)
+            stats[r] = s;
+    }
+    return worst;
+}
+
+// Mixed precision: FP64 outer true-residual refinement around an inner solve
+// in lo's precision (restarted each cycle: defect correction).
+int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
+                const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena)
+{
+    PinnedScalars pin;
+    if (hipHostMalloc((void **)&pin.p, sizeof(Scalars) * nrhs) != hipSuccess ||
+        hipHostMalloc((void **)&pin.d, sizeof(double) * 4 * nrhs) != hipSuccess)
+        return WL_EHIP;
+    Engine H{}, L{};
+    int rc;
+    // the outer engine only needs r, w and the partial/scalar buffers; it is
+    // initialised as a CGNR engine (4 vectors) for simplicity of layout
+    if ((rc = H.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, pin.p)))
+        return rc;
+    if ((rc = L.init(arena, lo, solver, nrhs, st, pin.p)))
+        return rc;
+    void *r_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
+    void *e_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
+    double *sig_dev = (double *)arena.take(sizeof(double) * nrhs);
+    if (!r_lo || !e_lo || !sig_dev)
+        return WL_EWORKSPACE;
+    H.check_every = L.check_every = prm->check_every > 0 ? prm->check_every : default_check_every(hi->V);
+    double *bb = pin.d, *rr = pin.d + nrhs, *sig = pin.d + 2 * nrhs;
+    if ((rc = H.norm2(b, bb)))
+        return rc;
+    if (!prm->use_x0)
+        if ((rc = H.blas(B_ZERO, x, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+            return rc;
+    const double tol = prm->tol;
+    const double delta = prm->inner_tol > 0 ? prm->inner_tol : (lo->prec == WL_F32 ? 1e-5 : 3e-2);
+    const int max_outer = prm->max_outer > 0 ? prm->max_outer : 50;
+    std::vector<int> iters(nrhs, 0);
+    std::vector<double> prev(nrhs, INFINITY), best(nrhs, INFINITY);
+    std::vector<int> stall(nrhs, 0);
+    int total = 0, outer = 0, worst_flag = 0;
+    bool stagnated = false;
+    for (;;) {
+        if ((rc = H.true_res2(x, b, rr)))
+            return rc;
+        bool all_ok = true;
+        for (int r = 0; r < nrhs; ++r) {
+            if (!std::isfinite(rr[r]))
+                return WL_ENAN;
+            const bool ok = rr[r] <= tol * tol * bb[r];
+            sig[r] = ok ? 0.0 : std::sqrt(rr[r]);
+            if (!ok) {
+                all_ok = false;
+                const double rel = std::sqrt(rr[r] / bb[r]);
+                if (rel > 0.9 * best[r])
+                    ++stall[r];
+                else
+                    stall[r] = 0;
+                if (rel < best[r])
+                    best[r] = rel;
+                if (stall[r] >= 2)
+                    stagnated = true;
+            }
+        }
+        if (all_ok || stagnated || outer >= max_outer || total >= prm->maxiter)
+            break;
+        WL_TRY(hipMemcpyAsync(sig_dev, sig, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+        // r_lo = r64 / sigma (0 for converged columns)
+        WL_TRY(launch_convert(WL_F64, lo->prec, hi->V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
+        int done = 0;
+        if ((rc = L.run(e_lo, r_lo, true, delta, prm->maxiter - total, &done)))
+            return rc;
+        for (int r = 0; r < nrhs; ++r) {
+            const Scalars &s = L.sc_host[r];
+            if (sig[r] != 0.0)
+                iters[r] += s.flag == 1 ? s.conv_iter : done;
+            if (s.flag == 3)
+                return WL_ENAN;
+            if (s.flag == 2 && worst_flag < 2)
+                worst_flag = 2;
+        }
+        total += done;
+        // x64 += sigma e
+        WL_TRY(launch_accum(lo->prec, hi->V, nrhs, x, e_lo, sig_dev, 1, st));
+        ++outer;
+    }
+    int worst = WL_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        wl_solve_stats s{};
+        s.iters = iters[r];
+        s.outer = outer;
+        s.stencil_calls = H.stencil_calls + L.stencil_calls;
+        s.true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
+        s.iter_rel_res = s.true_rel_res;
+        s.converged = s.true_rel_res <= tol;
+        int code = s.converged ? WL_OK : (stagnated ? WL_STAGNATED : worst_flag == 2 ? WL_BREAKDOWN : WL_NOT_CONVERGED);
+        if (code > worst)
+            worst = code;
+        if (stats)
+            stats[r] = s;
+    }
+    return worst;
+}
+
+}  // namespace
+
+size_t solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs)
+{
+    if (!lo)
+        return engine_bytes(solver, hi->prec, hi->V, nrhs) + 4 * ALIGN;
+    return engine_bytes(WL_SOLVER_CGNR, hi->prec, hi->V, nrhs) + engine_bytes(solver, lo->prec, lo->V, nrhs) +
+           2 * align_up(vec_bytes(lo->prec, lo->V, nrhs)) + align_up(sizeof(double) * nrhs) + 8 * ALIGN;
+}
+
+int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *prm,
+          wl_solve_stats *stats, hipStream_t st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t need = solver_workspace_bytes(hi, lo, solver, nrhs);
+    OwnedWorkspace own;
+    Arena arena{nullptr, 0};
+    if (prm->workspace) {
+        if (prm->workspace_bytes < need)
+            return WL_EWORKSPACE;
+        arena.base = (char *)prm->workspace;
+        arena.cap = prm->workspace_bytes;
+    } else {
+        hipError_t e = hipMalloc(&own.p, need);
+        if (e != hipSuccess) {
+            set_last_hip_error(e);
+            return WL_EHIP;
+        }
+        arena.base = (char *)own.p;
+        arena.cap = need;
+    }
+    // align the arena start
+    const size_t mis = (uintptr_t)arena.base % ALIGN;
+    if (mis) {
+        arena.off = ALIGN - mis;
+    }
+    int rc = lo ? solve_mixed(solver, hi, lo, x, b, nrhs, prm, stats, st, arena)
+                : solve_plain(solver, hi, x, b, nrhs, prm, stats, st, arena);
+    (void)hipStreamSynchronize(st);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats && rc >= 0)
+        for (int r = 0; r < nrhs; ++r)
+            stats[r].seconds = secs;
+    return rc;
+}
+
+}  // namespace wl

@@ -1,0 +1,597 @@
+// wl_stencil.hip -- the Wilson-Dirac hopping stencil on gfx950, its
+// multi-lattice persistent variant and the link-force kernel.
+//
+// Operator (Kanamori & Matsufuru, Sec. II-B, eq. (1), kappa normalisation):
+//   (H psi)(x) = sum_mu [ s+ (1 - g_mu) U_mu(x) psi(x+mu) + s- (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ]
+//   D psi = psi - kappa H psi;   D^dag swaps the projector signs.
+// Cost convention (Table I): 1368 flop/site for D, 1320 for H.
+//
+// Design (bandwidth-bound; no matrix cores: the 3x3 complex mat-vec has
+// about 1.8 flop/byte in FP64, far below the machine balance):
+//   * one thread per lattice site, R right-hand sides per thread so that a
+//     link loaded once serves R spinors;
+//   * site-contiguous packed fields: every component load of a wavefront is
+//     a contiguous 1 KB (FP64) / 1 KB (FP32, 2 complex) / 1 KB (16-bit, 4 complex);
+//   * spin projection: (1 -+ g_mu) has rank 2, so only a 2-spin half-spinor
+//     is multiplied by the link and the other two spin rows are rebuilt
+//     with 0, +-1, +-i coefficients (chiral basis);
+//   * two-row links, row 2 = conj(row0 x row1) rebuilt in registers;
+//   * the antiperiodic boundary sign multiplies the hop (never the link,
+//     since -U has det -1 and would rebuild a wrong third row);
+//   * XCD-aware tile order and fused reductions for the solvers.
+#include "wl_internal.h"
+
+namespace wl {
+
+// Upper two spin rows of (1 + SIG g_MU) psi, per colour: h[3*spin + colour].
+// Chiral basis: g_MU = [[0, A],[A^dag, 0]], so h = psi_up + SIG A psi_dn.
+template <int MU, int SIG, typename T>
+__device__ __forceinline__ void project(const cx<T> (&ps)[12], cx<T> (&h)[6])
+{
+    const T s = (T)SIG;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<T> p0 = ps[a], p1 = ps[3 + a], p2 = ps[6 + a], p3 = ps[9 + a];
+        if constexpr (MU == 0) {  // A = [[0, i], [i, 0]]
+            h[a] = ifma(s, p3, p0);
+            h[3 + a] = ifma(s, p2, p1);
+        } else if constexpr (MU == 1) {  // A = [[0, -1], [1, 0]]
+            h[a] = rfma(-s, p3, p0);
+            h[3 + a] = rfma(s, p2, p1);
+        } else if constexpr (MU == 2) {  // A = [[i, 0], [0, -i]]
+            h[a] = ifma(s, p2, p0);
+            h[3 + a] = ifma(-s, p3, p1);
+        } else {  // A = 1
+            h[a] = rfma(s, p2, p0);
+            h[3 + a] = rfma(s, p3, p1);
+        }
+    }
+}
+
+// acc += sg * [g ; SIG A^dag g]  (the full 4-spinor of a projected hop).
+template <int MU, int SIG, typename T>
+__device__ __forceinline__ void accum(cx<T> (&acc)[12], const cx<T> (&g)[6], T sg)
+{
+    const T s = sg * (T)SIG;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<T> g0 = g[a], g1 = g[3 + a];
+        acc[a] = rfma(sg, g0, acc[a]);
+        acc[3 + a] = rfma(sg, g1, acc[3 + a]);
+        if constexpr (MU == 0) {  // A^dag g = (-i g1, -i g0)
+            acc[6 + a] = ifma(-s, g1, acc[6 + a]);
+            acc[9 + a] = ifma(-s, g0, acc[9 + a]);
+        } else if constexpr (MU == 1) {  // A^dag g = (g1, -g0)
+            acc[6 + a] = rfma(s, g1, acc[6 + a]);
+            acc[9 + a] = rfma(-s, g0, acc[9 + a]);
+        } else if constexpr (MU == 2) {  // A^dag g = (-i g0, i g1)
+            acc[6 + a] = ifma(-s, g0, acc[6 + a]);
+            acc[9 + a] = ifma(s, g1, acc[9 + a]);
+        } else {  // A^dag g = g
+            acc[6 + a] = rfma(s, g0, acc[6 + a]);
+            acc[9 + a] = rfma(s, g1, acc[9 + a]);
+        }
+    }
+}
+
+// g = U h for both spin rows.
+template <typename T>
+__device__ __forceinline__ void su3_mv(const cx<T> (&u)[9], const cx<T> (&h)[6], cx<T> (&g)[6])
+{
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<T> v = cmul(u[3 * a], h[3 * sp]);
+            v = cfma(u[3 * a + 1], h[3 * sp + 1], v);
+            v = cfma(u[3 * a + 2], h[3 * sp + 2], v);
+            g[3 * sp + a] = v;
+        }
+}
+// g = U^dag h for both spin rows.
+template <typename T>
+__device__ __forceinline__ void su3_adj_mv(const cx<T> (&u)[9], const cx<T> (&h)[6], cx<T> (&g)[6])
+{
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<T> v = cmul(cconj(u[a]), h[3 * sp]);
+            v = cjfma(u[3 + a], h[3 * sp + 1], v);
+            v = cjfma(u[6 + a], h[3 * sp + 2], v);
+            g[3 * sp + a] = v;
+        }
+}
+
+// Both hops in direction MU for R right-hand sides.
+template <int P, int DAG, int R, int MU>
+__device__ __forceinline__ void hop_dir(const StencilParams &p, uint32_t s, int c, uint32_t stride, int r0,
+                                        cx<typename Traits<P>::real> (&acc)[R][12])
+{
+    using T = typename Traits<P>::real;
+    constexpr int SF = DAG ? 1 : -1;  // forward hop uses (1 + SF g), backward (1 - SF g)
+    const int L = p.L[MU];
+    const bool wf = (c == L - 1), wb = (c == 0);
+    const uint32_t span = (uint32_t)(L - 1) * stride;
+    const uint32_t sf = wf ? s - span : s + stride;
+    const uint32_t sb = wb ? s + span : s - stride;
+    const bool anti = p.bc[MU] < 0;
+    const T gf = (wf && anti) ? T(-1) : T(1);
+    const T gb = (wb && anti) ? T(-1) : T(1);
+    cx<T> u[9];
+    load_link<P>(p.U, p.V, MU, s, u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        cx<T> ps[12], h[6], g[6];
+        load_site<P>(p.in, p.V, p.nrhs, sf, r0 + r, ps);
+        project<MU, SF>(ps, h);
+        su3_mv(u, h, g);
+        accum<MU, SF>(acc[r], g, gf);
+    }
+    // with several right-hand sides per thread, keep the scheduler from
+    // hoisting every neighbour load of the site (it would spill)
+    if constexpr (R > 1)
+        __builtin_amdgcn_sched_barrier(0);
+    load_link<P>(p.U, p.V, MU, sb, u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        cx<T> ps[12], h[6], g[6];
+        load_site<P>(p.in, p.V, p.nrhs, sb, r0 + r, ps);
+        project<MU, -SF>(ps, h);
+        su3_adj_mv(u, h, g);
+        accum<MU, -SF>(acc[r], g, gb);
+    }
+    if constexpr (R > 1)
+        __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int P, int DAG, int R>
+__device__ __forceinline__ void hop_site(const StencilParams &p, uint32_t s, int r0,
+                                         cx<typename Traits<P>::real> (&acc)[R][12])
+{
+    const uint32_t q1 = fdiv(s, p.fx);
+    const int x = (int)(s - q1 * (uint32_t)p.L[0]);
+    const uint32_t q2 = fdiv(q1, p.fy);
+    const int y = (int)(q1 - q2 * (uint32_t)p.L[1]);
+    const uint32_t q3 = fdiv(q2, p.fz);
+    const int z = (int)(q2 - q3 * (uint32_t)p.L[2]);
+    const int t = (int)q3;
+    const uint32_t sy = (uint32_t)p.L[0], sz = sy * (uint32_t)p.L[1], st = sz * (uint32_t)p.L[2];
+    hop_dir<P, DAG, R, 0>(p, s, x, 1u, r0, acc);
+    hop_dir<P, DAG, R, 1>(p, s, y, sy, r0, acc);
+    hop_dir<P, DAG, R, 2>(p, s, z, sz, r0, acc);
+    hop_dir<P, DAG, R, 3>(p, s, t, st, r0, acc);
+}
+
+// Round a site to what the 16-bit format will store (so that fused
+// reductions see exactly the stored values).
+template <int P>
+__device__ __forceinline__ void round_site(cx<float> (&v)[12])
+{
+    if constexpr (Traits<P>::SCALED) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            cx<float> q = unpack2<P>(pack2<P>(v[k].re * inv, v[k].im * inv));
+            v[k] = cx<float>{q.re * m, q.im * m};
+        }
+    }
+}
+
+template <int P, int DAG, int R, int RED, int APPLY>
+__global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
+{
+    using T = typename Traits<P>::real;
+    constexpr int NV = RED == RED_NORM ? 1 : RED == RED_DOTV ? 2 : RED == RED_DOTIN_NORM ? 3 : 0;
+    __shared__ double lds[(NV > 0 ? NV : 1) * R * 8];
+    const uint32_t tile = tile_of(blockIdx.x, gridDim.x, p.xcd);
+    const uint32_t s = tile * blockDim.x + threadIdx.x;
+    const int r0 = blockIdx.y * R;
+    const bool active = s < p.V;
+    double red[(NV > 0 ? NV : 1) * R];
+#pragma unroll
+    for (int i = 0; i < (NV > 0 ? NV : 1) * R; ++i)
+        red[i] = 0.0;
+    if (active) {
+        cx<T> acc[R][12];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                acc[r][k] = cx<T>{T(0), T(0)};
+        hop_site<P, DAG, R>(p, s, r0, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        const T kap = (T)p.kappa;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cx<T> o[12];
+            if constexpr (APPLY || RED == RED_DOTIN_NORM) {
+                cx<T> in[12];
+                load_site<P>(p.in, p.V, p.nrhs, s, r0 + r, in);
+                if constexpr (APPLY) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        o[k] = acc[r][k];
+                }
+                if constexpr (Traits<P>::SCALED)
+                    round_site<P>(o);
+                if constexpr (RED == RED_DOTIN_NORM) {
+                    double re = 0.0, im = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        re = fma((double)in[k].re, (double)o[k].re, fma((double)in[k].im, (double)o[k].im, re));
+                        im = fma((double)in[k].re, (double)o[k].im, fma(-(double)in[k].im, (double)o[k].re, im));
+                    }
+                    red[NV * r + 0] = re;
+                    red[NV * r + 1] = im;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    o[k] = acc[r][k];
+                if constexpr (Traits<P>::SCALED)
+                    round_site<P>(o);
+            }
+            store_site<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
+            if constexpr (RED == RED_NORM || RED == RED_DOTIN_NORM) {
+                double n2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    n2 = fma((double)o[k].re, (double)o[k].re, fma((double)o[k].im, (double)o[k].im, n2));
+                red[NV * r + NV - 1] = n2;
+            }
+            if constexpr (RED == RED_DOTV) {
+                cx<T> v[12];
+                load_site<P>(p.aux, p.V, p.nrhs, s, r0 + r, v);
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    re = fma((double)v[k].re, (double)o[k].re, fma((double)v[k].im, (double)o[k].im, re));
+                    im = fma((double)v[k].re, (double)o[k].im, fma(-(double)v[k].im, (double)o[k].re, im));
+                }
+                red[NV * r + 0] = re;
+                red[NV * r + 1] = im;
+            }
+        }
+    }
+    if constexpr (NV > 0) {
+        block_sum<NV * R>(red, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < NV; ++k)
+                    p.partials[((size_t)k * p.nrhs + r0 + r) * p.nblk + blockIdx.x] = red[NV * r + k];
+        }
+    }
+}
+
+int stencil_nval(int red) { return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : 0; }
+
+template <int P, int DAG, int R>
+static hipError_t launch_t(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
+{
+    dim3 grid(p.nblk, p.nrhs / R), block(cfg.block);
+    if (!p.apply) {  // the hopping term alone is only offered without fused reductions
+        if (p.red != RED_NONE)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NONE, 0>), grid, block, 0, st, p);
+        return hipGetLastError();
+    }
+    switch (p.red) {
+    case RED_NONE: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NONE, 1>), grid, block, 0, st, p); break;
+    case RED_NORM: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NORM, 1>), grid, block, 0, st, p); break;
+    case RED_DOTV: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTV, 1>), grid, block, 0, st, p); break;
+    case RED_DOTIN_NORM:
+        hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTIN_NORM, 1>), grid, block, 0, st, p);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Right-hand sides per thread: FP64 keeps at most 2 (24 FP64 accumulators
+// per right-hand side; 3 or more spill at the 256-VGPR budget of a
+// 512-thread workgroup), the FP32-arithmetic formats up to 4.
+template <int P, int DAG>
+static hipError_t launch_r(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
+{
+    switch (cfg.rpt) {
+    case 1: return launch_t<P, DAG, 1>(cfg, p, st);
+    case 2: return launch_t<P, DAG, 2>(cfg, p, st);
+    case 3:
+        if constexpr (P != F64)
+            return launch_t<P, DAG, 3>(cfg, p, st);
+        return hipErrorInvalidValue;
+    case 4:
+        if constexpr (P != F64)
+            return launch_t<P, DAG, 4>(cfg, p, st);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int max_rpt(int prec) { return prec == F64 ? 2 : 4; }
+
+hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st)
+{
+    if (cfg.rpt < 1 || cfg.rpt > 4 || p.nrhs % cfg.rpt != 0 || cfg.block < 64 || cfg.block > 512 ||
+        cfg.block % 64 != 0)
+        return hipErrorInvalidValue;
+    p.nblk = (int)((p.V + cfg.block - 1) / cfg.block);
+    p.xcd = cfg.xcd;
+    switch (prec * 2 + (dagger ? 1 : 0)) {
+    case 0: return launch_r<F64, 0>(cfg, p, st);
+    case 1: return launch_r<F64, 1>(cfg, p, st);
+    case 2: return launch_r<F32, 0>(cfg, p, st);
+    case 3: return launch_r<F32, 1>(cfg, p, st);
+    case 4: return launch_r<BF16S, 0>(cfg, p, st);
+    case 5: return launch_r<BF16S, 1>(cfg, p, st);
+    case 6: return launch_r<F16S, 0>(cfg, p, st);
+    case 7: return launch_r<F16S, 1>(cfg, p, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------- multi-lattice
+// One persistent grid; each workgroup pops (lattice, site tile, RHS group)
+// work items from a device-wide counter until the queue is empty, so uneven
+// lattices share one launch.  Every workgroup leaves the loop once the
+// counter passes the total, so the grid always drains.
+template <int P, int DAG, int R>
+__global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, uint32_t total, unsigned *counter)
+{
+    using T = typename Traits<P>::real;
+    __shared__ unsigned tile_s;
+    for (;;) {
+        if (threadIdx.x == 0)
+            tile_s = atomicAdd(counter, 1u);
+        __syncthreads();
+        const unsigned t = tile_s;
+        __syncthreads();
+        if (t >= total)
+            break;
+        int i = 0;
+        while (i + 1 < n && E[i + 1].tile_begin <= t)
+            ++i;
+        const StencilParams p = E[i].p;
+        const uint32_t local = t - E[i].tile_begin;
+        const uint32_t lt = local % (uint32_t)p.nblk;
+        const int r0 = (int)(local / (uint32_t)p.nblk) * R;
+        const uint32_t s = lt * blockDim.x + threadIdx.x;
+        if (s < p.V) {
+            cx<T> acc[R][12];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    acc[r][k] = cx<T>{T(0), T(0)};
+            hop_site<P, DAG, R>(p, s, r0, acc);
+            const T kap = (T)p.kappa;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cx<T> in[12], o[12];
+                load_site<P>(p.in, p.V, p.nrhs, s, r0 + r, in);
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
+                store_site<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
+            }
+        }
+    }
+}
+
+template <int P, int DAG, int R>
+static int multi_grid_t(int block)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel<P, DAG, R>, block, 0) != hipSuccess)
+        per_cu = 1;
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    return (per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
+}
+
+template <int P, int DAG>
+static hipError_t launch_multi_r(int rpt, int block, const MultiEntry *E, int n, uint32_t total, unsigned *counter,
+                                 int grid, hipStream_t st)
+{
+    switch (rpt) {
+    case 1: hipLaunchKernelGGL((multi_kernel<P, DAG, 1>), dim3(grid), dim3(block), 0, st, E, n, total, counter); break;
+    case 2: hipLaunchKernelGGL((multi_kernel<P, DAG, 2>), dim3(grid), dim3(block), 0, st, E, n, total, counter); break;
+    case 4:
+        if constexpr (P != F64) {
+            hipLaunchKernelGGL((multi_kernel<P, DAG, 4>), dim3(grid), dim3(block), 0, st, E, n, total, counter);
+            break;
+        }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int P, int DAG>
+static int multi_grid_r(int rpt, int block)
+{
+    switch (rpt) {
+    case 1: return multi_grid_t<P, DAG, 1>(block);
+    case 2: return multi_grid_t<P, DAG, 2>(block);
+    case 4:
+        if constexpr (P != F64)
+            return multi_grid_t<P, DAG, 4>(block);
+        return 0;
+    default: return 0;
+    }
+}
+
+int multi_grid_size(int prec, int dagger, int rpt, int block)
+{
+    switch (prec * 2 + (dagger ? 1 : 0)) {
+    case 0: return multi_grid_r<F64, 0>(rpt, block);
+    case 1: return multi_grid_r<F64, 1>(rpt, block);
+    case 2: return multi_grid_r<F32, 0>(rpt, block);
+    case 3: return multi_grid_r<F32, 1>(rpt, block);
+    case 4: return multi_grid_r<BF16S, 0>(rpt, block);
+    case 5: return multi_grid_r<BF16S, 1>(rpt, block);
+    case 6: return multi_grid_r<F16S, 0>(rpt, block);
+    case 7: return multi_grid_r<F16S, 1>(rpt, block);
+    default: return 0;
+    }
+}
+
+hipError_t launch_multi(int prec, int dagger, int rpt, int block, const MultiEntry *E, int n, uint32_t total,
+                        unsigned *counter, int grid, hipStream_t st)
+{
+    switch (prec * 2 + (dagger ? 1 : 0)) {
+    case 0: return launch_multi_r<F64, 0>(rpt, block, E, n, total, counter, grid, st);
+    case 1: return launch_multi_r<F64, 1>(rpt, block, E, n, total, counter, grid, st);
+    case 2: return launch_multi_r<F32, 0>(rpt, block, E, n, total, counter, grid, st);
+    case 3: return launch_multi_r<F32, 1>(rpt, block, E, n, total, counter, grid, st);
+    case 4: return launch_multi_r<BF16S, 0>(rpt, block, E, n, total, counter, grid, st);
+    case 5: return launch_multi_r<BF16S, 1>(rpt, block, E, n, total, counter, grid, st);
+    case 6: return launch_multi_r<F16S, 0>(rpt, block, E, n, total, counter, grid, st);
+    case 7: return launch_multi_r<F16S, 1>(rpt, block, E, n, total, counter, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------- link force
+// For each link (x, mu): G = kappa s_mu(x) [ sum_spin ((1-g_mu) x(x+mu)) mu(x)^dag
+//                                           + sum_spin mu(x+mu) ((1+g_mu) x(x))^dag ],
+// the derivative of Re<mu, D x> style terms with respect to U_mu(x)
+// (dL = Re Tr[dU G]); written out as G^dag or as P = TH(i U G).
+template <int P, int MU>
+__device__ __forceinline__ void force_dir(const StencilParams &p, uint32_t s, int c, uint32_t stride,
+                                          double2 *out, int want_p)
+{
+    using T = typename Traits<P>::real;
+    const int L = p.L[MU];
+    const bool wf = (c == L - 1);
+    const uint32_t sf = wf ? s - (uint32_t)(L - 1) * stride : s + stride;
+    const double sg = (wf && p.bc[MU] < 0) ? -1.0 : 1.0;
+    cx<T> xf[12], xs[12], mf[12], ms[12];
+    load_site<P>(p.in, p.V, 1, sf, 0, xf);
+    load_site<P>(p.in, p.V, 1, s, 0, xs);
+    load_site<P>(p.aux, p.V, 1, sf, 0, mf);
+    load_site<P>(p.aux, p.V, 1, s, 0, ms);
+    // v = (1 - g) x(x+mu), w = (1 + g) x(x): projected then expanded to 4 spins
+    cx<T> h[6], v[12], w[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        v[k] = w[k] = cx<T>{T(0), T(0)};
+    project<MU, -1>(xf, h);
+    accum<MU, -1>(v, h, T(1));
+    project<MU, 1>(xs, h);
+    accum<MU, 1>(w, h, T(1));
+    cx<double> G[9];
+    const double kf = p.kappa * sg;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            cx<double> acc{0.0, 0.0};
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                const cx<double> va{(double)v[3 * sp + a].re, (double)v[3 * sp + a].im};
+                const cx<double> mb{(double)ms[3 * sp + b].re, (double)ms[3 * sp + b].im};
+                const cx<double> fa{(double)mf[3 * sp + a].re, (double)mf[3 * sp + a].im};
+                const cx<double> wb{(double)w[3 * sp + b].re, (double)w[3 * sp + b].im};
+                acc = cfma(va, cconj(mb), acc);
+                acc = cfma(fa, cconj(wb), acc);
+            }
+            G[3 * a + b] = cx<double>{kf * acc.re, kf * acc.im};
+        }
+    double2 *o = out + ((size_t)MU * p.V + s) * 9;
+    if (!want_p) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                o[3 * a + b] = make_double2(G[3 * b + a].re, -G[3 * b + a].im);
+        return;
+    }
+    cx<T> ut[9];
+    load_link<P>(p.U, p.V, MU, s, ut);
+    cx<double> A[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            cx<double> acc{0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                acc = cfma(cx<double>{(double)ut[3 * a + k].re, (double)ut[3 * a + k].im}, G[3 * k + b], acc);
+            A[3 * a + b] = cx<double>{-acc.im, acc.re};  // i U G
+        }
+    // P = (A + A^dag)/2 - Tr[(A + A^dag)/2]/3
+    const double tr = (A[0].re + A[4].re + A[8].re) / 3.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double re = 0.5 * (A[3 * a + b].re + A[3 * b + a].re);
+            double im = 0.5 * (A[3 * a + b].im - A[3 * b + a].im);
+            if (a == b)
+                re -= tr;
+            o[3 * a + b] = make_double2(re, im);
+        }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void force_kernel(StencilParams p, double2 *out, int want_p)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.V)
+        return;
+    const uint32_t q1 = fdiv(s, p.fx);
+    const int x = (int)(s - q1 * (uint32_t)p.L[0]);
+    const uint32_t q2 = fdiv(q1, p.fy);
+    const int y = (int)(q1 - q2 * (uint32_t)p.L[1]);
+    const uint32_t q3 = fdiv(q2, p.fz);
+    const int z = (int)(q2 - q3 * (uint32_t)p.L[2]);
+    const int t = (int)q3;
+    const uint32_t sy = (uint32_t)p.L[0], sz = sy * (uint32_t)p.L[1], st = sz * (uint32_t)p.L[2];
+    force_dir<P, 0>(p, s, x, 1u, out, want_p);
+    force_dir<P, 1>(p, s, y, sy, out, want_p);
+    force_dir<P, 2>(p, s, z, sz, out, want_p);
+    force_dir<P, 3>(p, s, t, st, out, want_p);
+}
+
+hipError_t launch_force(int prec, const wl_op *op, void *out, const void *x, const void *mu, int project,
+                        hipStream_t st)
+{
+    StencilParams p{};
+    p.U = op->U;
+    p.in = x;
+    p.aux = mu;
+    p.V = op->V;
+    p.nrhs = 1;
+    p.kappa = op->kappa;
+    for (int i = 0; i < 4; ++i) {
+        p.L[i] = op->g.dims[i];
+        p.bc[i] = op->g.bc[i];
+    }
+    p.fx = make_fastdiv((uint32_t)p.L[0]);
+    p.fy = make_fastdiv((uint32_t)p.L[1]);
+    p.fz = make_fastdiv((uint32_t)p.L[2]);
+    const int block = 256;
+    dim3 grid((p.V + block - 1) / block);
+    if (prec == F64)
+        hipLaunchKernelGGL((force_kernel<F64>), grid, dim3(block), 0, st, p, (double2 *)out, project);
+    else if (prec == F32)
+        hipLaunchKernelGGL((force_kernel<F32>), grid, dim3(block), 0, st, p, (double2 *)out, project);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace wl

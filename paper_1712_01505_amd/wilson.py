@@ -1,0 +1,395 @@
+"""ctypes binding of libwilson.so (the gfx950 Wilson-Dirac library).
+
+Each ``wl_*`` / ``wilson_*`` / ``solve_*`` function here has the name and the
+arguments of the C entry point in include/wilson.h and only marshals them:
+every step of the computation runs in the HIP library.  On top of those,
+``Operator``, ``apply``, ``dslash`` and ``solve`` take canonical complex128
+torch tensors on the GPU (spinor ``(..., Lt, Lz, Ly, Lx, 4, 3)``, gauge
+``(4, Lt, Lz, Ly, Lx, 3, 3)``) and use torch only for device memory and the
+current stream.
+
+The library must be built (``python -m paper_1712_01505_amd.build``); there is
+no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwilson.so")
+
+WL_OK, WL_NOT_CONVERGED, WL_BREAKDOWN, WL_STAGNATED = 0, 1, 2, 3
+WL_EINVAL, WL_EALIGN, WL_EPREC, WL_EHIP, WL_ENAN, WL_EWORKSPACE = -1, -2, -3, -4, -5, -6
+WL_F64, WL_F32, WL_BF16S, WL_F16S = 0, 1, 2, 3
+WL_SPINOR, WL_GAUGE = 0, 1
+WL_SOLVER_CGNR, WL_SOLVER_BICGSTAB = 0, 1
+
+PREC = {"f64": WL_F64, "f32": WL_F32, "bf16": WL_BF16S, "f16": WL_F16S}
+SOLVER = {"cgnr": WL_SOLVER_CGNR, "bicgstab": WL_SOLVER_BICGSTAB}
+
+# Symbols the header declares (checked by the CPU test suite).
+EXPORTS = [
+    "wl_field_bytes", "wl_pack_gauge", "wl_pack_spinor", "wl_unpack_spinor", "wl_convert_spinor",
+    "wl_op_create", "wl_op_destroy", "wilson_dslash", "wilson_apply", "wl_solver_workspace_bytes",
+    "solve_cgnr", "solve_bicgstab", "wilson_gauge_force", "wilson_multi_apply", "wl_autotune",
+    "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read",
+    "wl_strerror", "wl_last_hip_error",
+]
+
+
+class wl_geom(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("bc", ctypes.c_int32 * 4)]
+
+
+class wl_solve_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("reliable", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("use_x0", ctypes.c_int), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class wl_solve_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("stencil_calls", ctypes.c_int),
+                ("converged", ctypes.c_int), ("iter_rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class wl_multi_desc(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("out", ctypes.c_void_p), ("in_", ctypes.c_void_p)]
+
+
+class WilsonError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().wl_strerror(code).decode()
+        if code == WL_EHIP:
+            msg += f" (hipError {lib().wl_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{code}]")
+
+
+_lib = None
+
+
+def lib():
+    """Load libwilson.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libwilson.so not found at {LIB_PATH}: build it with "
+                           "`python -m paper_1712_01505_amd.build` (there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    G = ctypes.POINTER(wl_geom)
+    sig = {
+        "wl_field_bytes": [G, I, I, I, ctypes.POINTER(SZ)],
+        "wl_pack_gauge": [G, I, P, P, P],
+        "wl_pack_spinor": [G, I, I, P, P, P],
+        "wl_unpack_spinor": [G, I, I, P, P, P],
+        "wl_convert_spinor": [G, I, I, I, P, P, P],
+        "wl_op_create": [G, D, I, P, ctypes.POINTER(P)],
+        "wl_op_destroy": [P],
+        "wilson_dslash": [P, P, P, I, I, P],
+        "wilson_apply": [P, P, P, I, I, P],
+        "wl_solver_workspace_bytes": [P, P, I, I, ctypes.POINTER(SZ)],
+        "solve_cgnr": [P, P, P, P, I, ctypes.POINTER(wl_solve_params), ctypes.POINTER(wl_solve_stats), P],
+        "solve_bicgstab": [P, P, P, P, I, ctypes.POINTER(wl_solve_params), ctypes.POINTER(wl_solve_stats), P],
+        "wilson_gauge_force": [P, P, P, P, I, P],
+        "wilson_multi_apply": [ctypes.POINTER(wl_multi_desc), I, I, I, P],
+        "wl_autotune": [P, I, I, P],
+        "wl_get_launch": [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
+        "wl_set_launch": [P, I, I, I, I],
+        "wl_prof_enable": [I],
+        "wl_prof_reset": [],
+        "wl_prof_read": [I, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), ctypes.POINTER(D)],
+        "wl_strerror": [I],
+        "wl_last_hip_error": [],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "wl_strerror" else I
+    _lib = L
+    return L
+
+
+def _check(code, where, allow_positive=False):
+    if code < 0 or (code > 0 and not allow_positive):
+        raise WilsonError(code, where)
+    return code
+
+
+# ---------------------------------------------------------------- thin C-ABI mirrors
+def make_geom(dims, bc=(1, 1, 1, -1)) -> wl_geom:
+    g = wl_geom()
+    for i in range(4):
+        g.dims[i] = int(dims[i])
+        g.bc[i] = int(bc[i])
+    return g
+
+
+def wl_field_bytes(geom, kind, prec, nrhs=1) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().wl_field_bytes(ctypes.byref(geom), kind, prec, nrhs, ctypes.byref(out)), "wl_field_bytes")
+    return out.value
+
+
+def wl_pack_gauge(geom, prec, U_canon, U_packed, stream):
+    return _check(lib().wl_pack_gauge(ctypes.byref(geom), prec, U_canon, U_packed, stream), "wl_pack_gauge")
+
+
+def wl_pack_spinor(geom, prec, nrhs, psi_canon, psi_packed, stream):
+    return _check(lib().wl_pack_spinor(ctypes.byref(geom), prec, nrhs, psi_canon, psi_packed, stream),
+                  "wl_pack_spinor")
+
+
+def wl_unpack_spinor(geom, prec, nrhs, psi_packed, psi_canon, stream):
+    return _check(lib().wl_unpack_spinor(ctypes.byref(geom), prec, nrhs, psi_packed, psi_canon, stream),
+                  "wl_unpack_spinor")
+
+
+def wl_convert_spinor(geom, prec_in, prec_out, nrhs, src, dst, stream):
+    return _check(lib().wl_convert_spinor(ctypes.byref(geom), prec_in, prec_out, nrhs, src, dst, stream),
+                  "wl_convert_spinor")
+
+
+def wl_op_create(geom, kappa, prec, U_packed) -> int:
+    h = ctypes.c_void_p(0)
+    _check(lib().wl_op_create(ctypes.byref(geom), float(kappa), prec, U_packed, ctypes.byref(h)), "wl_op_create")
+    return h.value
+
+
+def wl_op_destroy(op):
+    return _check(lib().wl_op_destroy(op), "wl_op_destroy")
+
+
+def wilson_dslash(op, out, inp, dagger, nrhs, stream):
+    return _check(lib().wilson_dslash(op, out, inp, int(dagger), nrhs, stream), "wilson_dslash")
+
+
+def wilson_apply(op, out, inp, dagger, nrhs, stream):
+    return _check(lib().wilson_apply(op, out, inp, int(dagger), nrhs, stream), "wilson_apply")
+
+
+def wl_solver_workspace_bytes(hi, lo, solver, nrhs) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().wl_solver_workspace_bytes(hi, lo, solver, nrhs, ctypes.byref(out)), "wl_solver_workspace_bytes")
+    return out.value
+
+
+def solve_cgnr(hi, lo, x, b, nrhs, params, stats, stream):
+    return _check(lib().solve_cgnr(hi, lo, x, b, nrhs, ctypes.byref(params), stats, stream), "solve_cgnr",
+                  allow_positive=True)
+
+
+def solve_bicgstab(hi, lo, x, b, nrhs, params, stats, stream):
+    return _check(lib().solve_bicgstab(hi, lo, x, b, nrhs, ctypes.byref(params), stats, stream), "solve_bicgstab",
+                  allow_positive=True)
+
+
+def wilson_gauge_force(op, out_canon, x, mu, project, stream):
+    return _check(lib().wilson_gauge_force(op, out_canon, x, mu, int(project), stream), "wilson_gauge_force")
+
+
+def wilson_multi_apply(descs, dagger, nrhs, stream):
+    arr = (wl_multi_desc * len(descs))(*[wl_multi_desc(o, out, inp) for o, out, inp in descs])
+    return _check(lib().wilson_multi_apply(arr, len(descs), int(dagger), nrhs, stream), "wilson_multi_apply")
+
+
+def wl_autotune(op, nrhs, dagger, stream):
+    return _check(lib().wl_autotune(op, nrhs, int(dagger), stream), "wl_autotune")
+
+
+def wl_get_launch(op, nrhs):
+    b, r, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().wl_get_launch(op, nrhs, ctypes.byref(b), ctypes.byref(r), ctypes.byref(x)), "wl_get_launch")
+    return b.value, r.value, x.value
+
+
+def wl_set_launch(op, nrhs, block, rpt, xcd):
+    return _check(lib().wl_set_launch(op, nrhs, block, rpt, xcd), "wl_set_launch")
+
+
+def wl_prof_enable(on):
+    return _check(lib().wl_prof_enable(int(on)), "wl_prof_enable")
+
+
+def wl_prof_reset():
+    return _check(lib().wl_prof_reset(), "wl_prof_reset")
+
+
+def wl_prof_read(prec):
+    n, ms, sites = ctypes.c_long(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().wl_prof_read(prec, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(sites)), "wl_prof_read")
+    return n.value, ms.value, sites.value
+
+
+# ---------------------------------------------------------------- torch conveniences
+def _torch():
+    import torch  # noqa: WPS433
+    return torch
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def dims_of_spinor(psi):
+    Lt, Lz, Ly, Lx = psi.shape[-6:-2]
+    return (Lx, Ly, Lz, Lt)
+
+
+def _nrhs_of(psi):
+    return 1 if psi.dim() == 6 else int(psi.shape[0])
+
+
+def alloc_field(geom, kind, prec, nrhs=1, device="cuda"):
+    torch = _torch()
+    n = wl_field_bytes(geom, kind, prec, nrhs)
+    return torch.empty(max(n, 16), dtype=torch.uint8, device=device)
+
+
+def pack_spinor(psi, prec=WL_F64, bc=(1, 1, 1, -1)):
+    """Canonical complex128 spinor(s) on the GPU -> packed uint8 tensor."""
+    torch = _torch()
+    if psi.dtype != torch.complex128 or not psi.is_cuda:
+        raise TypeError("pack_spinor expects a complex128 CUDA tensor")
+    psi = psi.contiguous()
+    geom = make_geom(dims_of_spinor(psi), bc)
+    nrhs = _nrhs_of(psi)
+    out = alloc_field(geom, WL_SPINOR, prec, nrhs, psi.device)
+    wl_pack_spinor(geom, prec, nrhs, _ptr(psi), _ptr(out), _stream())
+    return out
+
+
+def unpack_spinor(packed, dims, prec=WL_F64, nrhs=None, bc=(1, 1, 1, -1)):
+    torch = _torch()
+    geom = make_geom(dims, bc)
+    Lx, Ly, Lz, Lt = dims
+    shape = (Lt, Lz, Ly, Lx, 4, 3) if nrhs is None else (nrhs, Lt, Lz, Ly, Lx, 4, 3)
+    out = torch.empty(shape, dtype=torch.complex128, device=packed.device)
+    wl_unpack_spinor(geom, prec, 1 if nrhs is None else nrhs, _ptr(packed), _ptr(out), _stream())
+    return out
+
+
+@dataclass
+class Operator:
+    """D = 1 - kappa H on packed links of one precision (owns the packed links)."""
+
+    dims: tuple
+    kappa: float
+    prec: int
+    bc: tuple
+    U_packed: object
+    handle: int
+
+    @classmethod
+    def create(cls, U, kappa, prec=WL_F64, bc=(1, 1, 1, -1)):
+        torch = _torch()
+        if U.dtype != torch.complex128 or not U.is_cuda:
+            raise TypeError("Operator.create expects a complex128 CUDA gauge tensor")
+        U = U.contiguous()
+        Lt, Lz, Ly, Lx = U.shape[1:5]
+        dims = (Lx, Ly, Lz, Lt)
+        geom = make_geom(dims, bc)
+        Up = alloc_field(geom, WL_GAUGE, prec, 1, U.device)
+        wl_pack_gauge(geom, prec, _ptr(U), _ptr(Up), _stream())
+        h = wl_op_create(geom, kappa, prec, _ptr(Up))
+        return cls(dims, float(kappa), prec, tuple(bc), Up, h)
+
+    @property
+    def geom(self):
+        return make_geom(self.dims, self.bc)
+
+    def close(self):
+        if self.handle:
+            wl_op_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 -- interpreter shutdown
+            pass
+
+    def pack(self, psi):
+        return pack_spinor(psi, self.prec, self.bc)
+
+    def unpack(self, packed, nrhs=None):
+        return unpack_spinor(packed, self.dims, self.prec, nrhs, self.bc)
+
+    def new_field(self, nrhs=1):
+        return alloc_field(self.geom, WL_SPINOR, self.prec, nrhs, self.U_packed.device)
+
+    def apply_packed(self, out, inp, nrhs=1, dagger=False):
+        wilson_apply(self.handle, _ptr(out), _ptr(inp), dagger, nrhs, _stream())
+
+    def dslash_packed(self, out, inp, nrhs=1, dagger=False):
+        wilson_dslash(self.handle, _ptr(out), _ptr(inp), dagger, nrhs, _stream())
+
+
+def apply(U, psi, kappa, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None):
+    """D psi (or D^dag psi) for canonical complex128 CUDA tensors."""
+    p = PREC[prec] if isinstance(prec, str) else prec
+    op = op or Operator.create(U, kappa, p, bc)
+    nrhs = None if psi.dim() == 6 else int(psi.shape[0])
+    src = op.pack(psi)
+    dst = op.new_field(nrhs or 1)
+    op.apply_packed(dst, src, nrhs or 1, dagger)
+    return op.unpack(dst, nrhs)
+
+
+def dslash(U, psi, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None):
+    """H psi (the hopping term) for canonical complex128 CUDA tensors."""
+    p = PREC[prec] if isinstance(prec, str) else prec
+    op = op or Operator.create(U, 0.0, p, bc)
+    nrhs = None if psi.dim() == 6 else int(psi.shape[0])
+    src = op.pack(psi)
+    dst = op.new_field(nrhs or 1)
+    op.dslash_packed(dst, src, nrhs or 1, dagger)
+    return op.unpack(dst, nrhs)
+
+
+def solve(U, b, kappa, method="bicgstab", precision="f64", tol=1e-10, maxiter=10000, bc=(1, 1, 1, -1),
+          inner_tol=0.0, check_every=0, x0=None, ops=None, return_stats=False):
+    """x = D^{-1} b for canonical complex128 CUDA tensors.
+
+    precision: "f64" (plain FP64), "f32" (plain FP32), or "mixed-f32", "mixed-bf16",
+    "mixed-f16" (FP64 refinement around an inner solve with that storage)."""
+    torch = _torch()
+    nrhs = None if b.dim() == 6 else int(b.shape[0])
+    n = nrhs or 1
+    if precision.startswith("mixed-"):
+        lo_prec = PREC[precision.split("-", 1)[1]]
+        hi = ops[0] if ops else Operator.create(U, kappa, WL_F64, bc)
+        lo = ops[1] if ops else Operator.create(U, kappa, lo_prec, bc)
+    else:
+        hi = ops[0] if ops else Operator.create(U, kappa, PREC[precision], bc)
+        lo = None
+    bp = hi.pack(b)
+    xp = hi.pack(x0) if x0 is not None else hi.new_field(n)
+    prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=0,
+                          check_every=check_every, use_x0=1 if x0 is not None else 0, workspace=None,
+                          workspace_bytes=0)
+    ws = wl_solver_workspace_bytes(hi.handle, lo.handle if lo else None, SOLVER[method], n)
+    work = torch.empty(ws, dtype=torch.uint8, device=b.device)
+    prm.workspace = work.data_ptr()
+    prm.workspace_bytes = ws
+    stats = (wl_solve_stats * n)()
+    fn = solve_cgnr if method == "cgnr" else solve_bicgstab
+    code = fn(hi.handle, lo.handle if lo else None, _ptr(xp), _ptr(bp), n, prm, stats, _stream())
+    x = hi.unpack(xp, nrhs)
+    st = [s.as_dict() for s in stats]
+    for s in st:
+        s["status"] = code
+    if return_stats:
+        return x, (st[0] if nrhs is None else st)
+    return x

@@ -1,0 +1,133 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/wilson.h declares, and validates arguments before any
+launch; the header compiles as C; the fast integer division used for site
+coordinates is exact."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_1712_01505_amd import wilson
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wilson.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|char\s*\*|const char\s*\*)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_binding_exports():
+    assert sorted(wilson.EXPORTS) == header_functions()
+
+
+def test_library_exports_every_declared_symbol():
+    L = wilson.lib()
+    missing = [n for n in header_functions() if not hasattr(L, n)]
+    assert not missing
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc missing")
+def test_header_compiles_as_c(tmp_path):
+    c = tmp_path / "t.c"
+    c.write_text('#include "wilson.h"\nint main(void){ wl_geom g; (void)g; return WL_OK; }\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), "-c", str(c),
+                    "-o", str(tmp_path / "t.o")], check=True)
+
+
+def test_field_bytes():
+    g = wilson.make_geom((4, 4, 4, 8))
+    V = 512
+    assert wilson.wl_field_bytes(g, wilson.WL_SPINOR, wilson.WL_F64, 3) == 3 * V * 192
+    assert wilson.wl_field_bytes(g, wilson.WL_SPINOR, wilson.WL_F32, 1) == V * 96
+    assert wilson.wl_field_bytes(g, wilson.WL_SPINOR, wilson.WL_BF16S, 2) == 2 * V * 52
+    assert wilson.wl_field_bytes(g, wilson.WL_GAUGE, wilson.WL_F64) == 4 * V * 96
+    assert wilson.wl_field_bytes(g, wilson.WL_GAUGE, wilson.WL_F16S) == 4 * V * 24
+
+
+@pytest.mark.parametrize("dims,bc", [((1, 4, 4, 4), (1, 1, 1, -1)), ((4, 4, 4, 0), (1, 1, 1, -1)),
+                                     ((4, 4, 4, 4), (1, 1, 2, -1)), ((65536, 65536, 2, 2), (1, 1, 1, 1))])
+def test_bad_geometry_rejected(dims, bc):
+    L = wilson.lib()
+    out = ctypes.c_size_t(0)
+    assert L.wl_field_bytes(ctypes.byref(wilson.make_geom(dims, bc)), 0, 0, 1, ctypes.byref(out)) == wilson.WL_EINVAL
+    h = ctypes.c_void_p()
+    assert L.wl_op_create(ctypes.byref(wilson.make_geom(dims, bc)), 0.1, 0, 256, ctypes.byref(h)) == wilson.WL_EINVAL
+
+
+def test_bad_arguments_rejected_before_launch():
+    L = wilson.lib()
+    g = wilson.make_geom((4, 4, 4, 4))
+    out = ctypes.c_size_t(0)
+    assert L.wl_field_bytes(ctypes.byref(g), 0, 7, 1, ctypes.byref(out)) == wilson.WL_EPREC
+    assert L.wl_field_bytes(ctypes.byref(g), 0, 0, 0, ctypes.byref(out)) == wilson.WL_EINVAL
+    assert L.wl_pack_spinor(ctypes.byref(g), 0, 1, 24, 256, None) == wilson.WL_EALIGN
+    assert L.wl_pack_spinor(ctypes.byref(g), 0, 1, None, 256, None) == wilson.WL_EINVAL
+    h = ctypes.c_void_p()
+    assert L.wl_op_create(ctypes.byref(g), float("nan"), 0, 256, ctypes.byref(h)) == wilson.WL_EINVAL
+    assert L.wl_op_create(ctypes.byref(g), 0.12, 0, 8, ctypes.byref(h)) == wilson.WL_EALIGN
+    assert L.wl_op_create(ctypes.byref(g), 0.12, 0, 256, ctypes.byref(h)) == wilson.WL_OK
+    op = h.value
+    try:
+        assert L.wilson_apply(op, 512, 512, 0, 1, None) == wilson.WL_EINVAL  # in == out
+        assert L.wilson_apply(op, 512, 1024, 2, 1, None) == wilson.WL_EINVAL  # dagger flag
+        assert L.wilson_apply(op, 512, 1024, 0, 0, None) == wilson.WL_EINVAL  # nrhs
+        assert L.wilson_apply(op, 520, 1024, 0, 1, None) == wilson.WL_EALIGN
+        assert L.wl_set_launch(op, 1, 96, 1, 1) == wilson.WL_EINVAL
+        assert L.wl_set_launch(op, 4, 256, 3, 1) == wilson.WL_EINVAL  # 3 does not divide 4
+        assert L.wl_set_launch(op, 4, 256, 4, 1) == wilson.WL_EINVAL  # FP64 offers at most 2
+        assert L.wl_set_launch(op, 4, 256, 2, 0) == wilson.WL_OK
+        prm = wilson.wl_solve_params(tol=0.0, maxiter=10)
+        assert L.solve_cgnr(op, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
+        prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
+        assert L.solve_cgnr(op, op, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EPREC
+        assert L.solve_cgnr(op, None, 512, 1024, 65, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
+        assert L.wilson_gauge_force(op, 512, 1024, 2048, 3, None) == wilson.WL_EINVAL
+    finally:
+        L.wl_op_destroy(op)
+    for c in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):
+        assert L.wl_strerror(c).decode() != "unknown error"
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ missing")
+def test_fastdiv_is_exact(tmp_path):
+    """The magic-number division used to decode site coordinates (host copy of
+    the same header routine, evaluated with 64-bit arithmetic) is exact."""
+    src = tmp_path / "fd.cpp"
+    src.write_text(r'''
+#include <cstdint>
+#include <cstdio>
+#define __device__
+#define __forceinline__ inline
+static inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
+''' + "".join(_fastdiv_source()) + r'''
+int main() {
+  const uint32_t ds[] = {1,2,3,4,5,6,7,8,12,16,20,24,32,48,64,96,100,1000,4096,13824,32768,65535,100000,1u<<20};
+  for (uint32_t d : ds) {
+    wl::FastDiv f = wl::make_fastdiv(d);
+    for (uint64_t n = 0; n < 200000; ++n) if (wl::fdiv((uint32_t)n, f) != n / d) { printf("bad %u %llu\n", d, (unsigned long long)n); return 1; }
+    for (uint64_t n = 0x7fffffffull - 200000; n <= 0x7fffffffull; ++n) if (wl::fdiv((uint32_t)n, f) != n / d) { printf("bad %u %llu\n", d, (unsigned long long)n); return 1; }
+    for (uint64_t k = 1; k * d < 0x7fffffffull && k < 100000; k += 7) {
+      uint64_t n = k * d; if (wl::fdiv((uint32_t)n, f) != k || wl::fdiv((uint32_t)(n - 1), f) != k - 1) { printf("bad %u\n", d); return 1; }
+    }
+  }
+  puts("ok"); return 0;
+}
+''')
+    exe = tmp_path / "fd"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-o", str(exe), str(src)], check=True)
+    assert subprocess.run([str(exe)], capture_output=True, text=True).stdout.strip() == "ok"
+
+
+def _fastdiv_source():
+    """Extract the FastDiv struct and its two functions from wl_common.h."""
+    text = open(os.path.join(ROOT, "paper_1712_01505_amd", "csrc", "wl_common.h")).read()
+    start = text.index("struct FastDiv {")
+    end = text.index("// ---------------------------------------------------------------- tile order")
+    return ["namespace wl {\n", text[start:end], "}\n"]
