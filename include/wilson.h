@@ -189,11 +189,15 @@ int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void
 int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
 
 /* Launch configuration currently used for (op, nrhs): block size, RHS per
- * thread, XCD-aware tile order flag. */
-int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rhs_per_thread, int *xcd_remap);
-/* Force a launch configuration (block in {64,128,256,512}; rhs_per_thread in
- * 1..4 dividing nrhs; xcd_remap 0/1).  Used by tests and the autotuner. */
-int wl_set_launch(wl_op *op, int nrhs, int block, int rhs_per_thread, int xcd_remap);
+ * thread, XCD-aware tile order flag, stencil code variant. */
+int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rhs_per_thread, int *xcd_remap, int *variant);
+/* Force a launch configuration: block in {64,...,512} (multiple of 64);
+ * rhs_per_thread dividing nrhs, at most 2 for WL_F64 and 4 otherwise;
+ * xcd_remap 0/1; variant 0 (straight-line hops) or, with rhs_per_thread = 1,
+ * a software-pipelined hop loop: 1 (all precisions), 2 (not WL_F64),
+ * 3 (16-bit formats only).  Results do not depend on the configuration.
+ * Used by tests and the autotuner. */
+int wl_set_launch(wl_op *op, int nrhs, int block, int rhs_per_thread, int xcd_remap, int variant);
 
 /* Stencil timing: when enabled, every stencil launch is bracketed by HIP
  * events on its stream; wl_prof_read synchronises and returns, for stencil

@@ -137,7 +137,7 @@ static std::string tune_key(const wl_op *op, int nrhs, int dagger)
     return buf;
 }
 
-// Cache file: one line per entry, "key block rpt xcd".
+// Cache file: one line per entry, "key block rpt xcd variant".
 static void load_tune_cache_locked()
 {
     if (g_tune_loaded)
@@ -152,7 +152,7 @@ static void load_tune_cache_locked()
         std::istringstream is(line);
         std::string key;
         LaunchCfg c;
-        if (is >> key >> c.block >> c.rpt >> c.xcd)
+        if (is >> key >> c.block >> c.rpt >> c.xcd >> c.var)
             g_tune[key] = c;
     }
 }
@@ -164,14 +164,26 @@ static void save_tune_cache_locked()
         return;
     std::ofstream f(path, std::ios::trunc);
     for (auto &kv : g_tune)
-        f << kv.first << " " << kv.second.block << " " << kv.second.rpt << " " << kv.second.xcd << "\n";
+        f << kv.first << " " << kv.second.block << " " << kv.second.rpt << " " << kv.second.xcd << " "
+          << kv.second.var << "\n";
 }
 
+// Untuned defaults (measured on MI355X at 32^3 x 64): one right-hand side
+// runs the pipelined hop loop with small workgroups; several right-hand
+// sides share each link load across RHS_per_thread spinors.
 static LaunchCfg default_launch(int prec, int nrhs)
 {
     LaunchCfg c;
+    if (nrhs == 1) {
+        c.rpt = 1;
+        c.block = prec == WL_F64 || prec == WL_F32 ? 64 : 128;
+        c.xcd = prec == WL_F64 || prec == WL_F32 ? 0 : 1;
+        c.var = prec == WL_F64 ? 1 : 2;
+        return c;
+    }
     c.block = 256;
     c.xcd = 1;
+    c.var = 0;
     c.rpt = 1;
     if (prec != WL_F64) {
         if (nrhs % 4 == 0)
@@ -350,8 +362,10 @@ static int stencil_call(const wl_op *op, void *out, const void *in, int dagger, 
     if (!al16(out) || !al16(in))
         return WL_EALIGN;
     LaunchCfg cfg = launch_for(op, nrhs);
-    if (nrhs % cfg.rpt != 0)
+    if (nrhs % cfg.rpt != 0) {
         cfg.rpt = 1;
+        cfg.var = 0;
+    }
     StencilParams p = base_params(op, out, in, nrhs, apply);
     CHECK_HIP(prof_stencil(op->prec, op, dagger, cfg, p, (hipStream_t)stream));
     return WL_OK;
@@ -473,24 +487,34 @@ int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void
     return WL_OK;
 }
 
-int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rpt, int *xcd)
+int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rpt, int *xcd, int *variant)
 {
-    if (!op || nrhs < 1 || !block || !rpt || !xcd)
+    if (!op || nrhs < 1 || !block || !rpt || !xcd || !variant)
         return WL_EINVAL;
     LaunchCfg c = launch_for(op, nrhs);
     *block = c.block;
     *rpt = c.rpt;
     *xcd = c.xcd;
+    *variant = c.var;
     return WL_OK;
 }
 
-int wl_set_launch(wl_op *op, int nrhs, int block, int rpt, int xcd)
+static bool launch_ok(int prec, int nrhs, const LaunchCfg &c)
 {
-    if (!op || nrhs < 1 || block < 64 || block > 512 || block % 64 || rpt < 1 || rpt > max_rpt(op->prec) ||
-        nrhs % rpt || (xcd != 0 && xcd != 1))
+    return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
+           nrhs % c.rpt == 0 && (c.xcd == 0 || c.xcd == 1) && c.var >= 0 && c.var <= max_var(prec) &&
+           (c.var == 0 || c.rpt == 1);
+}
+
+int wl_set_launch(wl_op *op, int nrhs, int block, int rpt, int xcd, int variant)
+{
+    if (!op || nrhs < 1)
+        return WL_EINVAL;
+    const LaunchCfg c{block, rpt, xcd, variant};
+    if (!launch_ok(op->prec, nrhs, c))
         return WL_EINVAL;
     std::lock_guard<std::mutex> lk(op->mu);
-    op->launch[nrhs] = LaunchCfg{block, rpt, xcd};
+    op->launch[nrhs] = c;
     return WL_OK;
 }
 
@@ -515,33 +539,37 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     LaunchCfg best = default_launch(op->prec, nrhs);
     float best_ms = INFINITY;
     const int blocks[] = {64, 128, 256, 512};
-    for (int bi = 0; bi < 4 && e == hipSuccess; ++bi)
-        for (int rpt = 1; rpt <= max_rpt(op->prec) && e == hipSuccess; ++rpt) {
-            if (nrhs % rpt)
-                continue;
-            for (int xcd = 0; xcd <= 1 && e == hipSuccess; ++xcd) {
-                LaunchCfg c{blocks[bi], rpt, xcd};
-                StencilParams p = base_params(op, out, in, nrhs, 1);
-                for (int w = 0; w < 2 && e == hipSuccess; ++w)
-                    e = launch_stencil(op->prec, dagger, c, p, st);
-                const int reps = 10;
-                if (e == hipSuccess)
-                    e = hipEventRecord(a, st);
-                for (int k = 0; k < reps && e == hipSuccess; ++k)
-                    e = launch_stencil(op->prec, dagger, c, p, st);
-                if (e == hipSuccess)
-                    e = hipEventRecord(b, st);
-                if (e == hipSuccess)
-                    e = hipEventSynchronize(b);
-                float ms = 0.f;
-                if (e == hipSuccess)
-                    e = hipEventElapsedTime(&ms, a, b);
-                if (e == hipSuccess && ms < best_ms) {
-                    best_ms = ms;
-                    best = c;
+    std::vector<LaunchCfg> cands;
+    for (int bi = 0; bi < 4; ++bi)
+        for (int rpt = 1; rpt <= max_rpt(op->prec); ++rpt)
+            for (int xcd = 0; xcd <= 1; ++xcd)
+                for (int var = 0; var <= max_var(op->prec); ++var) {
+                    const LaunchCfg c{blocks[bi], rpt, xcd, var};
+                    if (launch_ok(op->prec, nrhs, c))
+                        cands.push_back(c);
                 }
-            }
+    for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
+        const LaunchCfg c = cands[ci];
+        StencilParams p = base_params(op, out, in, nrhs, 1);
+        for (int w = 0; w < 2 && e == hipSuccess; ++w)
+            e = launch_stencil(op->prec, dagger, c, p, st);
+        const int reps = 10;
+        if (e == hipSuccess)
+            e = hipEventRecord(a, st);
+        for (int k = 0; k < reps && e == hipSuccess; ++k)
+            e = launch_stencil(op->prec, dagger, c, p, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(b, st);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = c;
         }
+    }
     if (a)
         (void)hipEventDestroy(a);
     if (b)

@@ -245,48 +245,67 @@ hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e,
 }
 
 // ---------------------------------------------------------------- finalize
-constexpr int FIN_THREADS = 256;
+// One workgroup sums every (value, right-hand side) row of the partial
+// arrays in a fixed order and then runs the scalar recurrence per column.
+// Rows are summed G at a time; each thread keeps 8 independent loads in
+// flight per row, so a pass costs about one memory latency.
+constexpr int FIN_THREADS = 512;
 constexpr int FIN_MAX = 3 * 64;  // values x right-hand sides per partial set
-
-// Sum partials[(v * nrhs + r) * nblk + b] over b in a fixed order.
-__device__ double fixed_sum(const double *part, int nblk, double *lds)
-{
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += FIN_THREADS)
-        a += part[b];
-    double v[1] = {a};
-    block_sum<1>(v, lds);
-    __shared__ double out;
-    if (threadIdx.x == 0)
-        out = v[0];
-    __syncthreads();
-    const double res = out;
-    __syncthreads();
-    return res;
-}
+constexpr int FIN_G = 4;
 
 __device__ __forceinline__ bool finite2(double a) { return isfinite(a); }
 
+struct RowRef {
+    const double *p;
+    int n;
+};
+
+__device__ __forceinline__ RowRef fin_row(const FinParams &p, int c)
+{
+    const int na = p.nvalA * p.nrhs, nb = p.nvalB * p.nrhs;
+    if (c < na)
+        return RowRef{p.A + (size_t)c * p.nblkA, p.nblkA};
+    c -= na;
+    if (c < nb)
+        return RowRef{p.B + (size_t)c * p.nblkB, p.nblkB};
+    c -= nb;
+    return RowRef{p.C + (size_t)c * p.nblkC, p.nblkC};
+}
+
 __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int op)
 {
-    __shared__ double lds[FIN_THREADS / 64];
-    __shared__ double sA[FIN_MAX], sB[FIN_MAX], sC[FIN_MAX];
+    __shared__ double lds[FIN_G * FIN_THREADS / 64];
+    __shared__ double sums[3 * FIN_MAX];
     const int nr = p.nrhs;
-    for (int i = 0; i < p.nvalA * nr; ++i) {
-        const double v = fixed_sum(p.A + (size_t)i * p.nblkA, p.nblkA, lds);
-        if (threadIdx.x == 0)
-            sA[i] = v;
+    const int na = p.nvalA * nr, nb = p.nvalB * nr, ncomb = na + nb + p.nvalC * nr;
+    for (int c0 = 0; c0 < ncomb; c0 += FIN_G) {
+        double v[FIN_G];
+#pragma unroll
+        for (int g = 0; g < FIN_G; ++g) {
+            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (c0 + g < ncomb) {
+                const RowRef row = fin_row(p, c0 + g);
+                for (int base = 0; base < row.n; base += 8 * FIN_THREADS) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int i = base + j * FIN_THREADS + threadIdx.x;
+                        if (i < row.n)
+                            a[j] += row.p[i];
+                    }
+                }
+            }
+            v[g] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        }
+        block_sum<FIN_G>(v, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int g = 0; g < FIN_G; ++g)
+                if (c0 + g < ncomb)
+                    sums[c0 + g] = v[g];
+        }
+        __syncthreads();
     }
-    for (int i = 0; i < p.nvalB * nr; ++i) {
-        const double v = fixed_sum(p.B + (size_t)i * p.nblkB, p.nblkB, lds);
-        if (threadIdx.x == 0)
-            sB[i] = v;
-    }
-    for (int i = 0; i < p.nvalC * nr; ++i) {
-        const double v = fixed_sum(p.C + (size_t)i * p.nblkC, p.nblkC, lds);
-        if (threadIdx.x == 0)
-            sC[i] = v;
-    }
+    const double *sA = sums, *sB = sums + na, *sC = sums + na + nb;
     __syncthreads();
     const int r = threadIdx.x;
     if (r >= nr)
@@ -430,6 +449,10 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
     default: break;
     }
     p.sc[r] = sc;
+    if (p.hflag) {  // mirror the status into host-visible memory for polling
+        p.hrr[r] = sc.rr;
+        p.hflag[r] = sc.flag;
+    }
 }
 
 hipError_t launch_finalize(int op, const FinParams &p, hipStream_t st)

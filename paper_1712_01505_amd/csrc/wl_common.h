@@ -46,8 +46,13 @@ __device__ __forceinline__ cx<T> cjfma(cx<T> a, cx<T> b, cx<T> c)
     c.im = fma(-a.im, b.re, c.im);
     return c;
 }
+// a*b with explicit fused operations (the library is built with
+// -ffp-contract=off so that every kernel variant rounds identically)
 template <typename T>
-__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) { return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return cx<T>{fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
+}
 template <typename T>
 __device__ __forceinline__ cx<T> cconj(cx<T> a) { return cx<T>{a.re, -a.im}; }
 // s*a + c (real s)

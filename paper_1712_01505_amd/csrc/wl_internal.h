@@ -20,6 +20,7 @@ struct LaunchCfg {
     int block = 256;  // threads per workgroup (= sites per tile)
     int rpt = 1;      // right-hand sides per thread
     int xcd = 1;      // XCD-aware tile order
+    int var = 0;      // stencil code variant (0 = straight-line hops; 1..3 = pipelined, R = 1 only)
 };
 
 }  // namespace wl
@@ -66,6 +67,7 @@ struct StencilParams {
 hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st);
 int stencil_nval(int red);
 int max_rpt(int prec);  // largest right-hand sides per thread the stencil offers
+int max_var(int prec);  // largest stencil code variant for R = 1
 
 struct MultiEntry {
     StencilParams p;
@@ -148,6 +150,8 @@ struct FinParams {
     int nvalA, nvalB, nvalC;
     Scalars *sc;
     double *out;      // F_SUM destination [nval][nrhs]
+    int *hflag;       // optional host-visible copy of flag[nrhs] ...
+    double *hrr;      // ... and rr[nrhs] (device pointers to mapped host memory)
     int nrhs;
     int iter;
     double tol2;

@@ -5,14 +5,17 @@
 //
 // Every vector operation is a kernel on the caller's stream; the scalar
 // recurrences live on the device (wl_blas.hip), so an iteration issues only
-// kernel launches and the host polls the per-right-hand-side status every
-// `check_every` iterations.  All right-hand sides run together; a converged
+// kernel launches; the finalize kernels mirror each column's status into
+// host-visible memory, and the host checks it behind a lookahead of
+// `check_every` queued iterations (HIP events, no copies, no stream drain
+// while iterating).  All right-hand sides run together; a converged
 // or broken-down column is frozen by zeroing its coefficients on the device.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "wl_internal.h"
@@ -68,22 +71,81 @@ size_t engine_bytes(int solver, int prec, uint32_t V, int nrhs)
         }                                                                                                      \
     } while (0)
 
+// Host-side buffers of one solve, kept in a pool: pinned copies of the
+// per-RHS scalars, host-visible (coherent, mapped) status written by the
+// finalize kernels, and lookahead events.
+constexpr int MAX_RHS = 64;
+constexpr int MAX_LOOK = 8;
+struct HostBufs {
+    Scalars *sc = nullptr;   // pinned, filled by copies
+    double *d = nullptr;     // pinned scratch [4 * MAX_RHS]
+    int *hflag = nullptr;    // coherent mapped status
+    double *hrr = nullptr;
+    int *dflag = nullptr;    // device views of hflag / hrr
+    double *drr = nullptr;
+    hipEvent_t ev[MAX_LOOK + 1] = {};
+    bool ok = false;
+    void create()
+    {
+        ok = hipHostMalloc((void **)&sc, sizeof(Scalars) * MAX_RHS) == hipSuccess &&
+             hipHostMalloc((void **)&d, sizeof(double) * 4 * MAX_RHS) == hipSuccess &&
+             hipHostMalloc((void **)&hflag, sizeof(int) * MAX_RHS, hipHostMallocMapped | hipHostMallocCoherent) ==
+                 hipSuccess &&
+             hipHostMalloc((void **)&hrr, sizeof(double) * MAX_RHS, hipHostMallocMapped | hipHostMallocCoherent) ==
+                 hipSuccess &&
+             hipHostGetDevicePointer((void **)&dflag, hflag, 0) == hipSuccess &&
+             hipHostGetDevicePointer((void **)&drr, hrr, 0) == hipSuccess;
+        for (int i = 0; ok && i <= MAX_LOOK; ++i)
+            ok = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+    }
+};
+std::mutex g_pool_mu;
+std::vector<HostBufs *> g_pool;
+
+struct HostLease {
+    HostBufs *b = nullptr;
+    HostLease()
+    {
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            if (!g_pool.empty()) {
+                b = g_pool.back();
+                g_pool.pop_back();
+            }
+        }
+        if (!b) {
+            b = new HostBufs();
+            b->create();
+        }
+    }
+    ~HostLease()
+    {
+        if (b && b->ok) {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            g_pool.push_back(b);
+        }
+        // a lease whose creation failed is leaked on purpose: its partially
+        // created resources are not reused
+    }
+};
+
 // A Krylov solver instance on one operator (one precision), nrhs columns.
 struct Engine {
     const wl_op *op;
     int solver, nrhs, prec;
     uint32_t V;
     hipStream_t st;
-    int check_every;
     void *v[6];
     double *part[3];
     int nblk[3] = {0, 0, 0}, nval[3] = {0, 0, 0};
     Scalars *sc;
     double *sums;
     Scalars *sc_host;  // pinned
+    HostBufs *hb;
+    int lookahead = 2;
     int stencil_calls = 0;
 
-    int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, Scalars *host_sc)
+    int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, HostBufs *h)
     {
         op = o;
         solver = solv;
@@ -91,7 +153,8 @@ struct Engine {
         prec = o->prec;
         V = o->V;
         st = s;
-        sc_host = host_sc;
+        hb = h;
+        sc_host = h->sc;
         const int nvec = solver == WL_SOLVER_CGNR ? 4 : 6;
         for (int i = 0; i < nvec; ++i)
             if (!(v[i] = a.take(vec_bytes(prec, V, nrhs))))
@@ -177,10 +240,37 @@ struct Engine {
         }
         p.sc = sc;
         p.out = sums;
+        p.hflag = hb->dflag;
+        p.hrr = hb->drr;
         p.nrhs = nrhs;
         p.iter = iter;
         p.tol2 = tol2;
         WL_TRY(launch_finalize(fop, p, st));
+        return WL_OK;
+    }
+
+    // Status as last mirrored by a finalize kernel (valid once an event
+    // recorded after that kernel has completed).
+    bool host_all_done() const
+    {
+        for (int r = 0; r < nrhs; ++r)
+            if (((volatile int *)hb->hflag)[r] == 0)
+                return false;
+        return true;
+    }
+
+    // Record the end of iteration `it` (0-based) and, once `lookahead`
+    // iterations are queued behind it, wait for an older one and check the
+    // mirrored status.  Returns true when every column has stopped.
+    int mark(int it, bool *stop)
+    {
+        const int L = lookahead, n = L + 1;
+        WL_TRY(hipEventRecord(hb->ev[it % n], st));
+        *stop = false;
+        if (it >= L) {
+            WL_TRY(hipEventSynchronize(hb->ev[(it - L) % n]));
+            *stop = host_all_done();
+        }
         return WL_OK;
     }
 
@@ -233,9 +323,9 @@ struct Engine {
                 return rc;
             if ((rc = blas(B_COPY, p, nullptr, z, nullptr, nullptr, nullptr, -1)))
                 return rc;
-            if ((rc = poll()))
-                return rc;
-            while (!all_done() && it < maxiter) {
+            WL_TRY(hipStreamSynchronize(st));
+            bool stop = host_all_done();
+            while (!stop && it < maxiter) {
                 if ((rc = stencil(w, p, 0, RED_NORM, nullptr, 0)))
                     return rc;
                 if ((rc = fin(F_CG_ALPHA, 0, -1, -1, it, tol2)))
@@ -248,10 +338,9 @@ struct Engine {
                     return rc;
                 if ((rc = blas(B_CG_P, p, nullptr, z, nullptr, nullptr, nullptr, -1)))
                     return rc;
+                if ((rc = mark(it, &stop)))
+                    return rc;
                 ++it;
-                if (it % check_every == 0 || it == maxiter)
-                    if ((rc = poll()))
-                        return rc;
             }
         } else {
             void *rh = v[1], *p = v[2], *vv = v[3], *s = v[4], *t = v[5];
@@ -263,9 +352,9 @@ struct Engine {
                 return rc;
             if ((rc = fin(F_INIT_BI, 0, -1, 2, 0, tol2)))
                 return rc;
-            if ((rc = poll()))
-                return rc;
-            while (!all_done() && it < maxiter) {
+            WL_TRY(hipStreamSynchronize(st));
+            bool stop = host_all_done();
+            while (!stop && it < maxiter) {
                 if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1)))
                     return rc;
                 if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0)))
@@ -282,15 +371,13 @@ struct Engine {
                     return rc;
                 if ((rc = fin(F_BI_RHO, 0, -1, -1, it, tol2)))
                     return rc;
+                if ((rc = mark(it, &stop)))
+                    return rc;
                 ++it;
-                if (it % check_every == 0 || it == maxiter)
-                    if ((rc = poll()))
-                        return rc;
             }
         }
-        if (!all_done())
-            if ((rc = poll()))
-                return rc;
+        if ((rc = poll()))
+            return rc;
         *iters_done = it;
         return WL_OK;
     }
@@ -324,18 +411,6 @@ struct Engine {
     }
 };
 
-struct PinnedScalars {
-    Scalars *p = nullptr;
-    double *d = nullptr;
-    ~PinnedScalars()
-    {
-        if (p)
-            (void)hipHostFree(p);
-        if (d)
-            (void)hipHostFree(d);
-    }
-};
-
 struct OwnedWorkspace {
     void *p = nullptr;
     ~OwnedWorkspace()
@@ -345,7 +420,13 @@ struct OwnedWorkspace {
     }
 };
 
-int default_check_every(uint32_t V) { return V >= (1u << 20) ? 2 : V >= (1u << 16) ? 4 : 8; }
+// Iterations the host lets the GPU run ahead of its convergence check
+// (check_every); the status is read from host-visible memory without a copy.
+int lookahead_of(const wl_solve_params *prm)
+{
+    const int c = prm->check_every > 0 ? prm->check_every : 2;
+    return c > MAX_LOOK ? MAX_LOOK : c;
+}
 
 int status_of(const wl_solve_stats &s, int flag)
 {
@@ -360,16 +441,15 @@ int status_of(const wl_solve_stats &s, int flag)
 int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, const wl_solve_params *prm,
                 wl_solve_stats *stats, hipStream_t st, Arena &arena)
 {
-    PinnedScalars pin;
-    if (hipHostMalloc((void **)&pin.p, sizeof(Scalars) * nrhs) != hipSuccess ||
-        hipHostMalloc((void **)&pin.d, sizeof(double) * 4 * nrhs) != hipSuccess)
+    HostLease lease;
+    if (!lease.b->ok)
         return WL_EHIP;
     Engine E{};
-    int rc = E.init(arena, op, solver, nrhs, st, pin.p);
+    int rc = E.init(arena, op, solver, nrhs, st, lease.b);
     if (rc)
         return rc;
-    E.check_every = prm->check_every > 0 ? prm->check_every : default_check_every(op->V);
-    double *bb = pin.d, *rr = pin.d + nrhs;
+    E.lookahead = lookahead_of(prm);
+    double *bb = lease.b->d, *rr = lease.b->d + nrhs;
     if ((rc = E.norm2(b, bb)))
         return rc;
     std::vector<int> iters(nrhs, 0), flags(nrhs, 0);
@@ -426,25 +506,24 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
 int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
                 const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena)
 {
-    PinnedScalars pin;
-    if (hipHostMalloc((void **)&pin.p, sizeof(Scalars) * nrhs) != hipSuccess ||
-        hipHostMalloc((void **)&pin.d, sizeof(double) * 4 * nrhs) != hipSuccess)
+    HostLease lease;
+    if (!lease.b->ok)
         return WL_EHIP;
     Engine H{}, L{};
     int rc;
     // the outer engine only needs r, w and the partial/scalar buffers; it is
     // initialised as a CGNR engine (4 vectors) for simplicity of layout
-    if ((rc = H.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, pin.p)))
+    if ((rc = H.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, lease.b)))
         return rc;
-    if ((rc = L.init(arena, lo, solver, nrhs, st, pin.p)))
+    if ((rc = L.init(arena, lo, solver, nrhs, st, lease.b)))
         return rc;
     void *r_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
     void *e_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
     double *sig_dev = (double *)arena.take(sizeof(double) * nrhs);
     if (!r_lo || !e_lo || !sig_dev)
         return WL_EWORKSPACE;
-    H.check_every = L.check_every = prm->check_every > 0 ? prm->check_every : default_check_every(hi->V);
-    double *bb = pin.d, *rr = pin.d + nrhs, *sig = pin.d + 2 * nrhs;
+    H.lookahead = L.lookahead = lookahead_of(prm);
+    double *bb = lease.b->d, *rr = lease.b->d + nrhs, *sig = lease.b->d + 2 * nrhs;
     if ((rc = H.norm2(b, bb)))
         return rc;
     if (!prm->use_x0)

@@ -163,6 +163,215 @@ __device__ __forceinline__ void hop_site(const StencilParams &p, uint32_t s, int
     hop_dir<P, DAG, R, 3>(p, s, t, st, r0, acc);
 }
 
+// ---------------------------------------------------------------- pipelined hops
+// The eight hops of a site as a software pipeline: the raw (still packed)
+// spinor and link data of the next G hops are loaded while the current G
+// hops are decoded and computed, so each wavefront keeps up to 2G hops of
+// loads in flight instead of draining after every hop.
+template <int P>
+struct RawHop;
+template <>
+struct RawHop<F64> {
+    double2 sp[12];
+    double2 lk[6];
+};
+template <>
+struct RawHop<F32> {
+    float4 sp[6];
+    float4 lk[3];
+};
+template <>
+struct RawHop<BF16S> {
+    uint4 sp[3];
+    uint2 lk[3];
+    float sc;
+};
+template <>
+struct RawHop<F16S> {
+    uint4 sp[3];
+    uint2 lk[3];
+    float sc;
+};
+
+struct Hops {
+    uint32_t nb[8];  // neighbour site of hop h = 2 mu + (0 forward, 1 backward)
+    float sg[8];     // boundary sign of the hop
+};
+
+__device__ __forceinline__ void make_hops(const StencilParams &p, uint32_t s, Hops &h)
+{
+    const uint32_t q1 = fdiv(s, p.fx);
+    const int x = (int)(s - q1 * (uint32_t)p.L[0]);
+    const uint32_t q2 = fdiv(q1, p.fy);
+    const int y = (int)(q1 - q2 * (uint32_t)p.L[1]);
+    const uint32_t q3 = fdiv(q2, p.fz);
+    const int z = (int)(q2 - q3 * (uint32_t)p.L[2]);
+    const int t = (int)q3;
+    const int c[4] = {x, y, z, t};
+    uint32_t stride = 1u;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = p.L[mu];
+        const bool wf = (c[mu] == L - 1), wb = (c[mu] == 0);
+        const uint32_t span = (uint32_t)(L - 1) * stride;
+        h.nb[2 * mu] = wf ? s - span : s + stride;
+        h.nb[2 * mu + 1] = wb ? s + span : s - stride;
+        const bool anti = p.bc[mu] < 0;
+        h.sg[2 * mu] = (wf && anti) ? -1.f : 1.f;
+        h.sg[2 * mu + 1] = (wb && anti) ? -1.f : 1.f;
+        stride *= (uint32_t)L;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void raw_load(const StencilParams &p, uint32_t nb, uint32_t ls, int mu, int rhs,
+                                         RawHop<P> &r)
+{
+    const uint32_t V = p.V;
+    const size_t so = (size_t)rhs * Traits<P>::NCH * V + nb;  // chunk 0 of the neighbour, this right-hand side
+    if constexpr (P == F64) {
+        const double2 *b = reinterpret_cast<const double2 *>(p.in) + so;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            r.sp[k] = b[(size_t)k * V];
+        const double2 *u = reinterpret_cast<const double2 *>(p.U) + (size_t)mu * 6 * V + ls;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            r.lk[k] = u[(size_t)k * V];
+    } else if constexpr (P == F32) {
+        const float4 *b = reinterpret_cast<const float4 *>(p.in) + so;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            r.sp[k] = b[(size_t)k * V];
+        const float4 *u = reinterpret_cast<const float4 *>(p.U) + (size_t)mu * 3 * V + ls;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            r.lk[k] = u[(size_t)k * V];
+    } else {
+        const uint4 *b = reinterpret_cast<const uint4 *>(p.in) + so;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            r.sp[k] = b[(size_t)k * V];
+        r.sc = scale_ptr<P>(p.in, V, p.nrhs)[(size_t)rhs * V + nb];
+        const uint2 *u = reinterpret_cast<const uint2 *>(p.U) + (size_t)mu * 3 * V + ls;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            r.lk[k] = u[(size_t)k * V];
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void decode(const RawHop<P> &r, cx<typename Traits<P>::real> (&ps)[12],
+                                       cx<typename Traits<P>::real> (&u)[9])
+{
+    using T = typename Traits<P>::real;
+    if constexpr (P == F64) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            ps[k] = cx<double>{r.sp[k].x, r.sp[k].y};
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            u[k] = cx<double>{r.lk[k].x, r.lk[k].y};
+    } else if constexpr (P == F32) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            ps[2 * k] = cx<float>{r.sp[k].x, r.sp[k].y};
+            ps[2 * k + 1] = cx<float>{r.sp[k].z, r.sp[k].w};
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            u[2 * k] = cx<float>{r.lk[k].x, r.lk[k].y};
+            u[2 * k + 1] = cx<float>{r.lk[k].z, r.lk[k].w};
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t w[4] = {r.sp[k].x, r.sp[k].y, r.sp[k].z, r.sp[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const cx<float> a = unpack2<P>(w[j]);
+                ps[4 * k + j] = cx<float>{a.re * r.sc, a.im * r.sc};
+            }
+            u[2 * k] = unpack2<P>(r.lk[k].x);
+            u[2 * k + 1] = unpack2<P>(r.lk[k].y);
+        }
+    }
+    // row 2 = conj(row0 x row1)
+    const cx<T> a0 = u[0], a1 = u[1], a2 = u[2], b0 = u[3], b1 = u[4], b2 = u[5];
+    cx<T> c0 = cmul(a1, b2), c1 = cmul(a2, b0), c2 = cmul(a0, b1);
+    c0 = cfma(cx<T>{-a2.re, -a2.im}, b1, c0);
+    c1 = cfma(cx<T>{-a0.re, -a0.im}, b2, c1);
+    c2 = cfma(cx<T>{-a1.re, -a1.im}, b0, c2);
+    u[6] = cconj(c0);
+    u[7] = cconj(c1);
+    u[8] = cconj(c2);
+}
+
+template <int P, int DAG, int H>
+__device__ __forceinline__ void compute_hop(const RawHop<P> &r, float sg, cx<typename Traits<P>::real> (&acc)[12])
+{
+    using T = typename Traits<P>::real;
+    constexpr int MU = H / 2;
+    constexpr int SF = DAG ? 1 : -1;
+    constexpr int SIG = (H % 2 == 0) ? SF : -SF;
+    cx<T> ps[12], u[9], h[6], g[6];
+    decode<P>(r, ps, u);
+    project<MU, SIG>(ps, h);
+    if constexpr (H % 2 == 0)
+        su3_mv(u, h, g);
+    else
+        su3_adj_mv(u, h, g);
+    accum<MU, SIG>(acc, g, (T)sg);
+}
+
+template <int P, int G, int H>
+__device__ __forceinline__ void load_group(const StencilParams &p, uint32_t s, int rhs, const Hops &hp,
+                                           RawHop<P> (&buf)[2 * G])
+{
+    constexpr int slot = ((H / G) % 2) * G;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const int h = H + j;
+        raw_load<P>(p, hp.nb[h], (h % 2 == 0) ? s : hp.nb[h], h / 2, rhs, buf[slot + j]);
+    }
+    // keep the group's loads here: the scheduler would otherwise sink them
+    // next to their first use and serialise the pipeline
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int P, int DAG, int G, int H>
+__device__ __forceinline__ void pipe(const StencilParams &p, uint32_t s, int rhs, const Hops &hp,
+                                     RawHop<P> (&buf)[2 * G], cx<typename Traits<P>::real> (&acc)[12])
+{
+    if constexpr (H < 8) {
+        if constexpr (H % G == 0 && H + G < 8)
+            load_group<P, G, H + G>(p, s, rhs, hp, buf);
+        compute_hop<P, DAG, H>(buf[((H / G) % 2) * G + H % G], hp.sg[H], acc);
+        pipe<P, DAG, G, H + 1>(p, s, rhs, hp, buf, acc);
+    }
+}
+
+template <int P, int DAG, int G>
+__device__ __forceinline__ void hop_site_pipe(const StencilParams &p, uint32_t s, int rhs,
+                                              cx<typename Traits<P>::real> (&acc)[12])
+{
+    Hops hp;
+    make_hops(p, s, hp);
+    RawHop<P> buf[2 * G];
+    load_group<P, G, 0>(p, s, rhs, hp, buf);
+    pipe<P, DAG, G, 0>(p, s, rhs, hp, buf, acc);
+}
+
+// Stencil code variants (chosen per launch by the autotuner):
+//   0: straight-line hops, compiler-scheduled loads (any R)
+//   1, 2, 3: pipelined hops with G = 1, 2, 4 hops per stage (R = 1)
+template <int P, int VAR>
+struct VarG {
+    static constexpr int G = VAR == 1 ? 1 : VAR == 2 ? 2 : 4;
+};
+// FP64 with G = 2 and FP32 with G = 4 exceed the register file and spill.
+int max_var(int prec) { return prec == F64 ? 1 : prec == F32 ? 2 : 3; }
+
 // Round a site to what the 16-bit format will store (so that fused
 // reductions see exactly the stored values).
 template <int P>
@@ -182,7 +391,7 @@ __device__ __forceinline__ void round_site(cx<float> (&v)[12])
     }
 }
 
-template <int P, int DAG, int R, int RED, int APPLY>
+template <int P, int DAG, int R, int RED, int APPLY, int VAR>
 __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 {
     using T = typename Traits<P>::real;
@@ -203,8 +412,10 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 acc[r][k] = cx<T>{T(0), T(0)};
-        hop_site<P, DAG, R>(p, s, r0, acc);
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (VAR == 0 || R > 1)
+            hop_site<P, DAG, R>(p, s, r0, acc);
+        else
+            hop_site_pipe<P, DAG, VarG<P, VAR>::G>(p, s, r0, acc[0]);
         const T kap = (T)p.kappa;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -276,26 +487,50 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 
 int stencil_nval(int red) { return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : 0; }
 
-template <int P, int DAG, int R>
-static hipError_t launch_t(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
+template <int P, int DAG, int R, int VAR>
+static hipError_t launch_v(dim3 grid, dim3 block, const StencilParams &p, hipStream_t st)
 {
-    dim3 grid(p.nblk, p.nrhs / R), block(cfg.block);
     if (!p.apply) {  // the hopping term alone is only offered without fused reductions
         if (p.red != RED_NONE)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NONE, 0>), grid, block, 0, st, p);
+        hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NONE, 0, VAR>), grid, block, 0, st, p);
         return hipGetLastError();
     }
     switch (p.red) {
-    case RED_NONE: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NONE, 1>), grid, block, 0, st, p); break;
-    case RED_NORM: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NORM, 1>), grid, block, 0, st, p); break;
-    case RED_DOTV: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTV, 1>), grid, block, 0, st, p); break;
+    case RED_NONE: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NONE, 1, VAR>), grid, block, 0, st, p); break;
+    case RED_NORM: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NORM, 1, VAR>), grid, block, 0, st, p); break;
+    case RED_DOTV: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTV, 1, VAR>), grid, block, 0, st, p); break;
     case RED_DOTIN_NORM:
-        hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTIN_NORM, 1>), grid, block, 0, st, p);
+        hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTIN_NORM, 1, VAR>), grid, block, 0, st, p);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int P, int DAG, int R>
+static hipError_t launch_t(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
+{
+    dim3 grid(p.nblk, p.nrhs / R), block(cfg.block);
+    if constexpr (R == 1) {
+        switch (cfg.var) {
+        case 0: return launch_v<P, DAG, 1, 0>(grid, block, p, st);
+        case 1: return launch_v<P, DAG, 1, 1>(grid, block, p, st);
+        case 2:
+            if constexpr (P != F64)
+                return launch_v<P, DAG, 1, 2>(grid, block, p, st);
+            return hipErrorInvalidValue;
+        case 3:
+            if constexpr (P == BF16S || P == F16S)
+                return launch_v<P, DAG, 1, 3>(grid, block, p, st);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        if (cfg.var != 0)
+            return hipErrorInvalidValue;
+        return launch_v<P, DAG, R, 0>(grid, block, p, st);
+    }
 }
 
 // Right-hand sides per thread: FP64 keeps at most 2 (24 FP64 accumulators

@@ -101,8 +101,8 @@ def lib():
         "wilson_gauge_force": [P, P, P, P, I, P],
         "wilson_multi_apply": [ctypes.POINTER(wl_multi_desc), I, I, I, P],
         "wl_autotune": [P, I, I, P],
-        "wl_get_launch": [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
-        "wl_set_launch": [P, I, I, I, I],
+        "wl_get_launch": [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
+        "wl_set_launch": [P, I, I, I, I, I],
         "wl_prof_enable": [I],
         "wl_prof_reset": [],
         "wl_prof_read": [I, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), ctypes.POINTER(D)],
@@ -205,13 +205,19 @@ def wl_autotune(op, nrhs, dagger, stream):
 
 
 def wl_get_launch(op, nrhs):
-    b, r, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(lib().wl_get_launch(op, nrhs, ctypes.byref(b), ctypes.byref(r), ctypes.byref(x)), "wl_get_launch")
-    return b.value, r.value, x.value
+    b, r, x, v = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().wl_get_launch(op, nrhs, ctypes.byref(b), ctypes.byref(r), ctypes.byref(x), ctypes.byref(v)),
+           "wl_get_launch")
+    return b.value, r.value, x.value, v.value
 
 
-def wl_set_launch(op, nrhs, block, rpt, xcd):
-    return _check(lib().wl_set_launch(op, nrhs, block, rpt, xcd), "wl_set_launch")
+def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0):
+    return _check(lib().wl_set_launch(op, nrhs, block, rpt, xcd, variant), "wl_set_launch")
+
+
+# Largest stencil code variant per precision (see wl_set_launch in the header).
+MAX_VARIANT = {WL_F64: 1, WL_F32: 2, WL_BF16S: 3, WL_F16S: 3}
+MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
 
 
 def wl_prof_enable(on):

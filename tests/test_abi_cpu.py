@@ -79,10 +79,13 @@ def test_bad_arguments_rejected_before_launch():
         assert L.wilson_apply(op, 512, 1024, 2, 1, None) == wilson.WL_EINVAL  # dagger flag
         assert L.wilson_apply(op, 512, 1024, 0, 0, None) == wilson.WL_EINVAL  # nrhs
         assert L.wilson_apply(op, 520, 1024, 0, 1, None) == wilson.WL_EALIGN
-        assert L.wl_set_launch(op, 1, 96, 1, 1) == wilson.WL_EINVAL
-        assert L.wl_set_launch(op, 4, 256, 3, 1) == wilson.WL_EINVAL  # 3 does not divide 4
-        assert L.wl_set_launch(op, 4, 256, 4, 1) == wilson.WL_EINVAL  # FP64 offers at most 2
-        assert L.wl_set_launch(op, 4, 256, 2, 0) == wilson.WL_OK
+        assert L.wl_set_launch(op, 1, 96, 1, 1, 0) == wilson.WL_EINVAL
+        assert L.wl_set_launch(op, 4, 256, 3, 1, 0) == wilson.WL_EINVAL  # 3 does not divide 4
+        assert L.wl_set_launch(op, 4, 256, 4, 1, 0) == wilson.WL_EINVAL  # FP64 offers at most 2
+        assert L.wl_set_launch(op, 4, 256, 2, 0, 1) == wilson.WL_EINVAL  # pipelined variants need 1 RHS/thread
+        assert L.wl_set_launch(op, 1, 256, 1, 0, 2) == wilson.WL_EINVAL  # FP64 offers variants 0, 1
+        assert L.wl_set_launch(op, 1, 256, 1, 0, 1) == wilson.WL_OK
+        assert L.wl_set_launch(op, 4, 256, 2, 0, 0) == wilson.WL_OK
         prm = wilson.wl_solve_params(tol=0.0, maxiter=10)
         assert L.solve_cgnr(op, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
         prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)

@@ -76,9 +76,13 @@ def test_apply_matches_oracle(W, oracle_mod, dims, kind, prec, dagger):
     kappa = 0.1255
     U = _gauge(dims, kind)
     psi = inputs.gaussian_spinor(dims, seed=0)
-    out = W.apply(dev(U), dev(psi), kappa, dagger=dagger, prec=prec).cpu().numpy()
     ref = oracle_mod.apply(U, psi, kappa, dagger=dagger)
-    assert rel(out, ref) < TOL[prec]
+    p = W.PREC[prec]
+    op = W.Operator.create(dev(U), kappa, p)
+    for var in range(W.MAX_VARIANT[p] + 1):
+        W.wl_set_launch(op.handle, 1, 256, 1, 1, var)
+        out = W.apply(None, dev(psi), kappa, dagger=dagger, op=op).cpu().numpy()
+        assert rel(out, ref) < TOL[prec], var
 
 
 @pytest.mark.parametrize("dims,kind", CASES[:4])
@@ -119,14 +123,15 @@ def test_multi_rhs_columns_equal_single_rhs(W, prec):
     src = op.pack(dev(psi))
     outs = []
     for rpt in (1, 2, 3, 4):
-        if rpt > (2 if prec == "f64" else 4):
+        if rpt > W.MAX_RPT[p]:
             continue
         for block in (64, 256, 512):
             for xcd in (0, 1):
-                W.wl_set_launch(op.handle, 12, block, rpt, xcd)
-                dst = op.new_field(12)
-                op.apply_packed(dst, src, 12)
-                outs.append(op.unpack(dst, 12).cpu().numpy())
+                for var in range(W.MAX_VARIANT[p] + 1 if rpt == 1 else 1):
+                    W.wl_set_launch(op.handle, 12, block, rpt, xcd, var)
+                    dst = op.new_field(12)
+                    op.apply_packed(dst, src, 12)
+                    outs.append(op.unpack(dst, 12).cpu().numpy())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])  # launch shape never changes a result
     for k in (0, 5, 11):
