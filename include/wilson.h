@@ -129,6 +129,7 @@ typedef struct {
     int reliable;         /* mixed: 0 = restart inner solve per cycle, 1 = reliable updates */
     int check_every;      /* host convergence check period in iterations (0 = default) */
     int use_x0;           /* 1 = x holds the initial guess on entry, 0 = start from x = 0 */
+    int dagger;           /* 1 = solve D^dag x = b (the adjoint system; D^dag = gamma5 D gamma5) */
     void *workspace;      /* device scratch, NULL = library allocates for the call */
     size_t workspace_bytes;
 } wl_solve_params;
@@ -165,8 +166,9 @@ int solve_bicgstab(const wl_op *hi, const wl_op *lo, void *x, const void *b, int
  *   G_mu(x) = kappa s_mu(x) [ sum_spin ((1 - g_mu) x(x+mu)) mu(x)^dag
  *                           + sum_spin mu(x+mu) ((1 + g_mu) x(x))^dag ].
  * project = 0: out = G^dag (the unconstrained complex gradient dL/dRe U + i dL/dIm U);
- * project = 1: out = P = traceless Hermitian part of i U G (the su(3) force;
- *              the tangent gradient is i P U).
+ * project = 1: out = P = traceless Hermitian part of i U G (the su(3) force:
+ *              along U -> exp(i w T) U, dL/dw = Tr[T P]);
+ * project = 2: out = i P U (the gradient in the tangent space of SU(3)).
  * x, mu: packed spinors of the op's precision (WL_F64 or WL_F32), nrhs = 1.
  * out: canonical complex128 gauge layout.  Async. */
 int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const void *mu, int project,
@@ -193,7 +195,9 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
 int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rhs_per_thread, int *xcd_remap, int *variant);
 /* Force a launch configuration: block in {64,...,512} (multiple of 64);
  * rhs_per_thread dividing nrhs, at most 2 for WL_F64 and 4 otherwise;
- * xcd_remap 0/1; variant 0 (straight-line hops) or, with rhs_per_thread = 1,
+ * xcd_remap: 0 natural tile order, 1 one contiguous site range per XCD,
+ * 2 one z-slab per XCD walked t-major (needs Lz % 8 == 0 and block dividing
+ * V/8); variant 0 (straight-line hops) or, with rhs_per_thread = 1,
  * a software-pipelined hop loop: 1 (all precisions), 2 (not WL_F64),
  * 3 (16-bit formats only).  Results do not depend on the configuration.
  * Used by tests and the autotuner. */
@@ -206,6 +210,12 @@ int wl_set_launch(wl_op *op, int nrhs, int block, int rhs_per_thread, int xcd_re
 int wl_prof_enable(int on);
 int wl_prof_reset(void);
 int wl_prof_read(int prec, long *launches, double *total_ms, double *site_rhs);
+
+/* Plain device-to-device streaming copy of `bytes` (a multiple of 16, no
+ * overlap): the reference point for achievable HBM bandwidth and for
+ * calibrating hardware byte counters against a kernel of known traffic.
+ * Async. */
+int wl_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 const char *wl_strerror(int code);
 int wl_last_hip_error(void);

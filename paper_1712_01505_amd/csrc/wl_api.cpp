@@ -198,6 +198,14 @@ static LaunchCfg default_launch(int prec, int nrhs)
     return c;
 }
 
+static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
+{
+    const int prec = op->prec;
+    return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
+           nrhs % c.rpt == 0 && c.xcd >= 0 && c.xcd <= 2 && (c.xcd != 2 || slab_ok(op->g.dims, c.block)) &&
+           c.var >= 0 && c.var <= max_var(prec) && (c.var == 0 || c.rpt == 1);
+}
+
 LaunchCfg launch_for(const wl_op *op, int nrhs)
 {
     wl_op *o = const_cast<wl_op *>(op);
@@ -212,7 +220,7 @@ LaunchCfg launch_for(const wl_op *op, int nrhs)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_cache_locked();
         auto it = g_tune.find(tune_key(op, nrhs, 0));
-        if (it != g_tune.end())
+        if (it != g_tune.end() && launch_ok(op, nrhs, it->second))
             c = it->second;
     }
     std::lock_guard<std::mutex> lk(o->mu);
@@ -392,7 +400,8 @@ int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int 
 static int solve_entry(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
                        const wl_solve_params *p, wl_solve_stats *stats, void *stream)
 {
-    if (!hi || !x || !b || !p || nrhs < 1 || nrhs > 64 || x == b || !(p->tol > 0) || p->maxiter < 1)
+    if (!hi || !x || !b || !p || nrhs < 1 || nrhs > 64 || x == b || !(p->tol > 0) || p->maxiter < 1 ||
+        (p->dagger != 0 && p->dagger != 1))
         return WL_EINVAL;
     if (!al16(x) || !al16(b))
         return WL_EALIGN;
@@ -424,7 +433,7 @@ int solve_bicgstab(const wl_op *hi, const wl_op *lo, void *x, const void *b, int
 
 int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const void *mu, int project, void *stream)
 {
-    if (!op || !out_canon || !x || !mu || (project != 0 && project != 1))
+    if (!op || !out_canon || !x || !mu || project < 0 || project > 2)
         return WL_EINVAL;
     if (op->prec != WL_F64 && op->prec != WL_F32)
         return WL_EPREC;
@@ -499,19 +508,13 @@ int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rpt, int *xcd, int
     return WL_OK;
 }
 
-static bool launch_ok(int prec, int nrhs, const LaunchCfg &c)
-{
-    return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
-           nrhs % c.rpt == 0 && (c.xcd == 0 || c.xcd == 1) && c.var >= 0 && c.var <= max_var(prec) &&
-           (c.var == 0 || c.rpt == 1);
-}
 
 int wl_set_launch(wl_op *op, int nrhs, int block, int rpt, int xcd, int variant)
 {
     if (!op || nrhs < 1)
         return WL_EINVAL;
     const LaunchCfg c{block, rpt, xcd, variant};
-    if (!launch_ok(op->prec, nrhs, c))
+    if (!launch_ok(op, nrhs, c))
         return WL_EINVAL;
     std::lock_guard<std::mutex> lk(op->mu);
     op->launch[nrhs] = c;
@@ -542,10 +545,10 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     std::vector<LaunchCfg> cands;
     for (int bi = 0; bi < 4; ++bi)
         for (int rpt = 1; rpt <= max_rpt(op->prec); ++rpt)
-            for (int xcd = 0; xcd <= 1; ++xcd)
+            for (int xcd = 0; xcd <= 2; ++xcd)
                 for (int var = 0; var <= max_var(op->prec); ++var) {
                     const LaunchCfg c{blocks[bi], rpt, xcd, var};
-                    if (launch_ok(op->prec, nrhs, c))
+                    if (launch_ok(op, nrhs, c))
                         cands.push_back(c);
                 }
     for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
@@ -586,6 +589,21 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     load_tune_cache_locked();
     g_tune[tune_key(op, nrhs, 0)] = best;
     save_tune_cache_locked();
+    return WL_OK;
+}
+
+int wl_stream_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if (!dst || !src || bytes % 16 != 0)
+        return WL_EINVAL;
+    if (!al16(dst) || !al16(src))
+        return WL_EALIGN;
+    const char *d = (const char *)dst, *s = (const char *)src;
+    if (d < s + bytes && s < d + bytes)
+        return WL_EINVAL;  // overlapping ranges
+    if (bytes == 0)
+        return WL_OK;
+    CHECK_HIP(launch_stream_copy(dst, src, bytes, (hipStream_t)stream));
     return WL_OK;
 }
 

@@ -288,6 +288,23 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t b, uint32_t nb, int xcd)
     return k * q + (k < r ? k : r) + j;
 }
 
+// Slab order (xcd mode 2): XCD k owns the z-slab [k Lz/8, (k+1) Lz/8) and
+// walks it t-major, so the +-t neighbours of its in-flight sites are in its
+// own recent traffic (its L2) instead of one full t-slice away.  Needs
+// Lz % 8 == 0 and a block size dividing V / 8 (the host checks).
+// slab_xy = Lx Ly, slab_n = Lx Ly Lz / 8 sites per slab t-slice.
+__device__ __forceinline__ uint32_t slab_site(uint32_t b, uint32_t tid, uint32_t block, uint32_t slab_xy,
+                                              FastDiv f_slab_n, FastDiv f_slab_xy, uint32_t slab_n, uint32_t vslice)
+{
+    const uint32_t k = b & 7u, j = b >> 3;
+    const uint32_t l = j * block + tid;
+    const uint32_t t = fdiv(l, f_slab_n);
+    const uint32_t rem = l - t * slab_n;
+    const uint32_t z = fdiv(rem, f_slab_xy);
+    const uint32_t xy = rem - z * slab_xy;
+    return xy + slab_xy * (k * (slab_n / slab_xy) + z) + vslice * t;
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v)
 {

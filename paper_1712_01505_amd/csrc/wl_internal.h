@@ -19,7 +19,7 @@ namespace wl {
 struct LaunchCfg {
     int block = 256;  // threads per workgroup (= sites per tile)
     int rpt = 1;      // right-hand sides per thread
-    int xcd = 1;      // XCD-aware tile order
+    int xcd = 1;      // tile order: 0 natural, 1 contiguous range per XCD, 2 z-slab per XCD (t-major)
     int var = 0;      // stencil code variant (0 = straight-line hops; 1..3 = pipelined, R = 1 only)
 };
 
@@ -61,6 +61,9 @@ struct StencilParams {
     int red;
     int xcd;
     int nblk;   // number of site tiles (gridDim.x)
+    // slab order (xcd == 2)
+    FastDiv f_slab_n, f_slab_xy;
+    uint32_t slab_n, slab_xy, vslice;
 };
 
 // ---- stencil (wl_stencil.hip)
@@ -68,6 +71,7 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
 int stencil_nval(int red);
 int max_rpt(int prec);  // largest right-hand sides per thread the stencil offers
 int max_var(int prec);  // largest stencil code variant for R = 1
+bool slab_ok(const int *L, int block);  // slab order usable for these extents and block size
 
 struct MultiEntry {
     StencilParams p;
@@ -89,6 +93,7 @@ hipError_t launch_unpack_spinor(int prec, uint32_t V, int nrhs, const void *pack
 hipError_t launch_convert(int pin, int pout, uint32_t V, int nrhs, const void *in, void *out, const double *s,
                           int sstride, int mode, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, unsigned v, int n, hipStream_t st);
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 // ---- BLAS-1 and solver scalars (wl_blas.hip)
 // Per-right-hand-side solver scalars, kept on the device.

@@ -129,6 +129,38 @@ __global__ void fill_u32_kernel(unsigned *p, unsigned v, int n)
         p[i] = v;
 }
 
+// Plain streaming copy, 4 x 16 bytes per thread per pass (bandwidth and
+// byte-counter calibration: it reads and writes exactly `n16` 16-byte units).
+__global__ __launch_bounds__(256) void stream_copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+                                                          size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    const size_t n16 = bytes / 16;
+    const int B = 256;
+    size_t blocks = (n16 + 4 * B - 1) / (4 * B);
+    if (blocks > 65536)
+        blocks = 65536;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(B), 0, st, (uint4 *)dst, (const uint4 *)src,
+                       n16);
+    return hipGetLastError();
+}
+
 static inline dim3 grid_for(uint32_t V, int nrhs, int block) { return dim3((V + block - 1) / block, nrhs); }
 
 hipError_t launch_pack_gauge(int prec, uint32_t V, const void *canon, void *packed, hipStream_t st)

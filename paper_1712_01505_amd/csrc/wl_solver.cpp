@@ -143,6 +143,7 @@ struct Engine {
     Scalars *sc_host;  // pinned
     HostBufs *hb;
     int lookahead = 2;
+    int adj = 0;  // solving with D^dag: every stencil's dagger flag is flipped
     int stencil_calls = 0;
 
     int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, HostBufs *h)
@@ -195,7 +196,7 @@ struct Engine {
             nval[slot] = stencil_nval(red);
         }
         ++stencil_calls;
-        WL_TRY(prof_stencil(prec, op, dagger, cfg, p, st));
+        WL_TRY(prof_stencil(prec, op, dagger ^ adj, cfg, p, st));
         return WL_OK;
     }
 
@@ -448,6 +449,7 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
     int rc = E.init(arena, op, solver, nrhs, st, lease.b);
     if (rc)
         return rc;
+    E.adj = prm->dagger;
     E.lookahead = lookahead_of(prm);
     double *bb = lease.b->d, *rr = lease.b->d + nrhs;
     if ((rc = E.norm2(b, bb)))
@@ -517,6 +519,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         return rc;
     if ((rc = L.init(arena, lo, solver, nrhs, st, lease.b)))
         return rc;
+    H.adj = L.adj = prm->dagger;
     void *r_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
     void *e_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
     double *sig_dev = (double *)arena.take(sizeof(double) * nrhs);

@@ -397,8 +397,9 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
     using T = typename Traits<P>::real;
     constexpr int NV = RED == RED_NORM ? 1 : RED == RED_DOTV ? 2 : RED == RED_DOTIN_NORM ? 3 : 0;
     __shared__ double lds[(NV > 0 ? NV : 1) * R * 8];
-    const uint32_t tile = tile_of(blockIdx.x, gridDim.x, p.xcd);
-    const uint32_t s = tile * blockDim.x + threadIdx.x;
+    const uint32_t s = p.xcd == 2 ? slab_site(blockIdx.x, threadIdx.x, blockDim.x, p.slab_xy, p.f_slab_n, p.f_slab_xy,
+                                              p.slab_n, p.vslice)
+                                  : tile_of(blockIdx.x, gridDim.x, p.xcd) * blockDim.x + threadIdx.x;
     const int r0 = blockIdx.y * R;
     const bool active = s < p.V;
     double red[(NV > 0 ? NV : 1) * R];
@@ -485,6 +486,12 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
     }
 }
 
+bool slab_ok(const int *L, int block)
+{
+    const uint64_t slab = (uint64_t)L[0] * L[1] * (L[2] / 8) * L[3];
+    return L[2] % 8 == 0 && slab % (uint64_t)block == 0;
+}
+
 int stencil_nval(int red) { return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : 0; }
 
 template <int P, int DAG, int R, int VAR>
@@ -563,6 +570,15 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
         return hipErrorInvalidValue;
     p.nblk = (int)((p.V + cfg.block - 1) / cfg.block);
     p.xcd = cfg.xcd;
+    if (p.xcd == 2) {
+        if (!slab_ok(p.L, cfg.block))
+            return hipErrorInvalidValue;
+        p.slab_xy = (uint32_t)p.L[0] * (uint32_t)p.L[1];
+        p.slab_n = p.slab_xy * (uint32_t)(p.L[2] / 8);
+        p.vslice = p.slab_xy * (uint32_t)p.L[2];
+        p.f_slab_n = make_fastdiv(p.slab_n);
+        p.f_slab_xy = make_fastdiv(p.slab_xy);
+    }
     switch (prec * 2 + (dagger ? 1 : 0)) {
     case 0: return launch_r<F64, 0>(cfg, p, st);
     case 1: return launch_r<F64, 1>(cfg, p, st);
@@ -769,6 +785,7 @@ __device__ __forceinline__ void force_dir(const StencilParams &p, uint32_t s, in
         }
     // P = (A + A^dag)/2 - Tr[(A + A^dag)/2]/3
     const double tr = (A[0].re + A[4].re + A[8].re) / 3.0;
+    cx<double> Pm[9];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -777,7 +794,24 @@ __device__ __forceinline__ void force_dir(const StencilParams &p, uint32_t s, in
             double im = 0.5 * (A[3 * a + b].im - A[3 * b + a].im);
             if (a == b)
                 re -= tr;
-            o[3 * a + b] = make_double2(re, im);
+            Pm[3 * a + b] = cx<double>{re, im};
+        }
+    if (want_p == 1) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            o[k] = make_double2(Pm[k].re, Pm[k].im);
+        return;
+    }
+    // tangent gradient i P U
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            cx<double> acc{0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                acc = cfma(Pm[3 * a + k], cx<double>{(double)ut[3 * k + b].re, (double)ut[3 * k + b].im}, acc);
+            o[3 * a + b] = make_double2(-acc.im, acc.re);
         }
 }
 

@@ -35,7 +35,7 @@ EXPORTS = [
     "wl_op_create", "wl_op_destroy", "wilson_dslash", "wilson_apply", "wl_solver_workspace_bytes",
     "solve_cgnr", "solve_bicgstab", "wilson_gauge_force", "wilson_multi_apply", "wl_autotune",
     "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read",
-    "wl_strerror", "wl_last_hip_error",
+    "wl_stream_copy", "wl_strerror", "wl_last_hip_error",
 ]
 
 
@@ -46,7 +46,8 @@ class wl_geom(ctypes.Structure):
 class wl_solve_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("reliable", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("use_x0", ctypes.c_int), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("use_x0", ctypes.c_int), ("dagger", ctypes.c_int), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class wl_solve_stats(ctypes.Structure):
@@ -106,6 +107,7 @@ def lib():
         "wl_prof_enable": [I],
         "wl_prof_reset": [],
         "wl_prof_read": [I, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), ctypes.POINTER(D)],
+        "wl_stream_copy": [P, P, SZ, P],
         "wl_strerror": [I],
         "wl_last_hip_error": [],
     }
@@ -195,6 +197,16 @@ def wilson_gauge_force(op, out_canon, x, mu, project, stream):
     return _check(lib().wilson_gauge_force(op, out_canon, x, mu, int(project), stream), "wilson_gauge_force")
 
 
+def gauge_force(op, x_packed, mu_packed, project=2):
+    """Link derivative from packed x and adjoint mu (op precision FP64/FP32):
+    project 0 -> G^dag, 1 -> P (su(3) force), 2 -> i P U; canonical complex128 (4, Lt, Lz, Ly, Lx, 3, 3)."""
+    torch = _torch()
+    Lx, Ly, Lz, Lt = op.dims
+    out = torch.empty((4, Lt, Lz, Ly, Lx, 3, 3), dtype=torch.complex128, device=op.U_packed.device)
+    wilson_gauge_force(op.handle, _ptr(out), _ptr(x_packed), _ptr(mu_packed), project, _stream())
+    return out
+
+
 def wilson_multi_apply(descs, dagger, nrhs, stream):
     arr = (wl_multi_desc * len(descs))(*[wl_multi_desc(o, out, inp) for o, out, inp in descs])
     return _check(lib().wilson_multi_apply(arr, len(descs), int(dagger), nrhs, stream), "wilson_multi_apply")
@@ -218,6 +230,10 @@ def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0):
 # Largest stencil code variant per precision (see wl_set_launch in the header).
 MAX_VARIANT = {WL_F64: 1, WL_F32: 2, WL_BF16S: 3, WL_F16S: 3}
 MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
+
+
+def wl_stream_copy(dst, src, nbytes, stream):
+    return _check(lib().wl_stream_copy(dst, src, nbytes, stream), "wl_stream_copy")
 
 
 def wl_prof_enable(on):
@@ -365,26 +381,29 @@ def dslash(U, psi, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None):
 
 
 def solve(U, b, kappa, method="bicgstab", precision="f64", tol=1e-10, maxiter=10000, bc=(1, 1, 1, -1),
-          inner_tol=0.0, check_every=0, x0=None, ops=None, return_stats=False):
-    """x = D^{-1} b for canonical complex128 CUDA tensors.
+          inner_tol=0.0, check_every=0, x0=None, ops=None, return_stats=False, dagger=False, reliable=False):
+    """x = D^{-1} b (dagger: x = D^{-dag} b) for canonical complex128 CUDA tensors.
 
     precision: "f64" (plain FP64), "f32" (plain FP32), or "mixed-f32", "mixed-bf16",
-    "mixed-f16" (FP64 refinement around an inner solve with that storage)."""
+    "mixed-f16" (FP64 refinement around an inner solve with that storage).
+    ops: optional (hi, lo) Operators to reuse (lo None for a plain solve)."""
     torch = _torch()
     nrhs = None if b.dim() == 6 else int(b.shape[0])
     n = nrhs or 1
-    if precision.startswith("mixed-"):
+    if ops is not None:
+        hi, lo = ops
+    elif precision.startswith("mixed-"):
         lo_prec = PREC[precision.split("-", 1)[1]]
-        hi = ops[0] if ops else Operator.create(U, kappa, WL_F64, bc)
-        lo = ops[1] if ops else Operator.create(U, kappa, lo_prec, bc)
+        hi = Operator.create(U, kappa, WL_F64, bc)
+        lo = Operator.create(U, kappa, lo_prec, bc)
     else:
-        hi = ops[0] if ops else Operator.create(U, kappa, PREC[precision], bc)
+        hi = Operator.create(U, kappa, PREC[precision], bc)
         lo = None
     bp = hi.pack(b)
     xp = hi.pack(x0) if x0 is not None else hi.new_field(n)
-    prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=0,
-                          check_every=check_every, use_x0=1 if x0 is not None else 0, workspace=None,
-                          workspace_bytes=0)
+    prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=int(reliable),
+                          check_every=check_every, use_x0=1 if x0 is not None else 0, dagger=int(dagger),
+                          workspace=None, workspace_bytes=0)
     ws = wl_solver_workspace_bytes(hi.handle, lo.handle if lo else None, SOLVER[method], n)
     work = torch.empty(ws, dtype=torch.uint8, device=b.device)
     prm.workspace = work.data_ptr()
