@@ -42,6 +42,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(prec, dims):
+    """HBM bytes per launch of the stencil of `prec`, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy
+    calibration), or None if there is none or the kernel sources changed."""
+    from paper_1712_01505_amd import profiling
+    path = os.path.join(ROOT, "profiles", "traffic_stencil_%dx%dx%dx%d.json" % tuple(dims))
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != profiling.source_hash():
+        return None
+    tot, n = 0.0, 0
+    for k, v in d["kernels"].items():
+        if not k.startswith("wl::stencil_kernel<"):
+            continue
+        targs = [int(a) for a in k[k.index("<") + 1:k.index(">")].split(",")]
+        # <prec, dagger, rhs/thread, reduction, apply, variant>: the solver's
+        # stencils carry a fused reduction (the autotuner's candidates do not)
+        if targs[0] == prec and targs[3] != 0:
+            tot += v["hbm_bytes"] * v["dispatches"]
+            n += v["dispatches"]
+    return round(tot / n) if n else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,7 +159,8 @@ def main():
     bytes_per_launch = BYTES[dom] * V
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": f"stencil_kernel<{PNAME[dom]}> (wilson_apply)", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, dims),
                 "bytes_per_site": BYTES[dom], "sites_per_launch": V, "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": n_l}
 

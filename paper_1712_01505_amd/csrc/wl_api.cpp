@@ -171,14 +171,21 @@ static void save_tune_cache_locked()
 // Untuned defaults (measured on MI355X at 32^3 x 64): one right-hand side
 // runs the pipelined hop loop with small workgroups; several right-hand
 // sides share each link load across RHS_per_thread spinors.
-static LaunchCfg default_launch(int prec, int nrhs)
+static LaunchCfg default_launch(const wl_op *op, int nrhs)
 {
+    const int prec = op->prec;
     LaunchCfg c;
     if (nrhs == 1) {
         c.rpt = 1;
-        c.block = prec == WL_F64 || prec == WL_F32 ? 64 : 128;
-        c.xcd = prec == WL_F64 || prec == WL_F32 ? 0 : 1;
-        c.var = prec == WL_F64 ? 1 : 2;
+        if (prec == WL_F64 || prec == WL_F32) {
+            c.block = 256;
+            c.xcd = slab_ok(op->g.dims, 256) ? 2 : 0;
+            c.var = prec == WL_F64 ? 1 : 2;
+        } else {
+            c.block = 128;
+            c.xcd = 1;
+            c.var = 2;
+        }
         return c;
     }
     c.block = 256;
@@ -215,7 +222,7 @@ LaunchCfg launch_for(const wl_op *op, int nrhs)
         if (it != o->launch.end())
             return it->second;
     }
-    LaunchCfg c = default_launch(op->prec, nrhs);
+    LaunchCfg c = default_launch(op, nrhs);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_cache_locked();
@@ -539,7 +546,7 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
         e = hipEventCreate(&a);
     if (e == hipSuccess)
         e = hipEventCreate(&b);
-    LaunchCfg best = default_launch(op->prec, nrhs);
+    LaunchCfg best = default_launch(op, nrhs);
     float best_ms = INFINITY;
     const int blocks[] = {64, 128, 256, 512};
     std::vector<LaunchCfg> cands;

@@ -60,6 +60,8 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
     const int r = blockIdx.y;
     const uint32_t V = p.V;
     const int nr = p.nrhs;
+    if (p.skip_frozen && p.sc[r].frozen)  // whole workgroup: one column per blockIdx.y
+        return;
     double red[3] = {0.0, 0.0, 0.0};
     if (s < V) {
         const Scalars &sc = p.sc[r];
@@ -330,6 +332,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
             sc.flag = 3;
         else if (sc.rr <= sc.tol2 * sc.bb)
             sc.flag = 1;
+        sc.frozen = sc.flag != 0;
         break;
     }
     case F_CG_ALPHA: {
@@ -363,6 +366,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
                 sc.flag = 2;
         }
         sc.beta = zero;
+        sc.frozen = 1;  // end of the iteration with flag != 0
         break;
     }
     case F_INIT_BI: {
@@ -378,6 +382,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
             sc.flag = 3;
         else if (sc.rr <= sc.tol2 * sc.bb)
             sc.flag = 1;
+        sc.frozen = sc.flag != 0;
         break;
     }
     case F_BI_ALPHA: {
@@ -444,6 +449,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         sc.beta = zero;
         sc.alpha = zero;
         sc.omega = zero;
+        sc.frozen = 1;  // end of the iteration with flag != 0
         break;
     }
     default: break;

@@ -182,6 +182,31 @@ __device__ __forceinline__ void load_site(const void *base, uint32_t V, int nrhs
     }
 }
 
+// As load_site, but 16-bit formats return the stored (unit-range) values and
+// the site scale separately (sc = 1 for FP64/FP32).
+template <int P>
+__device__ __forceinline__ void load_site_unscaled(const void *base, uint32_t V, int nrhs, uint32_t s, int rhs,
+                                                   cx<typename Traits<P>::real> (&v)[12],
+                                                   typename Traits<P>::real &sc)
+{
+    if constexpr (Traits<P>::SCALED) {
+        const size_t off = (size_t)rhs * Traits<P>::NCH * V + s;
+        const uint4 *b = reinterpret_cast<const uint4 *>(base) + off;
+        sc = scale_ptr<P>(base, V, nrhs)[(size_t)rhs * V + s];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 d = b[(size_t)k * V];
+            v[4 * k + 0] = unpack2<P>(d.x);
+            v[4 * k + 1] = unpack2<P>(d.y);
+            v[4 * k + 2] = unpack2<P>(d.z);
+            v[4 * k + 3] = unpack2<P>(d.w);
+        }
+    } else {
+        load_site<P>(base, V, nrhs, s, rhs, v);
+        sc = typename Traits<P>::real(1);
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void store_site(void *base, uint32_t V, int nrhs, uint32_t s, int rhs,
                                            const cx<typename Traits<P>::real> (&v)[12])

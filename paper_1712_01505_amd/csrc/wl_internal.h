@@ -37,6 +37,8 @@ struct wl_op {
 
 namespace wl {
 
+struct Scalars;
+
 // Reduction requested from a kernel epilogue (partials [nval][nrhs][nblk]).
 enum Red {
     RED_NONE = 0,
@@ -64,6 +66,7 @@ struct StencilParams {
     // slab order (xcd == 2)
     FastDiv f_slab_n, f_slab_xy;
     uint32_t slab_n, slab_xy, vslice;
+    const struct Scalars *skip;  // in a solver loop: skip a workgroup whose columns are all frozen
 };
 
 // ---- stencil (wl_stencil.hip)
@@ -106,7 +109,8 @@ struct Scalars {
     double tol2;          // converge when rr <= tol2 * bb
     int flag;             // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
     int conv_iter;
-    int pad[2];
+    int frozen;           // set at the end of an iteration once flag != 0: loop kernels skip the column
+    int pad;
 };
 
 enum BlasOp {
@@ -129,6 +133,7 @@ struct BlasParams {
     uint32_t V;
     int nrhs;
     int nblk;
+    int skip_frozen;   // in a solver loop: skip frozen columns
 };
 hipError_t launch_blas(int prec, int op, const BlasParams &p, int block, hipStream_t st);
 int blas_nval(int op);

@@ -170,9 +170,10 @@ struct Engine {
         return WL_OK;
     }
 
-    int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot)
+    int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot, bool loop = false)
     {
         StencilParams p{};
+        p.skip = loop ? sc : nullptr;
         p.U = op->U;
         p.in = in;
         p.out = out;
@@ -200,9 +201,11 @@ struct Engine {
         return WL_OK;
     }
 
-    int blas(int bop, void *y0, void *y1, const void *a0, const void *a1, const void *a2, const void *a3, int slot)
+    int blas(int bop, void *y0, void *y1, const void *a0, const void *a1, const void *a2, const void *a3, int slot,
+             bool loop = false)
     {
         BlasParams p{};
+        p.skip_frozen = loop ? 1 : 0;
         p.y0 = y0;
         p.y1 = y1;
         p.a0 = a0;
@@ -327,17 +330,17 @@ struct Engine {
             WL_TRY(hipStreamSynchronize(st));
             bool stop = host_all_done();
             while (!stop && it < maxiter) {
-                if ((rc = stencil(w, p, 0, RED_NORM, nullptr, 0)))
+                if ((rc = stencil(w, p, 0, RED_NORM, nullptr, 0, true)))
                     return rc;
                 if ((rc = fin(F_CG_ALPHA, 0, -1, -1, it, tol2)))
                     return rc;
-                if ((rc = blas(B_CG_XR, x, r, p, w, nullptr, nullptr, 0)))
+                if ((rc = blas(B_CG_XR, x, r, p, w, nullptr, nullptr, 0, true)))
                     return rc;
-                if ((rc = stencil(z, r, 1, RED_NORM, nullptr, 1)))
+                if ((rc = stencil(z, r, 1, RED_NORM, nullptr, 1, true)))
                     return rc;
                 if ((rc = fin(F_CG_BETA, 0, 1, -1, it, tol2)))
                     return rc;
-                if ((rc = blas(B_CG_P, p, nullptr, z, nullptr, nullptr, nullptr, -1)))
+                if ((rc = blas(B_CG_P, p, nullptr, z, nullptr, nullptr, nullptr, -1, true)))
                     return rc;
                 if ((rc = mark(it, &stop)))
                     return rc;
@@ -356,19 +359,19 @@ struct Engine {
             WL_TRY(hipStreamSynchronize(st));
             bool stop = host_all_done();
             while (!stop && it < maxiter) {
-                if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1)))
+                if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1, true)))
                     return rc;
-                if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0)))
+                if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0, true)))
                     return rc;
                 if ((rc = fin(F_BI_ALPHA, 0, -1, -1, it, tol2)))
                     return rc;
-                if ((rc = blas(B_BI_S, s, nullptr, r, vv, nullptr, nullptr, 0)))
+                if ((rc = blas(B_BI_S, s, nullptr, r, vv, nullptr, nullptr, 0, true)))
                     return rc;
-                if ((rc = stencil(t, s, 0, RED_DOTIN_NORM, nullptr, 1)))
+                if ((rc = stencil(t, s, 0, RED_DOTIN_NORM, nullptr, 1, true)))
                     return rc;
                 if ((rc = fin(F_BI_OMEGA, 0, 1, -1, it, tol2)))
                     return rc;
-                if ((rc = blas(B_BI_XR, x, r, p, s, t, rh, 0)))
+                if ((rc = blas(B_BI_XR, x, r, p, s, t, rh, 0, true)))
                     return rc;
                 if ((rc = fin(F_BI_RHO, 0, -1, -1, it, tol2)))
                     return rc;

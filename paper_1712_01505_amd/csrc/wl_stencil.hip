@@ -123,10 +123,11 @@ __device__ __forceinline__ void hop_dir(const StencilParams &p, uint32_t s, int 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         cx<T> ps[12], h[6], g[6];
-        load_site<P>(p.in, p.V, p.nrhs, sf, r0 + r, ps);
+        T sc;
+        load_site_unscaled<P>(p.in, p.V, p.nrhs, sf, r0 + r, ps, sc);
         project<MU, SF>(ps, h);
         su3_mv(u, h, g);
-        accum<MU, SF>(acc[r], g, gf);
+        accum<MU, SF>(acc[r], g, gf * sc);
     }
     // with several right-hand sides per thread, keep the scheduler from
     // hoisting every neighbour load of the site (it would spill)
@@ -136,10 +137,11 @@ __device__ __forceinline__ void hop_dir(const StencilParams &p, uint32_t s, int 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         cx<T> ps[12], h[6], g[6];
-        load_site<P>(p.in, p.V, p.nrhs, sb, r0 + r, ps);
+        T sc;
+        load_site_unscaled<P>(p.in, p.V, p.nrhs, sb, r0 + r, ps, sc);
         project<MU, -SF>(ps, h);
         su3_adj_mv(u, h, g);
-        accum<MU, -SF>(acc[r], g, gb);
+        accum<MU, -SF>(acc[r], g, gb * sc);
     }
     if constexpr (R > 1)
         __builtin_amdgcn_sched_barrier(0);
@@ -288,10 +290,8 @@ __device__ __forceinline__ void decode(const RawHop<P> &r, cx<typename Traits<P>
         for (int k = 0; k < 3; ++k) {
             const uint32_t w[4] = {r.sp[k].x, r.sp[k].y, r.sp[k].z, r.sp[k].w};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const cx<float> a = unpack2<P>(w[j]);
-                ps[4 * k + j] = cx<float>{a.re * r.sc, a.im * r.sc};
-            }
+            for (int j = 0; j < 4; ++j)
+                ps[4 * k + j] = unpack2<P>(w[j]);  // site scale applied in the accumulate
             u[2 * k] = unpack2<P>(r.lk[k].x);
             u[2 * k + 1] = unpack2<P>(r.lk[k].y);
         }
@@ -321,7 +321,12 @@ __device__ __forceinline__ void compute_hop(const RawHop<P> &r, float sg, cx<typ
         su3_mv(u, h, g);
     else
         su3_adj_mv(u, h, g);
-    accum<MU, SIG>(acc, g, (T)sg);
+    // the hop is linear in the neighbour spinor, so a 16-bit site's scale
+    // multiplies the accumulate coefficient instead of its 24 components
+    if constexpr (Traits<P>::SCALED)
+        accum<MU, SIG>(acc, g, (T)sg * r.sc);
+    else
+        accum<MU, SIG>(acc, g, (T)sg);
 }
 
 template <int P, int G, int H>
@@ -401,6 +406,14 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
                                               p.slab_n, p.vslice)
                                   : tile_of(blockIdx.x, gridDim.x, p.xcd) * blockDim.x + threadIdx.x;
     const int r0 = blockIdx.y * R;
+    if (p.skip) {  // solver loop: every column of this workgroup has stopped
+        bool all = true;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            all = all && p.skip[r0 + r].frozen;
+        if (all)
+            return;
+    }
     const bool active = s < p.V;
     double red[(NV > 0 ? NV : 1) * R];
 #pragma unroll
