@@ -66,6 +66,121 @@ def measured_traffic(prec, dims):
     return round(tot / n) if n else None
 
 
+def _time_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batching(W, inputs, torch, log):
+    """24^3 x 48 with the 12 point sources (one per spin-colour at the origin):
+    multi-RHS FP32 stencil vs one right-hand side at a time, and the batched
+    mixed-precision solve vs 12 sequential solves; plus one persistent launch
+    over the uneven lattices {8^4, 12^4, 16^3x32, 20^4} x 4 sources vs separate
+    launches."""
+    out = {}
+    dims = (24, 24, 24, 48)
+    V = inputs.volume(dims)
+    kappa = 0.12
+    log(f"[bench] batching: generating {dims}")
+    Ud = torch.from_numpy(inputs.near_unity_gauge(dims, 0.3, seed=inputs.GAUGE_SEED)).cuda()
+    src = torch.from_numpy(inputs.point_sources_all_spin_colour(dims)).cuda()
+    hi = W.Operator.create(Ud, kappa, W.WL_F64)
+    lo = W.Operator.create(Ud, kappa, W.WL_F32)
+    del Ud
+    st = W._stream()
+    W.wl_autotune(lo.handle, 12, 0, st)
+    W.wl_autotune(lo.handle, 1, 0, st)
+    s12 = lo.pack(src)
+    d12 = lo.new_field(12)
+    ms12 = _time_ms(torch, lambda: lo.apply_packed(d12, s12, 12), 10)
+    s1 = lo.pack(src[0])
+    d1 = lo.new_field(1)
+    ms1 = _time_ms(torch, lambda: lo.apply_packed(d1, s1, 1), 10)
+    bytes12 = (2 * 96 + 4 * 48 / 12) * V * 12
+    out["multi_rhs_stencil_f32"] = {
+        "nrhs": 12, "launch": W.wl_get_launch(lo.handle, 12), "us": round(ms12 * 1e3, 1),
+        "us_per_rhs": round(ms12 * 1e3 / 12, 1), "single_rhs_us": round(ms1 * 1e3, 1),
+        "speedup_vs_12_single": round(12 * ms1 / ms12, 3),
+        "GFLOP/s": round(1368 * V * 12 / (ms12 * 1e-3) / 1e9, 1),
+        "GB/s": round(bytes12 / (ms12 * 1e-3) / 1e9, 1), "bytes_per_site_per_rhs": 208}
+    log(f"[bench] multi-RHS stencil: {out['multi_rhs_stencil_f32']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, sts = W.solve(None, src, kappa, method="bicgstab", precision="mixed-f32", tol=1e-10, ops=(hi, lo),
+                     return_stats=True)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    iters = []
+    for k in range(12):
+        _, s_k = W.solve(None, src[k], kappa, method="bicgstab", precision="mixed-f32", tol=1e-10, ops=(hi, lo),
+                         return_stats=True)
+        iters.append(s_k["iters"])
+    t_seq = time.perf_counter() - t0
+    out["batched_solve"] = {"nrhs": 12, "precision": "mixed-f32", "seconds": round(t_batch, 4),
+                            "sequential_seconds": round(t_seq, 4), "speedup": round(t_seq / t_batch, 3),
+                            "max_true_rel_res": max(x["true_rel_res"] for x in sts),
+                            "iters": [x["iters"] for x in sts], "sequential_iters": iters}
+    log(f"[bench] batched solve: {out['batched_solve']}")
+    del hi, lo, src, s12, d12, s1, d1
+    torch.cuda.empty_cache()
+    # uneven lattices in one persistent launch
+    lattices = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (20, 20, 20, 20)]
+    ops, srcs, dsts = [], [], []
+    for j, dj in enumerate(lattices):
+        op = W.Operator.create(torch.from_numpy(inputs.near_unity_gauge(dj, 0.3, seed=10 + j)).cuda(), kappa, W.WL_F32)
+        srcs.append(op.pack(torch.from_numpy(inputs.gaussian_spinor(dj, seed=100 * j, nrhs=4)).cuda()))
+        dsts.append(op.new_field(4))
+        ops.append(op)
+    descs = [(o.handle, d.data_ptr(), s_.data_ptr()) for o, d, s_ in zip(ops, dsts, srcs)]
+    ms_multi = _time_ms(torch, lambda: W.wilson_multi_apply(descs, 0, 4, st), 10)
+
+    def separate():
+        for o, d, s_ in zip(ops, dsts, srcs):
+            o.apply_packed(d, s_, 4)
+    ms_sep = _time_ms(torch, separate, 10)
+    Vt = sum(inputs.volume(d) for d in lattices)
+    out["multi_lattice_f32"] = {"lattices": [list(d) for d in lattices], "nrhs": 4, "V_total": Vt,
+                                "one_launch_us": round(ms_multi * 1e3, 1), "separate_launches_us": round(ms_sep * 1e3, 1),
+                                "speedup": round(ms_sep / ms_multi, 3),
+                                "GFLOP/s": round(1368 * Vt * 4 / (ms_multi * 1e-3) / 1e9, 1)}
+    log(f"[bench] multi-lattice: {out['multi_lattice_f32']}")
+    return out
+
+
+def bench_autograd(W, inputs, torch, log):
+    """Differentiable solve at 16^3 x 32, kappa 0.12: L = ||D^{-1} b||^2,
+    forward (mixed FP32/FP64) + backward (adjoint solve + link force)."""
+    from paper_1712_01505_amd.autograd import wilson_solve
+    dims = (16, 16, 16, 32)
+    U = torch.from_numpy(inputs.near_unity_gauge(dims, 0.3, seed=inputs.GAUGE_SEED)).cuda().requires_grad_(True)
+    b = torch.from_numpy(inputs.gaussian_spinor(dims, seed=inputs.SOURCE_SEED)).cuda().requires_grad_(True)
+
+    def step():
+        U.grad = None
+        b.grad = None
+        x = wilson_solve(U, b, 0.12, precision="mixed-f32", tol=1e-10)
+        (x.abs() ** 2).sum().backward()
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    r = {"dims": list(dims), "kappa": 0.12, "forward_plus_backward_s": round(dt, 4),
+         "grad_b_norm": float(b.grad.abs().pow(2).sum().sqrt()), "grad_U_norm": float(U.grad.abs().pow(2).sum().sqrt())}
+    log(f"[bench] differentiable solve: {r}")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,8 +188,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dims", type=str, default="32,32,32,64")
     ap.add_argument("--inner", type=str, default="f16", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--reliable", type=int, default=0, choices=[0, 1],
+                    help="timed solve: 1 = reliable updates, 0 = defect correction")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and check")
     ap.add_argument("--no-extra", action="store_true", help="skip the measurements outside the timed region")
+    ap.add_argument("--no-batch", action="store_true", help="skip the multi-RHS / multi-lattice / autograd extras")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -109,8 +227,9 @@ def main():
                    for lo in [None] + [ops[p].handle for p in (1, 2, 3)] for s in (0, 1))
     work = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
-    def run_solve(method, lo_prec):
-        prm = W.wl_solve_params(tol=tol, maxiter=20000, inner_tol=0.0, max_outer=0, reliable=0, check_every=0,
+    def run_solve(method, lo_prec, reliable=args.reliable):
+        prm = W.wl_solve_params(tol=tol, maxiter=20000, inner_tol=0.0, max_outer=0, reliable=int(reliable),
+                                check_every=0,
                                 use_x0=0, workspace=work.data_ptr(), workspace_bytes=ws_bytes)
         st = (W.wl_solve_stats * 1)()
         fn = W.solve_cgnr if method == "cgnr" else W.solve_bicgstab
@@ -172,7 +291,7 @@ def main():
         "config": {"workload": f"wilson-dirac mixed-precision BiCGStab solve, {dims[0]}^3x{dims[3]}"
                    if dims[0] == dims[1] == dims[2] else f"wilson-dirac solve {dims}",
                    "dims": list(dims), "kappa": kappa, "eps": eps, "bc": [1, 1, 1, -1], "tol": tol,
-                   "inner": args.inner, "value_counts": "1368 flop/site x stencil applications per step / step time"},
+                   "inner": args.inner, "reliable_updates": bool(args.reliable), "value_counts": "1368 flop/site x stencil applications per step / step time"},
         "launch": tuned,
         "solve_step": {"iters": last["iters"], "outer": last["outer"], "stencil_calls": last["stencil_calls"],
                        "true_rel_res": last["true_rel_res"], "seconds": round(ms_per_step / 1e3, 4)},
@@ -203,13 +322,14 @@ def main():
             log(f"[bench] apply {PNAME[p]}: {dsl[PNAME[p]]}")
         result["dslash"] = dsl
         solves = {}
-        for method, lo in (("bicgstab", None), ("cgnr", None), ("bicgstab", W.WL_F32), ("bicgstab", W.WL_BF16S),
-                           ("bicgstab", W.WL_F16S), ("cgnr", W.WL_F16S)):
+        for method, lo, rel in (("bicgstab", None, 0), ("cgnr", None, 0), ("bicgstab", W.WL_F32, 0),
+                                ("bicgstab", W.WL_BF16S, 0), ("bicgstab", W.WL_F16S, 0), ("cgnr", W.WL_F16S, 0),
+                                ("bicgstab", W.WL_F32, 1), ("bicgstab", W.WL_BF16S, 1), ("bicgstab", W.WL_F16S, 1)):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            code, st = run_solve(method, lo)
+            code, st = run_solve(method, lo, rel)
             dt = time.perf_counter() - t1
-            key = f"{method}_{'f64' if lo is None else 'mixed_' + PNAME[lo]}"
+            key = f"{method}_{'f64' if lo is None else 'mixed_' + PNAME[lo]}{'_reliable' if rel else ''}"
             solves[key] = {"seconds": round(dt, 4), "status": code, "iters": st["iters"], "outer": st["outer"],
                            "true_rel_res": st["true_rel_res"]}
             log(f"[bench] solve {key}: {solves[key]}")
@@ -217,6 +337,12 @@ def main():
         for k, v in solves.items():
             v["speedup_vs_bicgstab_f64"] = round(base / v["seconds"], 3)
         result["solves"] = solves
+
+    if not args.no_extra and not args.no_batch:
+        del ops, hi, b64, x64, work
+        torch.cuda.empty_cache()
+        result["batching"] = bench_batching(W, inputs, torch, log)
+        result["differentiable"] = bench_autograd(W, inputs, torch, log)
 
     if not args.no_cpu:
         import oracle

@@ -124,9 +124,13 @@ int wilson_apply(const wl_op *op, void *out, const void *in, int dagger, int nrh
 typedef struct {
     double tol;           /* stop when ||b - D x|| <= tol ||b|| (true residual, FP64) */
     int maxiter;          /* Krylov iterations (summed over inner solves when mixed) */
-    double inner_tol;     /* mixed: relative tolerance of each inner solve (0 = default) */
+    double inner_tol;     /* mixed: defect correction: relative tolerance of each inner solve;
+                             reliable updates: residual drop that triggers an FP64 update
+                             (0 = default: 1e-5 FP32 / 3e-2 16-bit; 0.1 for reliable updates) */
     int max_outer;        /* mixed: maximum outer (refinement) cycles (0 = default 50) */
-    int reliable;         /* mixed: 0 = restart inner solve per cycle, 1 = reliable updates */
+    int reliable;         /* mixed BiCGStab: 0 = defect correction (restart the inner solve per
+                             cycle), 1 = reliable updates (one inner run, FP64 solution and
+                             residual refreshed in place).  Ignored by CGNR. */
     int check_every;      /* host convergence check period in iterations (0 = default) */
     int use_x0;           /* 1 = x holds the initial guess on entry, 0 = start from x = 0 */
     int dagger;           /* 1 = solve D^dag x = b (the adjoint system; D^dag = gamma5 D gamma5) */
@@ -136,7 +140,7 @@ typedef struct {
 
 typedef struct {
     int iters;            /* Krylov iterations performed for this right-hand side */
-    int outer;            /* outer refinement cycles (mixed) */
+    int outer;            /* mixed: FP64 residual refreshes (refinement cycles + reliable updates) */
     int stencil_calls;    /* stencil applications (all precisions) */
     int converged;        /* 1 if the final true relative residual <= tol */
     double iter_rel_res;  /* final iterated (recursive) relative residual */

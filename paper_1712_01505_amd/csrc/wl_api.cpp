@@ -210,7 +210,8 @@ static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
     const int prec = op->prec;
     return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
            nrhs % c.rpt == 0 && c.xcd >= 0 && c.xcd <= 2 && (c.xcd != 2 || slab_ok(op->g.dims, c.block)) &&
-           c.var >= 0 && c.var <= max_var(prec) && (c.var == 0 || c.rpt == 1);
+           c.var >= 0 && c.var <= max_var(prec) && var_ok(prec, c.var) && (c.var == 0 || c.rpt == 1) &&
+           (c.var < 4 || op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0);
 }
 
 LaunchCfg launch_for(const wl_op *op, int nrhs)
@@ -253,6 +254,7 @@ static StencilParams base_params(const wl_op *op, void *out, const void *in, int
     p.kappa = op->kappa;
     p.apply = apply;
     p.red = RED_NONE;
+    p.one = 1.0f;
     return p;
 }
 

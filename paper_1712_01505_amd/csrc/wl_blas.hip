@@ -157,9 +157,17 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             cx<T> v[12];
             load_site<P>(p.a0, V, nr, s, r, v);
             red[0] = n2(v);
+        } else if constexpr (OP == B_DOT_NORM) {
+            cx<T> a[12], b[12];
+            load_site<P>(p.a0, V, nr, s, r, a);
+            load_site<P>(p.a1, V, nr, s, r, b);
+            dot(a, b, red[0], red[1]);
+            red[2] = n2(b);
         }
     }
-    constexpr int NV = (OP == B_RES || OP == B_CG_XR || OP == B_BI_S || OP == B_NORM) ? 1 : OP == B_BI_XR ? 3 : 0;
+    constexpr int NV = (OP == B_RES || OP == B_CG_XR || OP == B_BI_S || OP == B_NORM) ? 1
+                       : (OP == B_BI_XR || OP == B_DOT_NORM)                          ? 3
+                                                                                       : 0;
     if constexpr (NV > 0) {
         block_sum<3>(red, lds);
         if (threadIdx.x == 0) {
@@ -174,7 +182,7 @@ int blas_nval(int op)
 {
     switch (op) {
     case B_RES: case B_CG_XR: case B_BI_S: case B_NORM: return 1;
-    case B_BI_XR: return 3;
+    case B_BI_XR: case B_DOT_NORM: return 3;
     default: return 0;
     }
 }
@@ -192,6 +200,7 @@ static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hip
     case B_COPY: hipLaunchKernelGGL((blas_kernel<P, B_COPY>), g, b, 0, st, p); break;
     case B_ZERO: hipLaunchKernelGGL((blas_kernel<P, B_ZERO>), g, b, 0, st, p); break;
     case B_NORM: hipLaunchKernelGGL((blas_kernel<P, B_NORM>), g, b, 0, st, p); break;
+    case B_DOT_NORM: hipLaunchKernelGGL((blas_kernel<P, B_DOT_NORM>), g, b, 0, st, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -251,9 +260,10 @@ hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e,
 // arrays in a fixed order and then runs the scalar recurrence per column.
 // Rows are summed G at a time; each thread keeps 8 independent loads in
 // flight per row, so a pass costs about one memory latency.
-constexpr int FIN_THREADS = 512;
+constexpr int FIN_THREADS = 1024;
 constexpr int FIN_MAX = 3 * 64;  // values x right-hand sides per partial set
-constexpr int FIN_G = 4;
+constexpr int FIN_G = 2;         // rows summed per pass
+constexpr int FIN_U = 16;        // independent loads per thread per row and pass
 
 __device__ __forceinline__ bool finite2(double a) { return isfinite(a); }
 
@@ -284,19 +294,28 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         double v[FIN_G];
 #pragma unroll
         for (int g = 0; g < FIN_G; ++g) {
-            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            double a[FIN_U];
+#pragma unroll
+            for (int j = 0; j < FIN_U; ++j)
+                a[j] = 0.0;
             if (c0 + g < ncomb) {
                 const RowRef row = fin_row(p, c0 + g);
-                for (int base = 0; base < row.n; base += 8 * FIN_THREADS) {
+                for (int base = 0; base < row.n; base += FIN_U * FIN_THREADS) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
+                    for (int j = 0; j < FIN_U; ++j) {
                         const int i = base + j * FIN_THREADS + threadIdx.x;
                         if (i < row.n)
                             a[j] += row.p[i];
                     }
                 }
             }
-            v[g] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+            // fixed pairwise order
+#pragma unroll
+            for (int w = FIN_U / 2; w > 0; w >>= 1)
+#pragma unroll
+                for (int j = 0; j < w; ++j)
+                    a[j] += a[j + w];
+            v[g] = a[0];
         }
         block_sum<FIN_G>(v, lds);
         if (threadIdx.x == 0) {
@@ -324,7 +343,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         sc.rr = sA[r];
         sc.zz = sB[r];
         sc.bb = sC[r];
-        sc.tol2 = p.tol2;
+        sc.tol2 = p.tol2v ? p.tol2v[r] : p.tol2;
         sc.alpha = sc.beta = zero;
         sc.flag = 0;
         sc.conv_iter = 0;
@@ -372,8 +391,9 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
     case F_INIT_BI: {
         sc.rr = sA[r];
         sc.bb = sC[r];
-        sc.tol2 = p.tol2;
-        sc.rho = make_double2(sc.rr, 0.0);  // <rh, r0> with rh = r0
+        sc.tol2 = p.tol2v ? p.tol2v[r] : p.tol2;
+        sc.rho = make_double2(sc.rr, 0.0);
+        sc.rho_prev = sc.rho;  // <rh, r0> with rh = r0
         sc.alpha = sc.omega = one;
         sc.beta = zero;  // p = v = 0 -> first p = r
         sc.flag = 0;
@@ -439,6 +459,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
                 const double2 q2 = make_double2((sc.alpha.x * sc.omega.x + sc.alpha.y * sc.omega.y) / om2,
                                                 (sc.alpha.y * sc.omega.x - sc.alpha.x * sc.omega.y) / om2);
                 sc.beta = make_double2(q1.x * q2.x - q1.y * q2.y, q1.x * q2.y + q1.y * q2.x);
+                sc.rho_prev = sc.rho;
                 sc.rho = rho_new;
                 break;
             } else
@@ -450,6 +471,37 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         sc.alpha = zero;
         sc.omega = zero;
         sc.frozen = 1;  // end of the iteration with flag != 0
+        break;
+    }
+    case F_BI_RELIABLE: {
+        // r was just replaced by the (converted) true residual; recompute
+        // rho = <rh, r> and beta = (rho / rho_prev)(alpha / omega) from it
+        if (sc.flag == 0) {
+            const double rr = sA[2 * nr + r];
+            const double2 rho_new = make_double2(sA[r], sA[nr + r]);
+            const double om2 = sc.omega.x * sc.omega.x + sc.omega.y * sc.omega.y;
+            const double rp2 = sc.rho_prev.x * sc.rho_prev.x + sc.rho_prev.y * sc.rho_prev.y;
+            sc.rr = rr;
+            if (!finite2(rr) || !finite2(rho_new.x) || !finite2(rho_new.y)) {
+                sc.flag = 3;
+            } else if (rr <= sc.tol2 * sc.bb) {
+                sc.flag = 1;
+                sc.conv_iter = p.iter + 1;
+            } else if (om2 > 0.0 && rp2 > 0.0 && (rho_new.x != 0.0 || rho_new.y != 0.0)) {
+                const double2 q1 = make_double2((rho_new.x * sc.rho_prev.x + rho_new.y * sc.rho_prev.y) / rp2,
+                                                (rho_new.y * sc.rho_prev.x - rho_new.x * sc.rho_prev.y) / rp2);
+                const double2 q2 = make_double2((sc.alpha.x * sc.omega.x + sc.alpha.y * sc.omega.y) / om2,
+                                                (sc.alpha.y * sc.omega.x - sc.alpha.x * sc.omega.y) / om2);
+                sc.beta = make_double2(q1.x * q2.x - q1.y * q2.y, q1.x * q2.y + q1.y * q2.x);
+                sc.rho = rho_new;
+            } else {
+                sc.flag = 2;
+            }
+            if (sc.flag != 0) {
+                sc.alpha = sc.beta = sc.omega = zero;
+                sc.frozen = 1;
+            }
+        }
         break;
     }
     default: break;

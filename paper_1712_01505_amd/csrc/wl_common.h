@@ -243,6 +243,38 @@ __device__ __forceinline__ void store_site(void *base, uint32_t V, int nrhs, uin
     }
 }
 
+// Store a site and replace v by exactly what was stored (16-bit formats
+// quantise once: site maximum, scale, round to nearest even).
+template <int P>
+__device__ __forceinline__ void store_site_q(void *base, uint32_t V, int nrhs, uint32_t s, int rhs,
+                                             cx<typename Traits<P>::real> (&v)[12])
+{
+    if constexpr (Traits<P>::SCALED) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        const size_t off = (size_t)rhs * 3 * V + s;
+        uint4 *b = reinterpret_cast<uint4 *>(base) + off;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                w[j] = pack2<P>(v[4 * k + j].re * inv, v[4 * k + j].im * inv);
+                const cx<float> q = unpack2<P>(w[j]);
+                v[4 * k + j] = cx<float>{q.re * m, q.im * m};
+            }
+            b[(size_t)k * V] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        float *scp = const_cast<float *>(scale_ptr<P>(base, V, nrhs));
+        scp[(size_t)rhs * V + s] = m;
+    } else {
+        store_site<P>(base, V, nrhs, s, rhs, v);
+    }
+}
+
 // Load the two stored rows of U_mu(s) and rebuild row 2 = conj(row0 x row1)
 // (valid for SU(3): unitary with det 1).  u[3*row + col].
 template <int P>

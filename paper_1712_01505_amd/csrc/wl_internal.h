@@ -67,6 +67,7 @@ struct StencilParams {
     FastDiv f_slab_n, f_slab_xy;
     uint32_t slab_n, slab_xy, vslice;
     const struct Scalars *skip;  // in a solver loop: skip a workgroup whose columns are all frozen
+    float one;                   // 1.0 (see project())
 };
 
 // ---- stencil (wl_stencil.hip)
@@ -74,6 +75,8 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
 int stencil_nval(int red);
 int max_rpt(int prec);  // largest right-hand sides per thread the stencil offers
 int max_var(int prec);  // largest stencil code variant for R = 1
+bool var_ok(int prec, int var);  // variant exists for this precision
+int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V);  // partials written by one launch
 bool slab_ok(const int *L, int block);  // slab order usable for these extents and block size
 
 struct MultiEntry {
@@ -106,6 +109,7 @@ struct Scalars {
     double zz;            // CGNR |z|^2
     double ss;            // BiCGStab |s|^2
     double2 alpha, beta, omega, rho;
+    double2 rho_prev;     // BiCGStab: rho before the last F_BI_RHO (for reliable updates)
     double tol2;          // converge when rr <= tol2 * bb
     int flag;             // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
     int conv_iter;
@@ -122,7 +126,8 @@ enum BlasOp {
     B_BI_XR = 5,      // x += alpha p + omega s ; r = s - omega t ; |r|^2, <rh, r>  (a3 = rh)
     B_COPY = 6,       // y = x
     B_ZERO = 7,       // y = 0
-    B_NORM = 8        // |x|^2
+    B_NORM = 8,       // |x|^2
+    B_DOT_NORM = 9    // <a0, a1> and |a1|^2  (3 values)
 };
 struct BlasParams {
     void *y0;          // first output / in-out vector
@@ -150,7 +155,9 @@ enum FinOp {
     F_BI_ALPHA = 4,   // vals: <rh, v>
     F_BI_OMEGA = 5,   // vals: |s|^2 (A), <s,t>, |t|^2 (B)
     F_BI_RHO = 6,     // vals: |r|^2, <rh, r> (A)
-    F_SUM = 7         // just reduce set A into out[] (nval x nrhs)
+    F_SUM = 7,        // just reduce set A into out[] (nval x nrhs)
+    F_BI_RELIABLE = 8 // after a reliable update replaced r: A = (<rh, r>, |r|^2) -> rr,
+                      // convergence, rho and beta = (rho'/rho_prev)(alpha/omega)
 };
 struct FinParams {
     const double *A;
@@ -165,6 +172,7 @@ struct FinParams {
     int nrhs;
     int iter;
     double tol2;
+    const double *tol2v;  // optional per-column tol2 for the F_INIT_* ops (overrides tol2)
 };
 hipError_t launch_finalize(int op, const FinParams &p, hipStream_t st);
 hipError_t launch_scalars_init(Scalars *sc, int nrhs, double tol2, hipStream_t st);

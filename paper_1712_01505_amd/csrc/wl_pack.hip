@@ -129,22 +129,28 @@ __global__ void fill_u32_kernel(unsigned *p, unsigned v, int n)
         p[i] = v;
 }
 
-// Plain streaming copy, 4 x 16 bytes per thread per pass (bandwidth and
-// byte-counter calibration: it reads and writes exactly `n16` 16-byte units).
-__global__ __launch_bounds__(256) void stream_copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+// Plain streaming copy (bandwidth and byte-counter calibration: it reads and
+// writes exactly `n16` 16-byte units).  A large grid, 4 units per thread per
+// pass and non-temporal loads/stores: the fastest plain copy measured on
+// MI355X (about 6.1 TB/s read + write).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void stream_copy_kernel(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
                                                           size_t n16)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i + 3 * stride < n16; i += 4 * stride) {
-        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
+        const u32x4 a = __builtin_nontemporal_load(src + i);
+        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
     }
     for (; i < n16; i += stride)
-        dst[i] = src[i];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
@@ -152,12 +158,12 @@ hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStrea
     const size_t n16 = bytes / 16;
     const int B = 256;
     size_t blocks = (n16 + 4 * B - 1) / (4 * B);
-    if (blocks > 65536)
-        blocks = 65536;
+    if (blocks > (1u << 20))
+        blocks = 1u << 20;
     if (blocks < 1)
         blocks = 1;
-    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(B), 0, st, (uint4 *)dst, (const uint4 *)src,
-                       n16);
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(B), 0, st, (u32x4 *)dst,
+                       (const u32x4 *)src, n16);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <vector>
 
@@ -36,9 +37,14 @@ size_t align_up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
 
 size_t vec_bytes(int prec, uint32_t V, int nrhs) { return (size_t)nrhs * V * spinor_site_bytes(prec); }
 
-// Largest number of per-workgroup partials any kernel here produces.
-size_t max_nblk(uint32_t V) { return (V + 63) / 64; }
-size_t partial_bytes(uint32_t V, int nrhs) { return align_up(3 * (size_t)nrhs * max_nblk(V) * sizeof(double)); }
+// Largest number of per-workgroup partials any kernel here produces (the
+// t-walk stencil writes at most one per 64 (x,y,z) sites per t-column step,
+// i.e. at most V/64 + Lt).
+size_t max_nblk(uint32_t V, int Lt) { return (V + 63) / 64 + (size_t)Lt; }
+size_t partial_bytes(uint32_t V, int Lt, int nrhs)
+{
+    return align_up(3 * (size_t)nrhs * max_nblk(V, Lt) * sizeof(double));
+}
 
 struct Arena {
     char *base;
@@ -55,10 +61,10 @@ struct Arena {
 };
 
 // Bytes of one Krylov engine for op precision `prec`.
-size_t engine_bytes(int solver, int prec, uint32_t V, int nrhs)
+size_t engine_bytes(int solver, int prec, uint32_t V, int Lt, int nrhs)
 {
     const int nvec = solver == WL_SOLVER_CGNR ? 4 : 6;
-    return nvec * align_up(vec_bytes(prec, V, nrhs)) + 3 * partial_bytes(V, nrhs) +
+    return nvec * align_up(vec_bytes(prec, V, nrhs)) + 3 * partial_bytes(V, Lt, nrhs) +
            align_up(sizeof(Scalars) * nrhs) + align_up(sizeof(double) * 3 * nrhs);
 }
 
@@ -145,6 +151,10 @@ struct Engine {
     int lookahead = 2;
     int adj = 0;  // solving with D^dag: every stencil's dagger flag is flipped
     int stencil_calls = 0;
+    const double *tol2v = nullptr;  // optional per-column tolerance^2 (device)
+    // Called after each queued BiCGStab iteration that did not stop the run
+    // (the reliable-update check of the mixed solver).
+    std::function<int(int)> on_iter;
 
     int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, HostBufs *h)
     {
@@ -161,7 +171,7 @@ struct Engine {
             if (!(v[i] = a.take(vec_bytes(prec, V, nrhs))))
                 return WL_EWORKSPACE;
         for (int i = 0; i < 3; ++i)
-            if (!(part[i] = (double *)a.take(partial_bytes(V, nrhs))))
+            if (!(part[i] = (double *)a.take(partial_bytes(V, o->g.dims[3], nrhs))))
                 return WL_EWORKSPACE;
         if (!(sc = (Scalars *)a.take(sizeof(Scalars) * nrhs)))
             return WL_EWORKSPACE;
@@ -193,7 +203,7 @@ struct Engine {
         p.red = red;
         LaunchCfg cfg = launch_for(op, nrhs);
         if (slot >= 0) {
-            nblk[slot] = (int)((V + cfg.block - 1) / cfg.block);
+            nblk[slot] = stencil_partials(cfg, p.L, V);
             nval[slot] = stencil_nval(red);
         }
         ++stencil_calls;
@@ -249,6 +259,7 @@ struct Engine {
         p.nrhs = nrhs;
         p.iter = iter;
         p.tol2 = tol2;
+        p.tol2v = tol2v;
         WL_TRY(launch_finalize(fop, p, st));
         return WL_OK;
     }
@@ -376,6 +387,8 @@ struct Engine {
                 if ((rc = fin(F_BI_RHO, 0, -1, -1, it, tol2)))
                     return rc;
                 if ((rc = mark(it, &stop)))
+                    return rc;
+                if (!stop && on_iter && (rc = on_iter(it)))
                     return rc;
                 ++it;
             }
@@ -507,7 +520,18 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
 }
 
 // Mixed precision: FP64 outer true-residual refinement around an inner solve
-// in lo's precision (restarted each cycle: defect correction).
+// in lo's precision.  Two forms (Sec. II-C names mixed precision without
+// fixing one):
+//  * defect correction (reliable = 0): each cycle solves D e = r/|r| to the
+//    relative tolerance delta from e = 0, then x += |r| e;
+//  * reliable updates (reliable = 1, BiCGStab): one inner Krylov run is
+//    continued across cycles.  Whenever the iterated low-precision residual
+//    has fallen by delta below its largest value since the last update, the
+//    partial solution is folded into x (FP64), the residual is recomputed as
+//    b - D x in FP64 and replaces the iterated one, and rho, beta are
+//    re-derived from it (Sleijpen & van der Vorst's reliable updates).  The
+//    inner run then stops on the global tolerance; the outer loop confirms
+//    it with a last FP64 residual.  CGNR ignores the flag (defect correction).
 int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
                 const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena)
 {
@@ -526,23 +550,75 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     void *r_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
     void *e_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
     double *sig_dev = (double *)arena.take(sizeof(double) * nrhs);
-    if (!r_lo || !e_lo || !sig_dev)
+    double *tol2_dev = (double *)arena.take(sizeof(double) * nrhs);
+    if (!r_lo || !e_lo || !sig_dev || !tol2_dev)
         return WL_EWORKSPACE;
     H.lookahead = L.lookahead = lookahead_of(prm);
-    double *bb = lease.b->d, *rr = lease.b->d + nrhs, *sig = lease.b->d + 2 * nrhs;
+    double *bb = lease.b->d, *rr = lease.b->d + nrhs, *sig = lease.b->d + 2 * nrhs, *t2 = lease.b->d + 3 * nrhs;
     if ((rc = H.norm2(b, bb)))
         return rc;
     if (!prm->use_x0)
         if ((rc = H.blas(B_ZERO, x, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
             return rc;
     const double tol = prm->tol;
-    const double delta = prm->inner_tol > 0 ? prm->inner_tol : (lo->prec == WL_F32 ? 1e-5 : 3e-2);
+    const bool reliable = prm->reliable && solver == WL_SOLVER_BICGSTAB;
+    const double delta = prm->inner_tol > 0 ? prm->inner_tol
+                         : reliable        ? 0.1
+                         : lo->prec == WL_F32 ? 1e-5
+                                              : 3e-2;
     const int max_outer = prm->max_outer > 0 ? prm->max_outer : 50;
     std::vector<int> iters(nrhs, 0);
-    std::vector<double> prev(nrhs, INFINITY), best(nrhs, INFINITY);
+    std::vector<double> best(nrhs, INFINITY), rmax(nrhs, 0.0);
     std::vector<int> stall(nrhs, 0);
-    int total = 0, outer = 0, worst_flag = 0;
+    int total = 0, outer = 0, updates = 0, worst_flag = 0, next_read = 0;
     bool stagnated = false;
+    if (reliable) {
+        // the inner run's stopping rule is the global one, in units of the
+        // scaled system (|r_lo|^2 ~ 1 at the start of a cycle); 0.8 leaves
+        // room for the rounding of the iterated residual
+        L.tol2v = tol2_dev;
+        const double d2 = delta * delta;
+        L.on_iter = [&](int it) -> int {
+            if (it < next_read)
+                return WL_OK;
+            const volatile int *hf = lease.b->hflag;
+            const volatile double *hr = lease.b->hrr;
+            bool need = false;
+            for (int r = 0; r < nrhs; ++r) {
+                if (hf[r] != 0)
+                    continue;
+                const double v = hr[r];
+                if (v > rmax[r])
+                    rmax[r] = v;
+                else if (v < d2 * rmax[r])
+                    need = true;
+            }
+            if (!need)
+                return WL_OK;
+            int e;
+            // x64 += sigma e ; e = 0 ; r64 = b - D64 x ; r_lo = r64 / sigma
+            WL_TRY(launch_accum(lo->prec, hi->V, nrhs, x, e_lo, sig_dev, 1, st));
+            if ((e = L.blas(B_ZERO, e_lo, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+                return e;
+            if ((e = H.stencil(H.v[1], x, 0, RED_NONE, nullptr, -1)))
+                return e;
+            if ((e = H.blas(B_RES, H.v[0], nullptr, b, H.v[1], nullptr, nullptr, 0)))
+                return e;
+            WL_TRY(launch_convert(WL_F64, lo->prec, hi->V, nrhs, H.v[0], L.v[0], sig_dev, 1, 2, st));
+            // rho = <rh, r>, |r|^2 of the replaced residual, then beta
+            if ((e = L.blas(B_DOT_NORM, nullptr, nullptr, L.v[1], L.v[0], nullptr, nullptr, 0)))
+                return e;
+            if ((e = L.fin(F_BI_RELIABLE, 0, -1, -1, it, 0.0)))
+                return e;
+            ++updates;
+            // the status mirrored by iteration it + 1 onwards includes this
+            // update; observations before that are skipped
+            next_read = it + L.lookahead + 1;
+            for (int r = 0; r < nrhs; ++r)
+                rmax[r] = 0.0;
+            return WL_OK;
+        };
+    }
     for (;;) {
         if ((rc = H.true_res2(x, b, rr)))
             return rc;
@@ -552,6 +628,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
                 return WL_ENAN;
             const bool ok = rr[r] <= tol * tol * bb[r];
             sig[r] = ok ? 0.0 : std::sqrt(rr[r]);
+            t2[r] = ok ? 0.0 : 0.64 * tol * tol * bb[r] / rr[r];
             if (!ok) {
                 all_ok = false;
                 const double rel = std::sqrt(rr[r] / bb[r]);
@@ -568,9 +645,14 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         if (all_ok || stagnated || outer >= max_outer || total >= prm->maxiter)
             break;
         WL_TRY(hipMemcpyAsync(sig_dev, sig, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+        if (reliable)
+            WL_TRY(hipMemcpyAsync(tol2_dev, t2, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
         // r_lo = r64 / sigma (0 for converged columns)
         WL_TRY(launch_convert(WL_F64, lo->prec, hi->V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
         int done = 0;
+        next_read = 0;
+        for (int r = 0; r < nrhs; ++r)
+            rmax[r] = 0.0;
         if ((rc = L.run(e_lo, r_lo, true, delta, prm->maxiter - total, &done)))
             return rc;
         for (int r = 0; r < nrhs; ++r) {
@@ -591,7 +673,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     for (int r = 0; r < nrhs; ++r) {
         wl_solve_stats s{};
         s.iters = iters[r];
-        s.outer = outer;
+        s.outer = outer + updates;
         s.stencil_calls = H.stencil_calls + L.stencil_calls;
         s.true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
         s.iter_rel_res = s.true_rel_res;
@@ -609,10 +691,11 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
 
 size_t solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs)
 {
+    const int Lt = hi->g.dims[3];
     if (!lo)
-        return engine_bytes(solver, hi->prec, hi->V, nrhs) + 4 * ALIGN;
-    return engine_bytes(WL_SOLVER_CGNR, hi->prec, hi->V, nrhs) + engine_bytes(solver, lo->prec, lo->V, nrhs) +
-           2 * align_up(vec_bytes(lo->prec, lo->V, nrhs)) + align_up(sizeof(double) * nrhs) + 8 * ALIGN;
+        return engine_bytes(solver, hi->prec, hi->V, Lt, nrhs) + 4 * ALIGN;
+    return engine_bytes(WL_SOLVER_CGNR, hi->prec, hi->V, Lt, nrhs) + engine_bytes(solver, lo->prec, lo->V, Lt, nrhs) +
+           2 * align_up(vec_bytes(lo->prec, lo->V, nrhs)) + 2 * align_up(sizeof(double) * nrhs) + 8 * ALIGN;
 }
 
 int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *prm,

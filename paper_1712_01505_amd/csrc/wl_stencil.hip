@@ -25,10 +25,13 @@ namespace wl {
 
 // Upper two spin rows of (1 + SIG g_MU) psi, per colour: h[3*spin + colour].
 // Chiral basis: g_MU = [[0, A],[A^dag, 0]], so h = psi_up + SIG A psi_dn.
+// `one` is 1 at run time; multiplying the +-1 coefficients by it keeps
+// the compiler from turning the fused form into an add, so a 16-bit input
+// feeds a mixed-precision FMA directly (no separate conversion).
 template <int MU, int SIG, typename T>
-__device__ __forceinline__ void project(const cx<T> (&ps)[12], cx<T> (&h)[6])
+__device__ __forceinline__ void project(const cx<T> (&ps)[12], cx<T> (&h)[6], T one = T(1))
 {
-    const T s = (T)SIG;
+    const T s = (T)SIG * one;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const cx<T> p0 = ps[a], p1 = ps[3 + a], p2 = ps[6 + a], p3 = ps[9 + a];
@@ -125,7 +128,7 @@ __device__ __forceinline__ void hop_dir(const StencilParams &p, uint32_t s, int 
         cx<T> ps[12], h[6], g[6];
         T sc;
         load_site_unscaled<P>(p.in, p.V, p.nrhs, sf, r0 + r, ps, sc);
-        project<MU, SF>(ps, h);
+        project<MU, SF>(ps, h, (T)p.one);
         su3_mv(u, h, g);
         accum<MU, SF>(acc[r], g, gf * sc);
     }
@@ -139,7 +142,7 @@ __device__ __forceinline__ void hop_dir(const StencilParams &p, uint32_t s, int 
         cx<T> ps[12], h[6], g[6];
         T sc;
         load_site_unscaled<P>(p.in, p.V, p.nrhs, sb, r0 + r, ps, sc);
-        project<MU, -SF>(ps, h);
+        project<MU, -SF>(ps, h, (T)p.one);
         su3_adj_mv(u, h, g);
         accum<MU, -SF>(acc[r], g, gb * sc);
     }
@@ -308,7 +311,8 @@ __device__ __forceinline__ void decode(const RawHop<P> &r, cx<typename Traits<P>
 }
 
 template <int P, int DAG, int H>
-__device__ __forceinline__ void compute_hop(const RawHop<P> &r, float sg, cx<typename Traits<P>::real> (&acc)[12])
+__device__ __forceinline__ void compute_hop(const RawHop<P> &r, float sg, cx<typename Traits<P>::real> (&acc)[12],
+                                            typename Traits<P>::real one)
 {
     using T = typename Traits<P>::real;
     constexpr int MU = H / 2;
@@ -316,7 +320,7 @@ __device__ __forceinline__ void compute_hop(const RawHop<P> &r, float sg, cx<typ
     constexpr int SIG = (H % 2 == 0) ? SF : -SF;
     cx<T> ps[12], u[9], h[6], g[6];
     decode<P>(r, ps, u);
-    project<MU, SIG>(ps, h);
+    project<MU, SIG>(ps, h, one);
     if constexpr (H % 2 == 0)
         su3_mv(u, h, g);
     else
@@ -344,15 +348,15 @@ __device__ __forceinline__ void load_group(const StencilParams &p, uint32_t s, i
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int P, int DAG, int G, int H>
+template <int P, int DAG, int G, int H, int NH = 8>
 __device__ __forceinline__ void pipe(const StencilParams &p, uint32_t s, int rhs, const Hops &hp,
                                      RawHop<P> (&buf)[2 * G], cx<typename Traits<P>::real> (&acc)[12])
 {
-    if constexpr (H < 8) {
-        if constexpr (H % G == 0 && H + G < 8)
+    if constexpr (H < NH) {
+        if constexpr (H % G == 0 && H + G < NH)
             load_group<P, G, H + G>(p, s, rhs, hp, buf);
-        compute_hop<P, DAG, H>(buf[((H / G) % 2) * G + H % G], hp.sg[H], acc);
-        pipe<P, DAG, G, H + 1>(p, s, rhs, hp, buf, acc);
+        compute_hop<P, DAG, H>(buf[((H / G) % 2) * G + H % G], hp.sg[H], acc, (typename Traits<P>::real)p.one);
+        pipe<P, DAG, G, H + 1, NH>(p, s, rhs, hp, buf, acc);
     }
 }
 
@@ -374,8 +378,211 @@ template <int P, int VAR>
 struct VarG {
     static constexpr int G = VAR == 1 ? 1 : VAR == 2 ? 2 : 4;
 };
-// FP64 with G = 2 and FP32 with G = 4 exceed the register file and spill.
-int max_var(int prec) { return prec == F64 ? 1 : prec == F32 ? 2 : 3; }
+// FP64 with G = 2 and FP32 with G = 4 exceed the register file and spill;
+// variants 4-6 (t-walk) exist for every precision.
+int max_var(int prec) { return 6; }
+bool var_ok(int prec, int var) { return var <= 1 || var >= 4 || (var == 2 && prec != F64) || (var == 3 && prec >= BF16S); }
+
+// ---------------------------------------------------------------- t-walk
+// Each thread walks a column of T sites along t.  The decoded spinor of the
+// current site and the backward-t contribution of the next site,
+// U_t(x)^dag (1 -+ g_t) psi(x), computed while U_t(x) and psi(x) are in
+// registers, are carried to the next step; every t-direction spinor and
+// link is therefore read from memory once per column instead of three and
+// two times, and the accesses of the co-resident workgroups (the same t
+// steps of neighbouring (x, y, z) blocks) stay close in time.
+template <int P>
+__device__ __forceinline__ void scale_site(cx<typename Traits<P>::real> (&v)[12], typename Traits<P>::real sc)
+{
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        v[k] = cx<typename Traits<P>::real>{v[k].re * sc, v[k].im * sc};
+}
+
+// Spatial hops of the t-walk are pipelined G at a time; FP64 does not carry
+// the site's own spinor (register budget) and reloads it, a near reuse.
+template <int P>
+struct TwalkG {
+    static constexpr int G = P == F64 ? 1 : P == F32 ? 2 : 3;
+    static constexpr bool CARRY_SELF = P != F64;
+    static constexpr bool EARLY_T = P != F64;  // issue the forward-t loads before the spatial hops
+};
+
+template <int P, int DAG, int RED, int APPLY>
+__global__ __launch_bounds__(512) void twalk_kernel(StencilParams p, int T, uint32_t nxyz, uint32_t nbxyz)
+{
+    using R_ = typename Traits<P>::real;
+    constexpr int NV = RED == RED_NORM ? 1 : RED == RED_DOTV ? 2 : RED == RED_DOTIN_NORM ? 3 : 0;
+    constexpr int SF = DAG ? 1 : -1;  // forward hops use (1 + SF g), backward (1 - SF g)
+    constexpr int G = TwalkG<P>::G;
+    constexpr bool CARRY = TwalkG<P>::CARRY_SELF;
+    __shared__ double lds[(NV > 0 ? NV : 1) * 8];
+    const int rhs = blockIdx.y;
+    if (p.skip && p.skip[rhs].frozen)
+        return;
+    const uint32_t unit = tile_of(blockIdx.x, gridDim.x, p.xcd ? 1 : 0);
+    const uint32_t chunk = unit / nbxyz;
+    const uint32_t sx = (unit - chunk * nbxyz) * blockDim.x + threadIdx.x;
+    double red[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < (NV > 0 ? NV : 1); ++i)
+        red[i] = 0.0;
+    if (sx < nxyz) {
+        // spatial coordinates and neighbours (in the xyz index), fixed along the walk
+        const uint32_t q1 = fdiv(sx, p.fx);
+        const int x = (int)(sx - q1 * (uint32_t)p.L[0]);
+        const uint32_t q2 = fdiv(q1, p.fy);
+        const int y = (int)(q1 - q2 * (uint32_t)p.L[1]);
+        const int z = (int)q2;
+        const int c[3] = {x, y, z};
+        Hops sp;  // spatial hops 0..5 (h = 2 mu + dir), sites relative to t = 0
+        uint32_t stride = 1u;
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            const int L = p.L[mu];
+            const bool wf = c[mu] == L - 1, wb = c[mu] == 0;
+            const uint32_t span = (uint32_t)(L - 1) * stride;
+            sp.nb[2 * mu] = wf ? sx - span : sx + stride;
+            sp.nb[2 * mu + 1] = wb ? sx + span : sx - stride;
+            sp.sg[2 * mu] = (wf && p.bc[mu] < 0) ? -1.f : 1.f;
+            sp.sg[2 * mu + 1] = (wb && p.bc[mu] < 0) ? -1.f : 1.f;
+            stride *= (uint32_t)L;
+        }
+        const int Lt = p.L[3];
+        const bool anti_t = p.bc[3] < 0;
+        const int t0 = (int)chunk * T;
+        cx<R_> self[12], C[12];
+        // prologue: the backward-t hop into the site at t0
+        {
+            if constexpr (CARRY)
+                load_site<P>(p.in, p.V, p.nrhs, sx + nxyz * (uint32_t)t0, rhs, self);
+            const int tb = t0 == 0 ? Lt - 1 : t0 - 1;
+            const uint32_t sb = sx + nxyz * (uint32_t)tb;
+            RawHop<P> rb;
+            raw_load<P>(p, sb, sb, 3, rhs, rb);
+            cx<R_> ps[12], u[9], h[6], g[6];
+            decode<P>(rb, ps, u);
+            project<3, -SF>(ps, h, (R_)p.one);
+            su3_adj_mv(u, h, g);
+            R_ gb = (t0 == 0 && anti_t) ? R_(-1) : R_(1);
+            if constexpr (Traits<P>::SCALED)
+                gb *= rb.sc;
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                C[k] = cx<R_>{R_(0), R_(0)};
+            accum<3, -SF>(C, g, gb);
+        }
+        const R_ kap = (R_)p.kappa;
+        for (int k = 0; k < T; ++k) {
+            const int t = t0 + k;
+            const uint32_t toff = nxyz * (uint32_t)t;
+            const uint32_t s = sx + toff;
+            // forward t neighbour and link U_t(x): the far loads, issued first
+            const bool wf = t == Lt - 1;
+            const uint32_t sn = sx + nxyz * (uint32_t)(wf ? 0 : t + 1);
+            RawHop<P> rf;
+            if constexpr (TwalkG<P>::EARLY_T)
+                raw_load<P>(p, sn, s, 3, rhs, rf);
+            Hops hp;
+#pragma unroll
+            for (int h = 0; h < 6; ++h) {
+                hp.nb[h] = sp.nb[h] + toff;
+                hp.sg[h] = sp.sg[h];
+            }
+            // hop order +x, -x, +y, -y, +z, -z, +t, -t as in the other variants; with
+            // FP64/FP32 storage the carried -t term is exact (its coefficients are
+            // +-1), so the site result rounds exactly as there
+            cx<R_> acc[12];
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                acc[i] = cx<R_>{R_(0), R_(0)};
+            {
+                RawHop<P> buf[2 * G];
+                load_group<P, G, 0>(p, s, rhs, hp, buf);
+                pipe<P, DAG, G, 0, 6>(p, s, rhs, hp, buf, acc);
+            }
+            if constexpr (!TwalkG<P>::EARLY_T)
+                raw_load<P>(p, sn, s, 3, rhs, rf);
+            if constexpr (!CARRY)
+                load_site<P>(p.in, p.V, p.nrhs, s, rhs, self);
+            cx<R_> nxt[12], u[9];
+            decode<P>(rf, nxt, u);
+            {
+                cx<R_> h[6], g[6];
+                project<3, SF>(nxt, h, (R_)p.one);
+                su3_mv(u, h, g);
+                R_ gf = (wf && anti_t) ? R_(-1) : R_(1);
+                if constexpr (Traits<P>::SCALED)
+                    gf *= rf.sc;
+                accum<3, SF>(acc, g, gf);
+            }
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                acc[i] = cx<R_>{acc[i].re + C[i].re, acc[i].im + C[i].im};
+            // backward-t contribution of the next site: U_t(x)^dag (1 - SF g_t) psi(x)
+            {
+                cx<R_> h[6], g[6];
+                project<3, -SF>(self, h, (R_)p.one);
+                su3_adj_mv(u, h, g);
+#pragma unroll
+                for (int i = 0; i < 12; ++i)
+                    C[i] = cx<R_>{R_(0), R_(0)};
+                accum<3, -SF>(C, g, R_(1));
+            }
+            // epilogue for site s
+            cx<R_> o[12];
+            if constexpr (APPLY) {
+#pragma unroll
+                for (int i = 0; i < 12; ++i)
+                    o[i] = cx<R_>{fma(-kap, acc[i].re, self[i].re), fma(-kap, acc[i].im, self[i].im)};
+            } else {
+#pragma unroll
+                for (int i = 0; i < 12; ++i)
+                    o[i] = acc[i];
+            }
+            store_site_q<P>(p.out, p.V, p.nrhs, s, rhs, o);
+            if constexpr (RED == RED_NORM || RED == RED_DOTIN_NORM) {
+#pragma unroll
+                for (int i = 0; i < 12; ++i)
+                    red[NV - 1] = fma((double)o[i].re, (double)o[i].re, fma((double)o[i].im, (double)o[i].im, red[NV - 1]));
+            }
+            if constexpr (RED == RED_DOTIN_NORM) {
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    red[0] = fma((double)self[i].re, (double)o[i].re, fma((double)self[i].im, (double)o[i].im, red[0]));
+                    red[1] = fma((double)self[i].re, (double)o[i].im, fma(-(double)self[i].im, (double)o[i].re, red[1]));
+                }
+            }
+            if constexpr (RED == RED_DOTV) {
+                cx<R_> v[12];
+                load_site<P>(p.aux, p.V, p.nrhs, s, rhs, v);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    red[0] = fma((double)v[i].re, (double)o[i].re, fma((double)v[i].im, (double)o[i].im, red[0]));
+                    red[1] = fma((double)v[i].re, (double)o[i].im, fma(-(double)v[i].im, (double)o[i].re, red[1]));
+                }
+            }
+            if constexpr (CARRY) {  // the forward neighbour becomes the next site
+                if constexpr (Traits<P>::SCALED)
+                    scale_site<P>(nxt, rf.sc);
+#pragma unroll
+                for (int i = 0; i < 12; ++i)
+                    self[i] = nxt[i];
+            }
+        }
+    }
+    if constexpr (NV > 0) {
+        block_sum<NV>(red, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                p.partials[((size_t)k * p.nrhs + rhs) * p.nblk + blockIdx.x] = red[k];
+        }
+    }
+}
+
+// t-walk column length of code variants 4, 5, 6
+__host__ __device__ constexpr int twalk_T(int var) { return var == 4 ? 4 : var == 5 ? 8 : 16; }
 
 // Round a site to what the 16-bit format will store (so that fused
 // reductions see exactly the stored values).
@@ -446,8 +653,7 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
                     for (int k = 0; k < 12; ++k)
                         o[k] = acc[r][k];
                 }
-                if constexpr (Traits<P>::SCALED)
-                    round_site<P>(o);
+
                 if constexpr (RED == RED_DOTIN_NORM) {
                     double re = 0.0, im = 0.0;
 #pragma unroll
@@ -462,10 +668,9 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 #pragma unroll
                 for (int k = 0; k < 12; ++k)
                     o[k] = acc[r][k];
-                if constexpr (Traits<P>::SCALED)
-                    round_site<P>(o);
+
             }
-            store_site<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
+            store_site_q<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
             if constexpr (RED == RED_NORM || RED == RED_DOTIN_NORM) {
                 double n2 = 0.0;
 #pragma unroll
@@ -528,6 +733,45 @@ static hipError_t launch_v(dim3 grid, dim3 block, const StencilParams &p, hipStr
     return hipGetLastError();
 }
 
+template <int P, int DAG>
+static hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
+{
+    const int T = twalk_T(cfg.var);
+    if (p.L[3] % T != 0)
+        return hipErrorInvalidValue;
+    const uint32_t nxyz = (uint32_t)p.L[0] * p.L[1] * p.L[2];
+    const uint32_t nbxyz = (nxyz + cfg.block - 1) / cfg.block;
+    const uint32_t units = nbxyz * (uint32_t)(p.L[3] / T);
+    p.nblk = (int)units;
+    dim3 grid(units, p.nrhs), block(cfg.block);
+    if (!p.apply) {
+        if (p.red != RED_NONE)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NONE, 0>), grid, block, 0, st, p, T, nxyz, nbxyz);
+        return hipGetLastError();
+    }
+    switch (p.red) {
+    case RED_NONE: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NONE, 1>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
+    case RED_NORM: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NORM, 1>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
+    case RED_DOTV: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_DOTV, 1>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
+    case RED_DOTIN_NORM:
+        hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_DOTIN_NORM, 1>), grid, block, 0, st, p, T, nxyz, nbxyz);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Number of per-workgroup partials a launch with this configuration writes.
+int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V)
+{
+    if (cfg.rpt == 1 && cfg.var >= 4) {
+        const uint32_t nxyz = (uint32_t)L[0] * L[1] * L[2];
+        return (int)(((nxyz + cfg.block - 1) / cfg.block) * (uint32_t)(L[3] / twalk_T(cfg.var)));
+    }
+    return (int)((V + cfg.block - 1) / cfg.block);
+}
+
 template <int P, int DAG, int R>
 static hipError_t launch_t(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
 {
@@ -544,6 +788,9 @@ static hipError_t launch_t(const LaunchCfg &cfg, StencilParams p, hipStream_t st
             if constexpr (P == BF16S || P == F16S)
                 return launch_v<P, DAG, 1, 3>(grid, block, p, st);
             return hipErrorInvalidValue;
+        case 4:
+        case 5:
+        case 6: return launch_twalk<P, DAG>(cfg, p, st);
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -583,6 +830,7 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
         return hipErrorInvalidValue;
     p.nblk = (int)((p.V + cfg.block - 1) / cfg.block);
     p.xcd = cfg.xcd;
+    p.one = 1.0f;
     if (p.xcd == 2) {
         if (!slab_ok(p.L, cfg.block))
             return hipErrorInvalidValue;
@@ -647,7 +895,7 @@ __global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, 
 #pragma unroll
                 for (int k = 0; k < 12; ++k)
                     o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
-                store_site<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
+                store_site_q<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
             }
         }
     }

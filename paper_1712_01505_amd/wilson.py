@@ -227,8 +227,17 @@ def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0):
     return _check(lib().wl_set_launch(op, nrhs, block, rpt, xcd, variant), "wl_set_launch")
 
 
-# Largest stencil code variant per precision (see wl_set_launch in the header).
-MAX_VARIANT = {WL_F64: 1, WL_F32: 2, WL_BF16S: 3, WL_F16S: 3}
+# Stencil code variants per precision (see wl_set_launch in the header):
+# 0 straight-line, 1-3 pipelined hops, 4-6 t-walk with columns of 4, 8, 16.
+VARIANTS = {WL_F64: (0, 1, 4, 5, 6), WL_F32: (0, 1, 2, 4, 5, 6), WL_BF16S: (0, 1, 2, 3, 4, 5, 6),
+            WL_F16S: (0, 1, 2, 3, 4, 5, 6)}
+MAX_VARIANT = {k: max(v) for k, v in VARIANTS.items()}
+
+
+def try_set_launch(op, nrhs, block, rpt, xcd, variant=0):
+    """wl_set_launch that returns False (instead of raising) for a configuration
+    the lattice does not admit (e.g. a t-walk column not dividing Lt)."""
+    return lib().wl_set_launch(op, nrhs, block, rpt, xcd, variant) == WL_OK
 MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
 
 

@@ -160,3 +160,73 @@ def test_warm_restart_from_solution(W, oracle_mod):
     x2, st = W.solve(Ud, bd, 0.12, tol=1e-10, x0=x1, return_stats=True)
     assert st["iters"] <= 1
     assert rel(x2.cpu().numpy(), x1.cpu().numpy()) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_solver_with_each_stencil_variant(W, oracle_mod, prec):
+    """The fused-reduction stencils of every code variant drive a solve to the
+    same answer (the variants differ in schedule, not in arithmetic)."""
+    dims = (8, 8, 8, 16)
+    kappa = 0.12
+    U = inputs.near_unity_gauge(dims, 0.3, seed=2)
+    b = inputs.gaussian_spinor(dims, seed=3)
+    Ud = dev(U)
+    hi = W.Operator.create(Ud, kappa, W.WL_F64)
+    lo = None if prec == "f64" else W.Operator.create(Ud, kappa, W.PREC[prec])
+    op = hi if lo is None else lo
+    xs, vs = [], []
+    for var in W.VARIANTS[op.prec]:
+        if not W.try_set_launch(op.handle, 1, 128, 1, 1, var):
+            continue
+        x, st = W.solve(None, dev(b), kappa, method="bicgstab", precision="f64" if lo is None else "mixed-" + prec,
+                        tol=1e-10, ops=(hi, lo), return_stats=True)
+        assert st["converged"], (var, st)
+        xs.append(x.cpu().numpy())
+        vs.append(var)
+    assert len(xs) >= 4
+    for x in xs:
+        assert rel(oracle_mod.apply(U, x, kappa), b) <= 1.05e-10
+    if prec == "f64":
+        # variants 0-3 share the per-workgroup partial layout, so even the
+        # reductions round identically; t-walk sums its column first
+        same = [x for x, v in zip(xs, vs) if v < 4]
+        for x in same[1:]:
+            assert np.array_equal(x, same[0])
+
+
+@pytest.mark.parametrize("lo", ["f32", "bf16", "f16"])
+def test_reliable_updates_reach_fp64_accuracy(W, oracle_mod, lo):
+    """BiCGStab with reliable updates (one inner run, FP64 solution and
+    residual refreshed in place) meets the same bar as defect correction."""
+    dims = (8, 8, 8, 16)
+    kappa = 0.1255
+    U = inputs.near_unity_gauge(dims, 0.3, seed=1)
+    b = inputs.gaussian_spinor(dims, seed=0)
+    x, st = W.solve(dev(U), dev(b), kappa, method="bicgstab", precision="mixed-" + lo, tol=1e-10,
+                    reliable=True, return_stats=True)
+    x = x.cpu().numpy()
+    assert st["status"] == 0, st
+    assert st["outer"] >= 2  # at least one in-run update besides the final check
+    assert true_res(oracle_mod, U, x, b, kappa) <= 1e-10 * 1.05
+    x_ref, _, _, _ = oracle_mod.bicgstab(U, b, kappa, tol=1e-13)
+    assert rel(x, x_ref) < 1e-8
+
+
+def test_reliable_updates_multi_rhs_and_adjoint(W, oracle_mod):
+    """12 point sources together, and the adjoint system, with reliable updates."""
+    dims = (8, 8, 8, 8)
+    kappa = 0.12
+    U = inputs.near_unity_gauge(dims, 0.3, seed=4)
+    srcs = inputs.point_sources_all_spin_colour(dims)
+    xs, st = W.solve(dev(U), dev(srcs), kappa, method="bicgstab", precision="mixed-f16", tol=1e-10,
+                     reliable=True, return_stats=True)
+    xs = xs.cpu().numpy()
+    assert all(s["converged"] for s in st)
+    for k in (0, 5, 11):
+        assert true_res(oracle_mod, U, xs[k], srcs[k], kappa) <= 1.05e-10
+    b = inputs.gaussian_spinor(dims, seed=9)
+    y = W.solve(dev(U), dev(b), kappa, method="bicgstab", precision="mixed-bf16", tol=1e-10, reliable=True,
+                dagger=True).cpu().numpy()
+    g5 = mp.gamma5_spinor
+    # D^dag = gamma5 D gamma5
+    assert rel(g5(oracle_mod.apply(U, g5(y), kappa)), b) <= 1.05e-10

@@ -79,10 +79,12 @@ def test_apply_matches_oracle(W, oracle_mod, dims, kind, prec, dagger):
     ref = oracle_mod.apply(U, psi, kappa, dagger=dagger)
     p = W.PREC[prec]
     op = W.Operator.create(dev(U), kappa, p)
-    for var in range(W.MAX_VARIANT[p] + 1):
-        W.wl_set_launch(op.handle, 1, 256, 1, 1, var)
-        out = W.apply(None, dev(psi), kappa, dagger=dagger, op=op).cpu().numpy()
-        assert rel(out, ref) < TOL[prec], var
+    for var in W.VARIANTS[p]:
+        for xcd in (0, 1, 2):
+            if not W.try_set_launch(op.handle, 1, 64, 1, xcd, var):
+                continue  # e.g. a t-walk column length not dividing Lt, or no z-slabs
+            out = W.apply(None, dev(psi), kappa, dagger=dagger, op=op).cpu().numpy()
+            assert rel(out, ref) < TOL[prec], (var, xcd)
 
 
 @pytest.mark.parametrize("dims,kind", CASES[:4])
@@ -121,19 +123,25 @@ def test_multi_rhs_columns_equal_single_rhs(W, prec):
     p = W.PREC[prec]
     op = W.Operator.create(dev(U), 0.125, p)
     src = op.pack(dev(psi))
-    outs = []
+    outs, cfgs = [], []
     for rpt in (1, 2, 3, 4):
         if rpt > W.MAX_RPT[p]:
             continue
         for block in (64, 256, 512):
-            for xcd in (0, 1):
-                for var in range(W.MAX_VARIANT[p] + 1 if rpt == 1 else 1):
-                    W.wl_set_launch(op.handle, 12, block, rpt, xcd, var)
+            for xcd in (0, 1, 2):
+                for var in (W.VARIANTS[p] if rpt == 1 else (0,)):
+                    if not W.try_set_launch(op.handle, 12, block, rpt, xcd, var):
+                        continue
                     dst = op.new_field(12)
                     op.apply_packed(dst, src, 12)
                     outs.append(op.unpack(dst, 12).cpu().numpy())
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])  # launch shape never changes a result
+                    cfgs.append((block, rpt, xcd, var))
+    for o, cfg in zip(outs[1:], cfgs[1:]):
+        if p in (W.WL_BF16S, W.WL_F16S) and cfg[3] >= 4:
+            # t-walk applies a neighbour's 16-bit scale in a different place: equal to rounding
+            assert rel(o, outs[0]) < 1e-6, cfg
+        else:
+            assert np.array_equal(o, outs[0]), cfg  # launch shape never changes a result
     for k in (0, 5, 11):
         single = W.apply(dev(U), dev(psi[k]), 0.125, prec=prec, op=op).cpu().numpy()
         assert np.array_equal(single, outs[0][k])
