@@ -139,15 +139,20 @@ def bench_batching(W, inputs, torch, log):
         dsts.append(op.new_field(4))
         ops.append(op)
     descs = [(o.handle, d.data_ptr(), s_.data_ptr()) for o, d, s_ in zip(ops, dsts, srcs)]
-    ms_multi = _time_ms(torch, lambda: W.wilson_multi_apply(descs, 0, 4, st), 10)
+    plan = W.MultiPlan(descs, 0, 4)
+    plan.tune(st)
+    ms_multi = _time_ms(torch, lambda: plan.run(st), 20)
+    for o in ops:
+        W.wl_autotune(o.handle, 4, 0, st)
 
     def separate():
         for o, d, s_ in zip(ops, dsts, srcs):
             o.apply_packed(d, s_, 4)
-    ms_sep = _time_ms(torch, separate, 10)
+    ms_sep = _time_ms(torch, separate, 20)
     Vt = sum(inputs.volume(d) for d in lattices)
     out["multi_lattice_f32"] = {"lattices": [list(d) for d in lattices], "nrhs": 4, "V_total": Vt,
-                                "one_launch_us": round(ms_multi * 1e3, 1), "separate_launches_us": round(ms_sep * 1e3, 1),
+                                "one_launch_us": round(ms_multi * 1e3, 1), "plan_launch": plan.launch(),
+                                "separate_launches_us": round(ms_sep * 1e3, 1),
                                 "speedup": round(ms_sep / ms_multi, 3),
                                 "GFLOP/s": round(1368 * Vt * 4 / (ms_multi * 1e-3) / 1e9, 1)}
     log(f"[bench] multi-lattice: {out['multi_lattice_f32']}")

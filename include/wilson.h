@@ -178,15 +178,41 @@ int solve_bicgstab(const wl_op *hi, const wl_op *lo, void *x, const void *b, int
 int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const void *mu, int project,
                        void *stream);
 
-/* One persistent launch applying D (or D^dag) to several lattices of
- * different sizes: entry i computes out_i = D_i in_i with nrhs right-hand
- * sides.  All ops must share one precision.  Work is split into fixed-size
- * site tiles drawn from one device-wide queue.  Async. */
+/* Several lattices of different sizes in one persistent launch: entry i
+ * computes out_i = D_i in_i (or D_i^dag in_i) with nrhs right-hand sides.
+ * All ops must share one precision; out_i and in_i are packed spinors of
+ * it, distinct, 16-byte aligned.  The work is cut into fixed-size site
+ * tiles x right-hand-side groups, drawn by resident workgroups from one
+ * device-wide queue, so small lattices fill the gaps of large ones. */
 typedef struct {
     const wl_op *op;
     void *out;
     const void *in;
 } wl_multi_desc;
+
+/* A plan uploads the descriptor table once (and owns the queue counter);
+ * each run is then one kernel launch.  The ops and buffers named in the
+ * descriptors must outlive the plan.  Runs of one plan must not overlap
+ * in time (they share the counter): issue them on one stream.
+ * create: n in [1, 1024], nrhs in [1, 65535]; synchronous.
+ * run: async on `stream`.
+ * tune: times the launch shapes (sites per workgroup, RHS per thread, code
+ *   variant) with HIP events, keeps the fastest (also in $WL_TUNE_CACHE);
+ *   synchronous; leaves out_i = D_i in_i.
+ * get_launch: current block size, RHS per thread, variant, resident grid.
+ * set_launch: force a shape: block in {64,...,512} (multiple of 64); RHS per
+ *   thread 1, 2 or 4 (WL_F64: 1, 2) dividing nrhs; variant 0 (any RHS per
+ *   thread) or a pipelined variant 1..3 the precision offers (1 RHS per
+ *   thread); synchronous, the plan must be idle. */
+typedef struct wl_multi_plan wl_multi_plan;
+int wl_multi_plan_create(const wl_multi_desc *d, int n, int dagger, int nrhs, wl_multi_plan **plan);
+int wl_multi_plan_run(wl_multi_plan *plan, void *stream);
+int wl_multi_plan_tune(wl_multi_plan *plan, void *stream);
+int wl_multi_plan_get_launch(const wl_multi_plan *plan, int *block, int *rhs_per_thread, int *variant, int *grid);
+int wl_multi_plan_set_launch(wl_multi_plan *plan, int block, int rhs_per_thread, int variant);
+int wl_multi_plan_destroy(wl_multi_plan *plan);
+
+/* One-shot form: create a plan, run it, wait for `stream`, destroy it. */
 int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void *stream);
 
 /* Time the stencil launch candidates for (op geometry, precision, nrhs,
@@ -194,18 +220,38 @@ int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void
  * memory and in the JSON file named by $WL_TUNE_CACHE (if set).  Synchronous. */
 int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
 
-/* Launch configuration currently used for (op, nrhs): block size, RHS per
- * thread, XCD-aware tile order flag, stencil code variant. */
-int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rhs_per_thread, int *xcd_remap, int *variant);
-/* Force a launch configuration: block in {64,...,512} (multiple of 64);
- * rhs_per_thread dividing nrhs, at most 2 for WL_F64 and 4 otherwise;
- * xcd_remap: 0 natural tile order, 1 one contiguous site range per XCD,
- * 2 one z-slab per XCD walked t-major (needs Lz % 8 == 0 and block dividing
- * V/8); variant 0 (straight-line hops) or, with rhs_per_thread = 1,
- * a software-pipelined hop loop: 1 (all precisions), 2 (not WL_F64),
- * 3 (16-bit formats only).  Results do not depend on the configuration.
- * Used by tests and the autotuner. */
-int wl_set_launch(wl_op *op, int nrhs, int block, int rhs_per_thread, int xcd_remap, int variant);
+/* Stencil launch configuration for (op, nrhs):
+ * block           threads per workgroup, 64..512, a multiple of 64;
+ * rhs_per_thread  right-hand sides per thread sharing its link registers:
+ *                 dividing nrhs, at most 2 for WL_F64 and 4 otherwise;
+ * rhs_lanes       right-hand sides interleaved across the lanes of every
+ *                 wavefront (1, 2, 4 or 8, dividing nrhs; > 1 needs
+ *                 rhs_per_thread = 1, variant <= 3 and block / rhs_lanes
+ *                 >= 64): the links of a site are fetched once per load
+ *                 instruction for all of them, and a workgroup covers
+ *                 block / rhs_lanes sites;
+ * xcd_remap       0 natural tile order, 1 one contiguous site range per XCD,
+ *                 2..5 one z-slab per XCD, walked in y-chunks of
+ *                 Ly >> (xcd_remap - 2) rows, each chunk t-major (needs
+ *                 Lz % 8 == 0, Ly divisible by the chunk count and
+ *                 block / rhs_lanes dividing V/8; the t-walk variants treat
+ *                 2..5 as 1);
+ * variant         0 straight-line hops; with rhs_per_thread = 1 a
+ *                 software-pipelined hop loop 1 (all precisions), 2 (not
+ *                 WL_F64), 3 (16-bit formats only), or a t-walk 4, 5, 6
+ *                 (columns of 4, 8, 16 sites along t; Lt divisible by that).
+ * Results do not depend on the configuration (16-bit t-walk: to rounding). */
+typedef struct {
+    int block;
+    int rhs_per_thread;
+    int rhs_lanes;
+    int xcd_remap;
+    int variant;
+} wl_launch;
+int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg);
+/* Force a configuration (WL_EINVAL if it breaks a rule above).  Used by
+ * tests and the autotuner. */
+int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg);
 
 /* Stencil timing: when enabled, every stencil launch is bracketed by HIP
  * events on its stream; wl_prof_read synchronises and returns, for stencil

@@ -15,6 +15,19 @@
 
 #include "wl_internal.h"
 
+// A multi-lattice plan: the descriptors, the device table built from them
+// for the current launch shape, and the work-queue counter.
+struct wl_multi_plan {
+    int n = 0, nrhs = 0, dagger = 0, prec = 0;
+    std::vector<wl_multi_desc> desc;
+    wl::LaunchCfg cfg{};
+    int grid = 0;
+    uint32_t total = 0;
+    void *buf = nullptr;             // device: table, then the counter
+    wl::MultiEntry *dE = nullptr;
+    unsigned *counter = nullptr;     // [0] queue head, [1] exit count; zero between launches
+};
+
 namespace wl {
 size_t solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs);
 int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *prm,
@@ -137,7 +150,7 @@ static std::string tune_key(const wl_op *op, int nrhs, int dagger)
     return buf;
 }
 
-// Cache file: one line per entry, "key block rpt xcd variant".
+// Cache file: one line per entry, "key block rpt xcd variant lanes".
 static void load_tune_cache_locked()
 {
     if (g_tune_loaded)
@@ -152,7 +165,7 @@ static void load_tune_cache_locked()
         std::istringstream is(line);
         std::string key;
         LaunchCfg c;
-        if (is >> key >> c.block >> c.rpt >> c.xcd >> c.var)
+        if (is >> key >> c.block >> c.rpt >> c.xcd >> c.var >> c.lanes)
             g_tune[key] = c;
     }
 }
@@ -165,7 +178,7 @@ static void save_tune_cache_locked()
     std::ofstream f(path, std::ios::trunc);
     for (auto &kv : g_tune)
         f << kv.first << " " << kv.second.block << " " << kv.second.rpt << " " << kv.second.xcd << " "
-          << kv.second.var << "\n";
+          << kv.second.var << " " << kv.second.lanes << "\n";
 }
 
 // Untuned defaults (measured on MI355X at 32^3 x 64): one right-hand side
@@ -179,7 +192,7 @@ static LaunchCfg default_launch(const wl_op *op, int nrhs)
         c.rpt = 1;
         if (prec == WL_F64 || prec == WL_F32) {
             c.block = 256;
-            c.xcd = slab_ok(op->g.dims, 256) ? 2 : 0;
+            c.xcd = slab_ok(op->g.dims, 256, 2) ? 2 : 0;
             c.var = prec == WL_F64 ? 1 : 2;
         } else {
             c.block = 128;
@@ -188,51 +201,68 @@ static LaunchCfg default_launch(const wl_op *op, int nrhs)
         }
         return c;
     }
+    // several right-hand sides: interleave them across the lanes of each
+    // wavefront (one link fetch per instruction serves all of them)
     c.block = 256;
     c.xcd = 1;
-    c.var = 0;
     c.rpt = 1;
-    if (prec != WL_F64) {
-        if (nrhs % 4 == 0)
-            c.rpt = 4;
-        else if (nrhs % 2 == 0)
-            c.rpt = 2;
-        else if (nrhs % 3 == 0)
-            c.rpt = 3;
-    } else if (nrhs % 2 == 0) {
-        c.rpt = 2;
-    }
+    c.var = prec == WL_F64 ? 1 : 2;
+    c.lanes = nrhs % 4 == 0 ? 4 : nrhs % 2 == 0 ? 2 : 1;
     return c;
 }
 
 static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
 {
     const int prec = op->prec;
+    const bool lanes_ok = c.lanes == 1 || ((c.lanes == 2 || c.lanes == 4 || c.lanes == 8) && c.rpt == 1 &&
+                                           c.var < 4 && nrhs % c.lanes == 0 && c.block / c.lanes >= 64);
     return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
-           nrhs % c.rpt == 0 && c.xcd >= 0 && c.xcd <= 2 && (c.xcd != 2 || slab_ok(op->g.dims, c.block)) &&
-           c.var >= 0 && c.var <= max_var(prec) && var_ok(prec, c.var) && (c.var == 0 || c.rpt == 1) &&
+           nrhs % c.rpt == 0 && lanes_ok && c.xcd >= 0 && c.xcd <= 5 &&
+           (c.xcd < 2 || slab_ok(op->g.dims, c.block / c.lanes, c.xcd)) && c.var >= 0 && c.var <= max_var(prec) &&
+           var_ok(prec, c.var) && (c.var == 0 || c.rpt == 1) &&
            (c.var < 4 || op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0);
 }
 
-LaunchCfg launch_for(const wl_op *op, int nrhs)
+// Launch configurations are kept per (nrhs, fused reduction): the solver's
+// stencils with a reduction epilogue are tuned separately from the plain
+// apply.  A reduction kind without its own entry uses the plain one.
+static int launch_key(int nrhs, int red) { return nrhs * 4 + red; }
+
+static std::string tune_key_red(const wl_op *op, int nrhs, int red)
+{
+    return red == RED_NONE ? tune_key(op, nrhs, 0) : tune_key(op, nrhs, 0) + ":r" + std::to_string(red);
+}
+
+LaunchCfg launch_for(const wl_op *op, int nrhs, int red)
 {
     wl_op *o = const_cast<wl_op *>(op);
     {
         std::lock_guard<std::mutex> lk(o->mu);
-        auto it = o->launch.find(nrhs);
+        auto it = o->launch.find(launch_key(nrhs, red));
         if (it != o->launch.end())
             return it->second;
+        if (red != RED_NONE) {
+            auto it0 = o->launch.find(launch_key(nrhs, RED_NONE));
+            if (it0 != o->launch.end())
+                return it0->second;
+        }
     }
     LaunchCfg c = default_launch(op, nrhs);
+    bool found = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_cache_locked();
-        auto it = g_tune.find(tune_key(op, nrhs, 0));
-        if (it != g_tune.end() && launch_ok(op, nrhs, it->second))
-            c = it->second;
+        for (int r : {red, (int)RED_NONE}) {
+            auto it = g_tune.find(tune_key_red(op, nrhs, r));
+            if (it != g_tune.end() && launch_ok(op, nrhs, it->second)) {
+                c = it->second;
+                found = r == red;
+                break;
+            }
+        }
     }
     std::lock_guard<std::mutex> lk(o->mu);
-    o->launch[nrhs] = c;
+    o->launch[launch_key(nrhs, found ? red : (int)RED_NONE)] = c;
     return c;
 }
 
@@ -256,6 +286,64 @@ static StencilParams base_params(const wl_op *op, void *out, const void *in, int
     p.red = RED_NONE;
     p.one = 1.0f;
     return p;
+}
+
+// ---------------------------------------------------------------- multi-lattice plans
+static LaunchCfg multi_default(int prec, int nrhs)
+{
+    (void)nrhs;
+    return LaunchCfg{256, 1, 0, prec == WL_F64 ? 1 : 2, 1};
+}
+
+static std::string multi_key(const wl_multi_plan *pl)
+{
+    std::string k = arch_name() + ":multi:p" + std::to_string(pl->prec) + ":n" + std::to_string(pl->nrhs) + ":d" +
+                    std::to_string(pl->dagger);
+    for (const auto &d : pl->desc) {
+        char buf[64];
+        snprintf(buf, sizeof buf, ":%dx%dx%dx%d", d.op->g.dims[0], d.op->g.dims[1], d.op->g.dims[2], d.op->g.dims[3]);
+        k += buf;
+    }
+    return k;
+}
+
+// (Re)build the descriptor table for launch shape c and upload it
+// (synchronous; the plan must be idle).
+static int plan_build(wl_multi_plan *pl, const LaunchCfg &c)
+{
+    if (pl->nrhs % c.rpt != 0 || !multi_launch_ok(pl->prec, c.rpt, c.block, c.var))
+        return WL_EINVAL;
+    std::vector<MultiEntry> E(pl->n);
+    const uint32_t ng = (uint32_t)(pl->nrhs / c.rpt);
+    uint64_t total = 0;
+    for (int i = 0; i < pl->n; ++i) {
+        const wl_multi_desc &d = pl->desc[i];
+        E[i].p = base_params(d.op, d.out, d.in, pl->nrhs, 1);
+        E[i].p.nblk = (int)((d.op->V + c.block - 1) / c.block);
+        E[i].p.ng = ng;
+        E[i].p.f_ng = make_fastdiv(ng);
+        E[i].tile_begin = (uint32_t)total;
+        total += (uint64_t)E[i].p.nblk * ng;
+        if (total > 0x7fffffffull)
+            return WL_EINVAL;
+    }
+    CHECK_HIP(hipMemcpy(pl->dE, E.data(), sizeof(MultiEntry) * pl->n, hipMemcpyHostToDevice));
+    int grid = multi_grid_size(pl->prec, pl->dagger, c.rpt, c.block, c.var);
+    if (grid < 1)
+        return WL_EINVAL;
+    if ((uint64_t)grid > total)
+        grid = (int)total;
+    pl->cfg = c;
+    pl->total = (uint32_t)total;
+    pl->grid = grid;
+    return WL_OK;
+}
+
+static void plan_free(wl_multi_plan *pl)
+{
+    if (pl->buf)
+        (void)hipFree(pl->buf);
+    delete pl;
 }
 
 }  // namespace wl
@@ -378,7 +466,7 @@ static int stencil_call(const wl_op *op, void *out, const void *in, int dagger, 
         return WL_EINVAL;
     if (!al16(out) || !al16(in))
         return WL_EALIGN;
-    LaunchCfg cfg = launch_for(op, nrhs);
+    LaunchCfg cfg = launch_for(op, nrhs, RED_NONE);
     if (nrhs % cfg.rpt != 0) {
         cfg.rpt = 1;
         cfg.var = 0;
@@ -452,8 +540,11 @@ int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const vo
     return WL_OK;
 }
 
-int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void *stream)
+int wl_multi_plan_create(const wl_multi_desc *d, int n, int dagger, int nrhs, wl_multi_plan **out)
 {
+    if (!out)
+        return WL_EINVAL;
+    *out = nullptr;
     if (!d || n < 1 || n > 1024 || (dagger != 0 && dagger != 1) || nrhs < 1 || nrhs > 65535)
         return WL_EINVAL;
     const int prec = d[0].op ? d[0].op->prec : -1;
@@ -465,68 +556,179 @@ int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void
         if (!al16(d[i].out) || !al16(d[i].in))
             return WL_EALIGN;
     }
-    const int block = 256;
-    const int rpt = (prec != WL_F64 && nrhs % 4 == 0) ? 4 : (nrhs % 2 == 0) ? 2 : 1;  // multi kernel offers 1, 2, 4
-    std::vector<MultiEntry> E(n);
-    uint32_t total = 0;
-    for (int i = 0; i < n; ++i) {
-        E[i].p = base_params(d[i].op, d[i].out, d[i].in, nrhs, 1);
-        E[i].p.nblk = (int)((d[i].op->V + block - 1) / block);
-        E[i].tile_begin = total;
-        const uint64_t t = (uint64_t)E[i].p.nblk * (uint64_t)(nrhs / rpt);
-        if ((uint64_t)total + t > 0xffffffffull)
-            return WL_EINVAL;
-        total += (uint32_t)t;
-    }
-    hipStream_t st = (hipStream_t)stream;
-    // descriptor table and queue counter live in one small device buffer
-    // owned by this call; it is released after the launch completes
+    wl_multi_plan *pl = new wl_multi_plan();
+    pl->n = n;
+    pl->nrhs = nrhs;
+    pl->dagger = dagger;
+    pl->prec = prec;
+    pl->desc.assign(d, d + n);
     const size_t bytes = sizeof(MultiEntry) * n + 256;
-    void *buf = nullptr;
-    CHECK_HIP(hipMallocAsync(&buf, bytes, st));
-    MultiEntry *dE = (MultiEntry *)buf;
-    unsigned *counter = (unsigned *)((char *)buf + (sizeof(MultiEntry) * n + 127) / 128 * 128);
-    hipError_t e = hipMemcpyAsync(dE, E.data(), sizeof(MultiEntry) * n, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMalloc(&pl->buf, bytes);
+    pl->dE = (MultiEntry *)pl->buf;
     if (e == hipSuccess)
-        e = launch_fill_u32(counter, 0u, 1, st);
-    if (e == hipSuccess) {
-        int grid = multi_grid_size(prec, dagger, rpt, block);
-        if ((uint32_t)grid > total)
-            grid = (int)total;
-        e = launch_multi(prec, dagger, rpt, block, dE, n, total, counter, grid, st);
+        pl->counter = (unsigned *)((char *)pl->buf + (sizeof(MultiEntry) * n + 127) / 128 * 128);
+    if (e == hipSuccess)
+        e = hipMemset(pl->counter, 0, 2 * sizeof(unsigned));
+    if (e != hipSuccess) {
+        set_last_hip_error(e);
+        plan_free(pl);
+        return WL_EHIP;
     }
-    hipError_t e2 = hipFreeAsync(buf, st);
+    LaunchCfg c = multi_default(prec, nrhs);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_cache_locked();
+        auto it = g_tune.find(multi_key(pl));
+        if (it != g_tune.end() && nrhs % it->second.rpt == 0 &&
+            multi_launch_ok(prec, it->second.rpt, it->second.block, it->second.var))
+            c = it->second;
+    }
+    const int rc = plan_build(pl, c);
+    if (rc != WL_OK) {
+        plan_free(pl);
+        return rc;
+    }
+    *out = pl;
+    return WL_OK;
+}
+
+int wl_multi_plan_run(wl_multi_plan *pl, void *stream)
+{
+    if (!pl)
+        return WL_EINVAL;
+    CHECK_HIP(launch_multi(pl->prec, pl->dagger, pl->cfg.rpt, pl->cfg.block, pl->cfg.var, pl->dE, pl->n, pl->total,
+                           pl->counter, pl->grid, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wl_multi_plan_tune(wl_multi_plan *pl, void *stream)
+{
+    if (!pl)
+        return WL_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(hipStreamSynchronize(st));
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess)
-        e = e2;
-    // the host copy of E must outlive the async H2D copy
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(st);
+        e = hipEventCreate(&b);
+    LaunchCfg best = pl->cfg;
+    float best_ms = INFINITY;
+    const int blocks[] = {64, 128, 256, 512};
+    int rc = WL_OK;
+    for (int bi = 0; bi < 4 && e == hipSuccess && rc == WL_OK; ++bi)
+        for (int rpt = 1; rpt <= 4 && e == hipSuccess && rc == WL_OK; ++rpt)
+            for (int var = 0; var <= 3 && e == hipSuccess && rc == WL_OK; ++var) {
+                if (pl->nrhs % rpt != 0 || !multi_launch_ok(pl->prec, rpt, blocks[bi], var))
+                    continue;
+                if ((rc = plan_build(pl, LaunchCfg{blocks[bi], rpt, 0, var, 1})) != WL_OK)
+                    break;
+                for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                    e = launch_multi(pl->prec, pl->dagger, rpt, blocks[bi], var, pl->dE, pl->n, pl->total,
+                                     pl->counter, pl->grid, st);
+                const int reps = 10;
+                if (e == hipSuccess)
+                    e = hipEventRecord(a, st);
+                for (int k = 0; k < reps && e == hipSuccess; ++k)
+                    e = launch_multi(pl->prec, pl->dagger, rpt, blocks[bi], var, pl->dE, pl->n, pl->total,
+                                     pl->counter, pl->grid, st);
+                if (e == hipSuccess)
+                    e = hipEventRecord(b, st);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(b);
+                float ms = 0.f;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, a, b);
+                if (e == hipSuccess && ms < best_ms) {
+                    best_ms = ms;
+                    best = pl->cfg;
+                }
+            }
+    if (a)
+        (void)hipEventDestroy(a);
+    if (b)
+        (void)hipEventDestroy(b);
+    CHECK_HIP(e);
+    if (rc != WL_OK)
+        return rc;
+    if ((rc = plan_build(pl, best)) != WL_OK)
+        return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    g_tune[multi_key(pl)] = best;
+    save_tune_cache_locked();
+    return WL_OK;
+}
+
+int wl_multi_plan_get_launch(const wl_multi_plan *pl, int *block, int *rpt, int *variant, int *grid)
+{
+    if (!pl || !block || !rpt || !variant || !grid)
+        return WL_EINVAL;
+    *block = pl->cfg.block;
+    *rpt = pl->cfg.rpt;
+    *variant = pl->cfg.var;
+    *grid = pl->grid;
+    return WL_OK;
+}
+
+int wl_multi_plan_set_launch(wl_multi_plan *pl, int block, int rpt, int variant)
+{
+    if (!pl)
+        return WL_EINVAL;
+    return plan_build(pl, LaunchCfg{block, rpt, 0, variant, 1});
+}
+
+int wl_multi_plan_destroy(wl_multi_plan *pl)
+{
+    if (!pl)
+        return WL_EINVAL;
+    plan_free(pl);
+    return WL_OK;
+}
+
+int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void *stream)
+{
+    wl_multi_plan *pl = nullptr;
+    int rc = wl_multi_plan_create(d, n, dagger, nrhs, &pl);
+    if (rc != WL_OK)
+        return rc;
+    rc = wl_multi_plan_run(pl, stream);
+    // the plan's table must outlive the launch
+    const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    plan_free(pl);
+    if (rc != WL_OK)
+        return rc;
     CHECK_HIP(e);
     return WL_OK;
 }
 
-int wl_get_launch(const wl_op *op, int nrhs, int *block, int *rpt, int *xcd, int *variant)
+int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg)
 {
-    if (!op || nrhs < 1 || !block || !rpt || !xcd || !variant)
+    if (!op || nrhs < 1 || !cfg)
         return WL_EINVAL;
-    LaunchCfg c = launch_for(op, nrhs);
-    *block = c.block;
-    *rpt = c.rpt;
-    *xcd = c.xcd;
-    *variant = c.var;
+    const LaunchCfg c = launch_for(op, nrhs, RED_NONE);
+    cfg->block = c.block;
+    cfg->rhs_per_thread = c.rpt;
+    cfg->rhs_lanes = c.lanes;
+    cfg->xcd_remap = c.xcd;
+    cfg->variant = c.var;
     return WL_OK;
 }
 
-
-int wl_set_launch(wl_op *op, int nrhs, int block, int rpt, int xcd, int variant)
+int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg)
 {
-    if (!op || nrhs < 1)
+    if (!op || nrhs < 1 || !cfg)
         return WL_EINVAL;
-    const LaunchCfg c{block, rpt, xcd, variant};
+    LaunchCfg c;
+    c.block = cfg->block;
+    c.rpt = cfg->rhs_per_thread;
+    c.lanes = cfg->rhs_lanes;
+    c.xcd = cfg->xcd_remap;
+    c.var = cfg->variant;
     if (!launch_ok(op, nrhs, c))
         return WL_EINVAL;
     std::lock_guard<std::mutex> lk(op->mu);
-    op->launch[nrhs] = c;
+    for (int red = RED_NONE; red <= RED_DOTIN_NORM; ++red)  // every stencil of this nrhs
+        op->launch[launch_key(nrhs, red)] = c;
     return WL_OK;
 }
 
@@ -548,55 +750,74 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
         e = hipEventCreate(&a);
     if (e == hipSuccess)
         e = hipEventCreate(&b);
-    LaunchCfg best = default_launch(op, nrhs);
-    float best_ms = INFINITY;
     const int blocks[] = {64, 128, 256, 512};
     std::vector<LaunchCfg> cands;
     for (int bi = 0; bi < 4; ++bi)
         for (int rpt = 1; rpt <= max_rpt(op->prec); ++rpt)
-            for (int xcd = 0; xcd <= 2; ++xcd)
-                for (int var = 0; var <= max_var(op->prec); ++var) {
-                    const LaunchCfg c{blocks[bi], rpt, xcd, var};
-                    if (launch_ok(op, nrhs, c))
-                        cands.push_back(c);
-                }
-    for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
-        const LaunchCfg c = cands[ci];
-        StencilParams p = base_params(op, out, in, nrhs, 1);
-        for (int w = 0; w < 2 && e == hipSuccess; ++w)
-            e = launch_stencil(op->prec, dagger, c, p, st);
-        const int reps = 10;
-        if (e == hipSuccess)
-            e = hipEventRecord(a, st);
-        for (int k = 0; k < reps && e == hipSuccess; ++k)
-            e = launch_stencil(op->prec, dagger, c, p, st);
-        if (e == hipSuccess)
-            e = hipEventRecord(b, st);
-        if (e == hipSuccess)
-            e = hipEventSynchronize(b);
-        float ms = 0.f;
-        if (e == hipSuccess)
-            e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = c;
+            for (int lanes = 1; lanes <= 8; lanes *= 2)
+                for (int xcd = 0; xcd <= 5; ++xcd)
+                    for (int var = 0; var <= max_var(op->prec); ++var) {
+                        const LaunchCfg c{blocks[bi], rpt, xcd, var, lanes};
+                        if (var >= 4 && xcd >= 2)
+                            continue;  // the t-walk orders only distinguish 0 and 1
+                        if (launch_ok(op, nrhs, c))
+                            cands.push_back(c);
+                    }
+    // the plain apply, then each fused reduction of the solvers (partials
+    // and the <v, out> operand in scratch)
+    LaunchCfg bests[4];
+    double *parts = nullptr;
+    if (e == hipSuccess)
+        e = hipMalloc(&parts, 3 * sizeof(double) * (size_t)nrhs * ((op->V + 63) / 64 + op->g.dims[3] + 8));
+    for (int red = RED_NONE; red <= RED_DOTIN_NORM && e == hipSuccess; ++red) {
+        float best_ms = INFINITY;
+        LaunchCfg best = default_launch(op, nrhs);
+        for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
+            const LaunchCfg c = cands[ci];
+            StencilParams p = base_params(op, out, in, nrhs, 1);
+            p.red = red;
+            p.partials = parts;
+            p.aux = in;
+            for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                e = launch_stencil(op->prec, dagger, c, p, st);
+            const int reps = 10;
+            if (e == hipSuccess)
+                e = hipEventRecord(a, st);
+            for (int k = 0; k < reps && e == hipSuccess; ++k)
+                e = launch_stencil(op->prec, dagger, c, p, st);
+            if (e == hipSuccess)
+                e = hipEventRecord(b, st);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, a, b);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
         }
+        bests[red] = best;
     }
     if (a)
         (void)hipEventDestroy(a);
     if (b)
         (void)hipEventDestroy(b);
+    if (parts)
+        (void)hipFree(parts);
     (void)hipFree(in);
     (void)hipFree(out);
     CHECK_HIP(e);
     {
         wl_op *o = const_cast<wl_op *>(op);
         std::lock_guard<std::mutex> lk(o->mu);
-        o->launch[nrhs] = best;
+        for (int red = RED_NONE; red <= RED_DOTIN_NORM; ++red)
+            o->launch[launch_key(nrhs, red)] = bests[red];
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache_locked();
-    g_tune[tune_key(op, nrhs, 0)] = best;
+    for (int red = RED_NONE; red <= RED_DOTIN_NORM; ++red)
+        g_tune[tune_key_red(op, nrhs, red)] = bests[red];
     save_tune_cache_locked();
     return WL_OK;
 }

@@ -345,21 +345,35 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t b, uint32_t nb, int xcd)
     return k * q + (k < r ? k : r) + j;
 }
 
-// Slab order (xcd mode 2): XCD k owns the z-slab [k Lz/8, (k+1) Lz/8) and
-// walks it t-major, so the +-t neighbours of its in-flight sites are in its
-// own recent traffic (its L2) instead of one full t-slice away.  Needs
-// Lz % 8 == 0 and a block size dividing V / 8 (the host checks).
-// slab_xy = Lx Ly, slab_n = Lx Ly Lz / 8 sites per slab t-slice.
-__device__ __forceinline__ uint32_t slab_site(uint32_t b, uint32_t tid, uint32_t block, uint32_t slab_xy,
-                                              FastDiv f_slab_n, FastDiv f_slab_xy, uint32_t slab_n, uint32_t vslice)
+// Slab orders (xcd modes 2..5): XCD k owns the z-slab [k Zs, (k+1) Zs),
+// Zs = Lz / 8, cut into y-chunks of Yc = Ly >> (mode - 2) rows; it walks the
+// chunks one after the other, each t-major (t, z, y, x).  The +-t (and +-z)
+// neighbours of the sites in flight were then fetched at most two chunk
+// t-slices (Lx Yc Zs sites) earlier by the same XCD, i.e. are in its L2;
+// smaller chunks shorten that distance at the price of misses on the chunk
+// faces in y.  Needs Lz % 8 == 0, Ly % 2^(mode - 2) == 0 and a block size
+// dividing V / 8 (the host checks).
+struct SlabOrder {
+    FastDiv f_chunk, f_slice, f_plane;  // divisions by chunk_n, slice_n, plane_n
+    uint32_t chunk_n;                   // Lx Yc Zs Lt: sites of one chunk
+    uint32_t slice_n;                   // Lx Yc Zs: one t-slice of a chunk
+    uint32_t plane_n;                   // Lx Yc: one z-plane of a chunk slice
+    uint32_t xy;                        // Lx Ly
+    uint32_t zs;                        // Lz / 8
+    uint32_t vslice;                    // Lx Ly Lz
+};
+
+__device__ __forceinline__ uint32_t slab_site(uint32_t b, uint32_t tid, uint32_t block, const SlabOrder &o)
 {
     const uint32_t k = b & 7u, j = b >> 3;
-    const uint32_t l = j * block + tid;
-    const uint32_t t = fdiv(l, f_slab_n);
-    const uint32_t rem = l - t * slab_n;
-    const uint32_t z = fdiv(rem, f_slab_xy);
-    const uint32_t xy = rem - z * slab_xy;
-    return xy + slab_xy * (k * (slab_n / slab_xy) + z) + vslice * t;
+    uint32_t r = j * block + tid;  // position in XCD k's walk
+    const uint32_t c = fdiv(r, o.f_chunk);
+    r -= c * o.chunk_n;
+    const uint32_t t = fdiv(r, o.f_slice);
+    r -= t * o.slice_n;
+    const uint32_t z = fdiv(r, o.f_plane);
+    r -= z * o.plane_n;  // r = x + Lx (y - c Yc)
+    return r + o.plane_n * c + o.xy * (k * o.zs + z) + o.vslice * t;
 }
 
 // ---------------------------------------------------------------- reductions
@@ -392,6 +406,38 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *lds)
             double a = 0.0;
             for (int k = 0; k < nw; ++k)
                 a += lds[i * nw + k];
+            v[i] = a;
+        }
+    }
+}
+
+// Block sums of N values per thread for lane-interleaved right-hand sides:
+// a wavefront holds 2^lg segments of 64 >> lg lanes, segment j serving
+// right-hand side j.  Thread j < 2^lg returns the sums of segment j over the
+// block (lg = 0 is block_sum).  Fixed order, so deterministic.  `lds` must
+// hold N * 2^lg * (blockDim.x / 64) doubles.
+template <int N>
+__device__ __forceinline__ void block_sum_lanes(double (&v)[N], double *lds, int lg)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int seg = 64 >> lg, nl = 1 << lg;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        for (int o = seg >> 1; o > 0; o >>= 1)
+            v[i] += __shfl_xor(v[i], o, 64);
+    if ((lane & (seg - 1)) == 0) {
+        const int j = lane / seg;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            lds[(i * nl + j) * nw + w] = v[i];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nl) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double a = 0.0;
+            for (int k = 0; k < nw; ++k)
+                a += lds[(i * nl + threadIdx.x) * nw + k];
             v[i] = a;
         }
     }

@@ -17,10 +17,12 @@ namespace wl {
 
 // Launch configuration of the stencil.
 struct LaunchCfg {
-    int block = 256;  // threads per workgroup (= sites per tile)
+    int block = 256;  // threads per workgroup (= sites per tile x lanes)
     int rpt = 1;      // right-hand sides per thread
-    int xcd = 1;      // tile order: 0 natural, 1 contiguous range per XCD, 2 z-slab per XCD (t-major)
+    int xcd = 1;      // tile order: 0 natural, 1 contiguous range per XCD, 2..5 z-slab per XCD walked
+                      // t-major in y-chunks of Ly >> (xcd - 2) rows
     int var = 0;      // stencil code variant (0 = straight-line hops; 1..3 = pipelined, R = 1 only)
+    int lanes = 1;    // right-hand sides interleaved across the lanes of a wavefront (1, 2, 4, 8; rpt = 1)
 };
 
 }  // namespace wl
@@ -62,10 +64,14 @@ struct StencilParams {
     int apply;  // 1: out = in - kappa H in; 0: out = H in
     int red;
     int xcd;
-    int nblk;   // number of site tiles (gridDim.x)
-    // slab order (xcd == 2)
-    FastDiv f_slab_n, f_slab_xy;
-    uint32_t slab_n, slab_xy, vslice;
+    int nblk;   // number of site tiles (partials per right-hand side)
+    // multi-RHS launches: ng right-hand-side groups per tile, interleaved
+    // with the tiles (see tile_group); ntile = tiles in the launch, padded
+    // to a multiple of 8 when ng > 1
+    uint32_t ng, ntile;
+    FastDiv f_ng;
+    int lanes_lg;  // log2 of the right-hand sides interleaved across lanes
+    SlabOrder slab;  // xcd >= 2
     const struct Scalars *skip;  // in a solver loop: skip a workgroup whose columns are all frozen
     float one;                   // 1.0 (see project())
 };
@@ -76,16 +82,17 @@ int stencil_nval(int red);
 int max_rpt(int prec);  // largest right-hand sides per thread the stencil offers
 int max_var(int prec);  // largest stencil code variant for R = 1
 bool var_ok(int prec, int var);  // variant exists for this precision
-int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V);  // partials written by one launch
-bool slab_ok(const int *L, int block);  // slab order usable for these extents and block size
+int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V, int nrhs);  // partials per RHS of one launch
+bool slab_ok(const int *L, int block, int mode);  // slab order `mode` usable for these extents and block size
 
 struct MultiEntry {
-    StencilParams p;
-    uint32_t tile_begin;  // prefix of tiles
+    StencilParams p;      // per lattice; ng / f_ng = RHS groups per tile
+    uint32_t tile_begin;  // first work item of this lattice
 };
-hipError_t launch_multi(int prec, int dagger, int rpt, int block, const MultiEntry *dev_entries, int n,
-                        uint32_t total_tiles, unsigned *counter, int grid, hipStream_t st);
-int multi_grid_size(int prec, int dagger, int rpt, int block);
+bool multi_launch_ok(int prec, int rpt, int block, int var);
+hipError_t launch_multi(int prec, int dagger, int rpt, int block, int var, const MultiEntry *dev_entries, int n,
+                        uint32_t total_items, unsigned *counter, int grid, hipStream_t st);
+int multi_grid_size(int prec, int dagger, int rpt, int block, int var);
 
 hipError_t launch_force(int prec, const wl_op *op, void *out, const void *x, const void *mu, int project,
                         hipStream_t st);

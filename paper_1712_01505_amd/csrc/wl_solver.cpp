@@ -25,7 +25,7 @@ namespace wl {
 
 hipError_t prof_stencil(int prec, const wl_op *op, int dagger, const LaunchCfg &cfg, StencilParams p,
                         hipStream_t st);  // wl_api.cpp
-LaunchCfg launch_for(const wl_op *op, int nrhs);  // wl_api.cpp
+LaunchCfg launch_for(const wl_op *op, int nrhs, int red);  // wl_api.cpp
 void set_last_hip_error(hipError_t e);           // wl_api.cpp
 
 namespace {
@@ -39,8 +39,9 @@ size_t vec_bytes(int prec, uint32_t V, int nrhs) { return (size_t)nrhs * V * spi
 
 // Largest number of per-workgroup partials any kernel here produces (the
 // t-walk stencil writes at most one per 64 (x,y,z) sites per t-column step,
-// i.e. at most V/64 + Lt).
-size_t max_nblk(uint32_t V, int Lt) { return (V + 63) / 64 + (size_t)Lt; }
+// i.e. at most V/64 + Lt; multi-RHS launches pad the tile count to a
+// multiple of 8).
+size_t max_nblk(uint32_t V, int Lt) { return (V + 63) / 64 + (size_t)Lt + 8; }
 size_t partial_bytes(uint32_t V, int Lt, int nrhs)
 {
     return align_up(3 * (size_t)nrhs * max_nblk(V, Lt) * sizeof(double));
@@ -201,9 +202,9 @@ struct Engine {
         p.kappa = op->kappa;
         p.apply = 1;
         p.red = red;
-        LaunchCfg cfg = launch_for(op, nrhs);
+        LaunchCfg cfg = launch_for(op, nrhs, red);
         if (slot >= 0) {
-            nblk[slot] = stencil_partials(cfg, p.L, V);
+            nblk[slot] = stencil_partials(cfg, p.L, V, nrhs);
             nval[slot] = stencil_nval(red);
         }
         ++stencil_calls;

@@ -401,6 +401,27 @@ __device__ __forceinline__ void scale_site(cx<typename Traits<P>::real> (&v)[12]
 
 // Spatial hops of the t-walk are pipelined G at a time; FP64 does not carry
 // the site's own spinor (register budget) and reloads it, a near reuse.
+// Workgroup -> (tile, right-hand-side group).  Single-group launches use
+// blockIdx.x as the tile.  With ng > 1 groups the grid is one-dimensional
+// and, among the workgroups that land on one XCD (b = 8 k + xcd under the
+// round-robin dispatch), the group index runs fastest: the ng groups of a
+// tile execute back to back on the same XCD, so the links and neighbour
+// spinors they share are re-read from that XCD's L2 instead of HBM.  The
+// tile keeps b's XCD (bt = b mod 8), so the per-XCD tile orders below still
+// apply; ntile is a multiple of 8 there, which makes the map a bijection.
+__device__ __forceinline__ uint32_t tile_group(const StencilParams &p, int &g)
+{
+    const uint32_t b = blockIdx.x;
+    if (p.ng == 1) {
+        g = 0;
+        return b;
+    }
+    const uint32_t k = b >> 3;
+    const uint32_t q = fdiv(k, p.f_ng);
+    g = (int)(k - q * p.ng);
+    return (q << 3) | (b & 7u);
+}
+
 template <int P>
 struct TwalkG {
     static constexpr int G = P == F64 ? 1 : P == F32 ? 2 : 3;
@@ -417,17 +438,18 @@ __global__ __launch_bounds__(512) void twalk_kernel(StencilParams p, int T, uint
     constexpr int G = TwalkG<P>::G;
     constexpr bool CARRY = TwalkG<P>::CARRY_SELF;
     __shared__ double lds[(NV > 0 ? NV : 1) * 8];
-    const int rhs = blockIdx.y;
+    int rhs;
+    const uint32_t bt = tile_group(p, rhs);
     if (p.skip && p.skip[rhs].frozen)
         return;
-    const uint32_t unit = tile_of(blockIdx.x, gridDim.x, p.xcd ? 1 : 0);
+    const uint32_t unit = tile_of(bt, p.ntile, p.xcd ? 1 : 0);
     const uint32_t chunk = unit / nbxyz;
     const uint32_t sx = (unit - chunk * nbxyz) * blockDim.x + threadIdx.x;
     double red[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < (NV > 0 ? NV : 1); ++i)
         red[i] = 0.0;
-    if (sx < nxyz) {
+    if (sx < nxyz && (int)chunk * T < p.L[3]) {  // padded multi-RHS grids have idle units
         // spatial coordinates and neighbours (in the xyz index), fixed along the walk
         const uint32_t q1 = fdiv(sx, p.fx);
         const int x = (int)(sx - q1 * (uint32_t)p.L[0]);
@@ -576,7 +598,7 @@ __global__ __launch_bounds__(512) void twalk_kernel(StencilParams p, int T, uint
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int k = 0; k < NV; ++k)
-                p.partials[((size_t)k * p.nrhs + rhs) * p.nblk + blockIdx.x] = red[k];
+                p.partials[((size_t)k * p.nrhs + rhs) * p.nblk + bt] = red[k];
         }
     }
 }
@@ -608,16 +630,24 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 {
     using T = typename Traits<P>::real;
     constexpr int NV = RED == RED_NORM ? 1 : RED == RED_DOTV ? 2 : RED == RED_DOTIN_NORM ? 3 : 0;
-    __shared__ double lds[(NV > 0 ? NV : 1) * R * 8];
-    const uint32_t s = p.xcd == 2 ? slab_site(blockIdx.x, threadIdx.x, blockDim.x, p.slab_xy, p.f_slab_n, p.f_slab_xy,
-                                              p.slab_n, p.vslice)
-                                  : tile_of(blockIdx.x, gridDim.x, p.xcd) * blockDim.x + threadIdx.x;
-    const int r0 = blockIdx.y * R;
+    __shared__ double lds[(NV > 0 ? NV : 1) * (R > 1 ? R : 8) * 8];
+    int grp;
+    const uint32_t bt = tile_group(p, grp);
+    // right-hand sides across lanes (R = 1 only): segment j of 64 >> lg lanes
+    // of every wavefront serves right-hand side grp 2^lg + j, so the links of
+    // a site are fetched once per instruction for all 2^lg of them
+    const int lg = p.lanes_lg;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t seg = 64u >> lg;
+    const uint32_t tsite = ((threadIdx.x >> 6) << (6 - lg)) + (lane & (seg - 1u));
+    const uint32_t tile = blockDim.x >> lg;
+    const uint32_t s = p.xcd >= 2 ? slab_site(bt, tsite, tile, p.slab) : tile_of(bt, p.ntile, p.xcd) * tile + tsite;
+    const int r0 = (grp << lg) * R + (int)(lane >> (6 - lg));
     if (p.skip) {  // solver loop: every column of this workgroup has stopped
         bool all = true;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            all = all && p.skip[r0 + r].frozen;
+        const int rb = (grp << lg) * R;
+        for (int r = 0; r < (R << lg); ++r)
+            all = all && p.skip[rb + r].frozen;
         if (all)
             return;
     }
@@ -693,24 +723,44 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
         }
     }
     if constexpr (NV > 0) {
-        block_sum<NV * R>(red, lds);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
+        if constexpr (R == 1) {
+            block_sum_lanes<NV>(red, lds, lg);
+            if ((int)threadIdx.x < (1 << lg)) {
 #pragma unroll
                 for (int k = 0; k < NV; ++k)
-                    p.partials[((size_t)k * p.nrhs + r0 + r) * p.nblk + blockIdx.x] = red[NV * r + k];
+                    p.partials[((size_t)k * p.nrhs + (grp << lg) + threadIdx.x) * p.nblk + bt] = red[k];
+            }
+        } else {
+            block_sum<NV * R>(red, lds);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k < NV; ++k)
+                        p.partials[((size_t)k * p.nrhs + r0 + r) * p.nblk + bt] = red[NV * r + k];
+            }
         }
     }
 }
 
-bool slab_ok(const int *L, int block)
+bool slab_ok(const int *L, int block, int mode)
 {
+    if (mode < 2 || mode > 5)
+        return false;
     const uint64_t slab = (uint64_t)L[0] * L[1] * (L[2] / 8) * L[3];
-    return L[2] % 8 == 0 && slab % (uint64_t)block == 0;
+    return L[2] % 8 == 0 && L[1] % (1 << (mode - 2)) == 0 && slab % (uint64_t)block == 0;
 }
 
 int stencil_nval(int red) { return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : 0; }
+
+// Tile count and right-hand-side groups of a launch (see tile_group).
+static void set_groups(StencilParams &p, uint32_t tiles, uint32_t ng)
+{
+    p.ng = ng;
+    p.f_ng = make_fastdiv(ng);
+    p.ntile = ng > 1 ? (tiles + 7u) & ~7u : tiles;
+    p.nblk = (int)p.ntile;
+}
 
 template <int P, int DAG, int R, int VAR>
 static hipError_t launch_v(dim3 grid, dim3 block, const StencilParams &p, hipStream_t st)
@@ -742,8 +792,10 @@ static hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_
     const uint32_t nxyz = (uint32_t)p.L[0] * p.L[1] * p.L[2];
     const uint32_t nbxyz = (nxyz + cfg.block - 1) / cfg.block;
     const uint32_t units = nbxyz * (uint32_t)(p.L[3] / T);
-    p.nblk = (int)units;
-    dim3 grid(units, p.nrhs), block(cfg.block);
+    set_groups(p, units, (uint32_t)p.nrhs);
+    if ((uint64_t)p.ntile * p.ng > 0x7fffffffull)
+        return hipErrorInvalidValue;
+    dim3 grid(p.ntile * p.ng), block(cfg.block);
     if (!p.apply) {
         if (p.red != RED_NONE)
             return hipErrorInvalidValue;
@@ -762,20 +814,28 @@ static hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_
     return hipGetLastError();
 }
 
-// Number of per-workgroup partials a launch with this configuration writes.
-int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V)
+static uint32_t pad8(uint32_t n) { return (n + 7u) & ~7u; }
+
+// Number of per-workgroup partials (per right-hand side) a launch with this
+// configuration writes.
+int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V, int nrhs)
 {
+    const uint32_t tile = (uint32_t)(cfg.block / cfg.lanes);
+    uint32_t n = (V + tile - 1) / tile;
     if (cfg.rpt == 1 && cfg.var >= 4) {
         const uint32_t nxyz = (uint32_t)L[0] * L[1] * L[2];
-        return (int)(((nxyz + cfg.block - 1) / cfg.block) * (uint32_t)(L[3] / twalk_T(cfg.var)));
+        n = ((nxyz + cfg.block - 1) / cfg.block) * (uint32_t)(L[3] / twalk_T(cfg.var));
     }
-    return (int)((V + cfg.block - 1) / cfg.block);
+    return (int)(nrhs / (cfg.rpt * cfg.lanes) > 1 ? pad8(n) : n);
 }
 
 template <int P, int DAG, int R>
 static hipError_t launch_t(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
 {
-    dim3 grid(p.nblk, p.nrhs / R), block(cfg.block);
+    set_groups(p, (uint32_t)p.nblk, (uint32_t)(p.nrhs / (R << p.lanes_lg)));
+    if ((uint64_t)p.ntile * p.ng > 0x7fffffffull)
+        return hipErrorInvalidValue;
+    dim3 grid(p.ntile * p.ng), block(cfg.block);
     if constexpr (R == 1) {
         switch (cfg.var) {
         case 0: return launch_v<P, DAG, 1, 0>(grid, block, p, st);
@@ -825,20 +885,31 @@ int max_rpt(int prec) { return prec == F64 ? 2 : 4; }
 
 hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st)
 {
+    const int lg = cfg.lanes == 1 ? 0 : cfg.lanes == 2 ? 1 : cfg.lanes == 4 ? 2 : cfg.lanes == 8 ? 3 : -1;
     if (cfg.rpt < 1 || cfg.rpt > 4 || p.nrhs % cfg.rpt != 0 || cfg.block < 64 || cfg.block > 512 ||
-        cfg.block % 64 != 0)
+        cfg.block % 64 != 0 || lg < 0 ||
+        (lg > 0 && (cfg.rpt != 1 || cfg.var >= 4 || p.nrhs % cfg.lanes != 0 || (cfg.block >> lg) < 64)))
         return hipErrorInvalidValue;
-    p.nblk = (int)((p.V + cfg.block - 1) / cfg.block);
+    p.lanes_lg = lg;
+    const int tile = cfg.block >> lg;
+    p.nblk = (int)((p.V + tile - 1) / tile);
     p.xcd = cfg.xcd;
     p.one = 1.0f;
-    if (p.xcd == 2) {
-        if (!slab_ok(p.L, cfg.block))
+    if (p.xcd >= 2 && !(cfg.rpt == 1 && cfg.var >= 4)) {  // the t-walk kernels use modes 0 / 1 only
+        if (!slab_ok(p.L, tile, p.xcd))
             return hipErrorInvalidValue;
-        p.slab_xy = (uint32_t)p.L[0] * (uint32_t)p.L[1];
-        p.slab_n = p.slab_xy * (uint32_t)(p.L[2] / 8);
-        p.vslice = p.slab_xy * (uint32_t)p.L[2];
-        p.f_slab_n = make_fastdiv(p.slab_n);
-        p.f_slab_xy = make_fastdiv(p.slab_xy);
+        const uint32_t Lx = (uint32_t)p.L[0], Ly = (uint32_t)p.L[1], Lz = (uint32_t)p.L[2], Lt = (uint32_t)p.L[3];
+        const uint32_t yc = Ly >> (p.xcd - 2);
+        SlabOrder &o = p.slab;
+        o.zs = Lz / 8;
+        o.plane_n = Lx * yc;
+        o.slice_n = o.plane_n * o.zs;
+        o.chunk_n = o.slice_n * Lt;
+        o.xy = Lx * Ly;
+        o.vslice = o.xy * Lz;
+        o.f_chunk = make_fastdiv(o.chunk_n);
+        o.f_slice = make_fastdiv(o.slice_n);
+        o.f_plane = make_fastdiv(o.plane_n);
     }
     switch (prec * 2 + (dagger ? 1 : 0)) {
     case 0: return launch_r<F64, 0>(cfg, p, st);
@@ -854,30 +925,41 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
 }
 
 // ---------------------------------------------------------------- multi-lattice
-// One persistent grid; each workgroup pops (lattice, site tile, RHS group)
-// work items from a device-wide counter until the queue is empty, so uneven
-// lattices share one launch.  Every workgroup leaves the loop once the
-// counter passes the total, so the grid always drains.
-template <int P, int DAG, int R>
+// One persistent grid; each workgroup pops work items (lattice, site tile,
+// RHS group; the group index fastest within a lattice) from a device-wide
+// counter until the queue is empty, so uneven lattices share one launch.
+// counter[0] is the queue head, counter[1] counts workgroups that have left
+// the loop: the last one to leave resets both to zero, so the queue is ready
+// for the next launch without a host-side reset.  Every workgroup leaves the
+// loop once the head passes the total, so the grid always drains.
+template <int P, int DAG, int R, int VAR>
 __global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, uint32_t total, unsigned *counter)
 {
     using T = typename Traits<P>::real;
-    __shared__ unsigned tile_s;
+    __shared__ unsigned item_s;
+    if (threadIdx.x == 0)
+        item_s = atomicAdd(&counter[0], 1u);
+    __syncthreads();
+    unsigned t = item_s;
     for (;;) {
-        if (threadIdx.x == 0)
-            tile_s = atomicAdd(counter, 1u);
-        __syncthreads();
-        const unsigned t = tile_s;
-        __syncthreads();
+        __syncthreads();  // everyone has read item_s
         if (t >= total)
             break;
-        int i = 0;
-        while (i + 1 < n && E[i + 1].tile_begin <= t)
-            ++i;
-        const StencilParams p = E[i].p;
-        const uint32_t local = t - E[i].tile_begin;
-        const uint32_t lt = local % (uint32_t)p.nblk;
-        const int r0 = (int)(local / (uint32_t)p.nblk) * R;
+        // pop the next item now, so the atomic's latency overlaps this one
+        if (threadIdx.x == 0)
+            item_s = atomicAdd(&counter[0], 1u);
+        int lo = 0, hi = n - 1;  // last entry with tile_begin <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (E[mid].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const StencilParams p = E[lo].p;
+        const uint32_t local = t - E[lo].tile_begin;
+        const uint32_t lt = fdiv(local, p.f_ng);
+        const int r0 = (int)(local - lt * p.ng) * R;
         const uint32_t s = lt * blockDim.x + threadIdx.x;
         if (s < p.V) {
             cx<T> acc[R][12];
@@ -886,7 +968,10 @@ __global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, 
 #pragma unroll
                 for (int k = 0; k < 12; ++k)
                     acc[r][k] = cx<T>{T(0), T(0)};
-            hop_site<P, DAG, R>(p, s, r0, acc);
+            if constexpr (VAR == 0 || R > 1)
+                hop_site<P, DAG, R>(p, s, r0, acc);
+            else
+                hop_site_pipe<P, DAG, VarG<P, VAR>::G>(p, s, r0, acc[0]);
             const T kap = (T)p.kappa;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -898,14 +983,90 @@ __global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, 
                 store_site_q<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
             }
         }
+        __syncthreads();  // item_s written
+        t = item_s;
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's last pop precedes its exit count
+        if (atomicAdd(&counter[1], 1u) == gridDim.x - 1) {
+            atomicExch(&counter[0], 0u);
+            atomicExch(&counter[1], 0u);
+        }
     }
 }
 
-template <int P, int DAG, int R>
-static int multi_grid_t(int block)
+// Multi-lattice launch shapes: R in {1, 2, 4} (FP64: 1, 2); R = 1 takes the
+// pipelined code variants 1..3 where the precision offers them.
+static bool multi_shape_ok(int prec, int rpt, int var)
 {
+    if (rpt != 1 && rpt != 2 && rpt != 4)
+        return false;
+    if (prec == F64 && rpt == 4)
+        return false;
+    if (rpt > 1)
+        return var == 0;
+    return var >= 0 && var <= 3 && var_ok(prec, var);
+}
+
+template <int P, int DAG, int R, int VAR>
+static const void *multi_fn()
+{
+    return reinterpret_cast<const void *>(&multi_kernel<P, DAG, R, VAR>);
+}
+
+template <int P, int DAG>
+static const void *multi_pick(int rpt, int var)
+{
+    if (rpt == 2)
+        return multi_fn<P, DAG, 2, 0>();
+    if constexpr (P != F64)
+        if (rpt == 4)
+            return multi_fn<P, DAG, 4, 0>();
+    switch (var) {
+    case 0: return multi_fn<P, DAG, 1, 0>();
+    case 1: return multi_fn<P, DAG, 1, 1>();
+    case 2:
+        if constexpr (P != F64)
+            return multi_fn<P, DAG, 1, 2>();
+        return nullptr;
+    case 3:
+        if constexpr (P == BF16S || P == F16S)
+            return multi_fn<P, DAG, 1, 3>();
+        return nullptr;
+    default: return nullptr;
+    }
+}
+
+static const void *multi_kernel_ptr(int prec, int dagger, int rpt, int var)
+{
+    if (!multi_shape_ok(prec, rpt, var))
+        return nullptr;
+    switch (prec * 2 + (dagger ? 1 : 0)) {
+    case 0: return multi_pick<F64, 0>(rpt, var);
+    case 1: return multi_pick<F64, 1>(rpt, var);
+    case 2: return multi_pick<F32, 0>(rpt, var);
+    case 3: return multi_pick<F32, 1>(rpt, var);
+    case 4: return multi_pick<BF16S, 0>(rpt, var);
+    case 5: return multi_pick<BF16S, 1>(rpt, var);
+    case 6: return multi_pick<F16S, 0>(rpt, var);
+    case 7: return multi_pick<F16S, 1>(rpt, var);
+    default: return nullptr;
+    }
+}
+
+bool multi_launch_ok(int prec, int rpt, int block, int var)
+{
+    return block >= 64 && block <= 512 && block % 64 == 0 && multi_shape_ok(prec, rpt, var);
+}
+
+// Resident workgroups for a full machine: occupancy per CU x CUs.
+int multi_grid_size(int prec, int dagger, int rpt, int block, int var)
+{
+    const void *fn = multi_kernel_ptr(prec, dagger, rpt, var);
+    if (!fn)
+        return 0;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel<P, DAG, R>, block, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess)
         per_cu = 1;
     int dev = 0, ncu = 0;
     (void)hipGetDevice(&dev);
@@ -913,67 +1074,14 @@ static int multi_grid_t(int block)
     return (per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
 }
 
-template <int P, int DAG>
-static hipError_t launch_multi_r(int rpt, int block, const MultiEntry *E, int n, uint32_t total, unsigned *counter,
-                                 int grid, hipStream_t st)
+hipError_t launch_multi(int prec, int dagger, int rpt, int block, int var, const MultiEntry *E, int n,
+                        uint32_t total, unsigned *counter, int grid, hipStream_t st)
 {
-    switch (rpt) {
-    case 1: hipLaunchKernelGGL((multi_kernel<P, DAG, 1>), dim3(grid), dim3(block), 0, st, E, n, total, counter); break;
-    case 2: hipLaunchKernelGGL((multi_kernel<P, DAG, 2>), dim3(grid), dim3(block), 0, st, E, n, total, counter); break;
-    case 4:
-        if constexpr (P != F64) {
-            hipLaunchKernelGGL((multi_kernel<P, DAG, 4>), dim3(grid), dim3(block), 0, st, E, n, total, counter);
-            break;
-        }
+    const void *fn = multi_kernel_ptr(prec, dagger, rpt, var);
+    if (!fn || grid < 1)
         return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int P, int DAG>
-static int multi_grid_r(int rpt, int block)
-{
-    switch (rpt) {
-    case 1: return multi_grid_t<P, DAG, 1>(block);
-    case 2: return multi_grid_t<P, DAG, 2>(block);
-    case 4:
-        if constexpr (P != F64)
-            return multi_grid_t<P, DAG, 4>(block);
-        return 0;
-    default: return 0;
-    }
-}
-
-int multi_grid_size(int prec, int dagger, int rpt, int block)
-{
-    switch (prec * 2 + (dagger ? 1 : 0)) {
-    case 0: return multi_grid_r<F64, 0>(rpt, block);
-    case 1: return multi_grid_r<F64, 1>(rpt, block);
-    case 2: return multi_grid_r<F32, 0>(rpt, block);
-    case 3: return multi_grid_r<F32, 1>(rpt, block);
-    case 4: return multi_grid_r<BF16S, 0>(rpt, block);
-    case 5: return multi_grid_r<BF16S, 1>(rpt, block);
-    case 6: return multi_grid_r<F16S, 0>(rpt, block);
-    case 7: return multi_grid_r<F16S, 1>(rpt, block);
-    default: return 0;
-    }
-}
-
-hipError_t launch_multi(int prec, int dagger, int rpt, int block, const MultiEntry *E, int n, uint32_t total,
-                        unsigned *counter, int grid, hipStream_t st)
-{
-    switch (prec * 2 + (dagger ? 1 : 0)) {
-    case 0: return launch_multi_r<F64, 0>(rpt, block, E, n, total, counter, grid, st);
-    case 1: return launch_multi_r<F64, 1>(rpt, block, E, n, total, counter, grid, st);
-    case 2: return launch_multi_r<F32, 0>(rpt, block, E, n, total, counter, grid, st);
-    case 3: return launch_multi_r<F32, 1>(rpt, block, E, n, total, counter, grid, st);
-    case 4: return launch_multi_r<BF16S, 0>(rpt, block, E, n, total, counter, grid, st);
-    case 5: return launch_multi_r<BF16S, 1>(rpt, block, E, n, total, counter, grid, st);
-    case 6: return launch_multi_r<F16S, 0>(rpt, block, E, n, total, counter, grid, st);
-    case 7: return launch_multi_r<F16S, 1>(rpt, block, E, n, total, counter, grid, st);
-    default: return hipErrorInvalidValue;
-    }
+    void *args[] = {(void *)&E, (void *)&n, (void *)&total, (void *)&counter};
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
 }
 
 // ---------------------------------------------------------------- link force

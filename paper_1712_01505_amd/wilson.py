@@ -35,7 +35,8 @@ EXPORTS = [
     "wl_op_create", "wl_op_destroy", "wilson_dslash", "wilson_apply", "wl_solver_workspace_bytes",
     "solve_cgnr", "solve_bicgstab", "wilson_gauge_force", "wilson_multi_apply", "wl_autotune",
     "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read",
-    "wl_stream_copy", "wl_strerror", "wl_last_hip_error",
+    "wl_stream_copy", "wl_strerror", "wl_last_hip_error", "wl_multi_plan_create", "wl_multi_plan_run",
+    "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
 ]
 
 
@@ -57,6 +58,11 @@ class wl_solve_stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class wl_launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("rhs_per_thread", ctypes.c_int), ("rhs_lanes", ctypes.c_int),
+                ("xcd_remap", ctypes.c_int), ("variant", ctypes.c_int)]
 
 
 class wl_multi_desc(ctypes.Structure):
@@ -102,14 +108,20 @@ def lib():
         "wilson_gauge_force": [P, P, P, P, I, P],
         "wilson_multi_apply": [ctypes.POINTER(wl_multi_desc), I, I, I, P],
         "wl_autotune": [P, I, I, P],
-        "wl_get_launch": [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
-        "wl_set_launch": [P, I, I, I, I, I],
+        "wl_get_launch": [P, I, ctypes.POINTER(wl_launch)],
+        "wl_set_launch": [P, I, ctypes.POINTER(wl_launch)],
         "wl_prof_enable": [I],
         "wl_prof_reset": [],
         "wl_prof_read": [I, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), ctypes.POINTER(D)],
         "wl_stream_copy": [P, P, SZ, P],
         "wl_strerror": [I],
         "wl_last_hip_error": [],
+        "wl_multi_plan_create": [ctypes.POINTER(wl_multi_desc), I, I, I, ctypes.POINTER(P)],
+        "wl_multi_plan_run": [P, P],
+        "wl_multi_plan_tune": [P, P],
+        "wl_multi_plan_get_launch": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
+        "wl_multi_plan_set_launch": [P, I, I, I],
+        "wl_multi_plan_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -212,19 +224,54 @@ def wilson_multi_apply(descs, dagger, nrhs, stream):
     return _check(lib().wilson_multi_apply(arr, len(descs), int(dagger), nrhs, stream), "wilson_multi_apply")
 
 
+class MultiPlan:
+    """Several lattices in one persistent launch (wl_multi_plan_*): descs is
+    a list of (op handle, out pointer, in pointer); the buffers must outlive
+    the plan."""
+
+    def __init__(self, descs, dagger, nrhs):
+        arr = (wl_multi_desc * len(descs))(*[wl_multi_desc(o, out, inp) for o, out, inp in descs])
+        h = ctypes.c_void_p()
+        _check(lib().wl_multi_plan_create(arr, len(descs), int(dagger), int(nrhs), ctypes.byref(h)),
+               "wl_multi_plan_create")
+        self.handle = h.value
+
+    def run(self, stream=None):
+        _check(lib().wl_multi_plan_run(self.handle, _stream() if stream is None else stream), "wl_multi_plan_run")
+
+    def tune(self, stream=None):
+        _check(lib().wl_multi_plan_tune(self.handle, _stream() if stream is None else stream), "wl_multi_plan_tune")
+
+    def launch(self):
+        b, r, v, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().wl_multi_plan_get_launch(self.handle, ctypes.byref(b), ctypes.byref(r), ctypes.byref(v),
+                                              ctypes.byref(g)), "wl_multi_plan_get_launch")
+        return b.value, r.value, v.value, g.value
+
+    def set_launch(self, block, rpt, variant):
+        """Force a launch shape; returns False if the library rejects it."""
+        return lib().wl_multi_plan_set_launch(self.handle, block, rpt, variant) == WL_OK
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.wl_multi_plan_destroy(self.handle)
+            self.handle = None
+
+
 def wl_autotune(op, nrhs, dagger, stream):
     return _check(lib().wl_autotune(op, nrhs, int(dagger), stream), "wl_autotune")
 
 
 def wl_get_launch(op, nrhs):
-    b, r, x, v = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(lib().wl_get_launch(op, nrhs, ctypes.byref(b), ctypes.byref(r), ctypes.byref(x), ctypes.byref(v)),
-           "wl_get_launch")
-    return b.value, r.value, x.value, v.value
+    """(block, rhs_per_thread, xcd_remap, variant, rhs_lanes) used for nrhs right-hand sides."""
+    c = wl_launch()
+    _check(lib().wl_get_launch(op, nrhs, ctypes.byref(c)), "wl_get_launch")
+    return c.block, c.rhs_per_thread, c.xcd_remap, c.variant, c.rhs_lanes
 
 
-def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0):
-    return _check(lib().wl_set_launch(op, nrhs, block, rpt, xcd, variant), "wl_set_launch")
+def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1):
+    c = wl_launch(block=block, rhs_per_thread=rpt, rhs_lanes=lanes, xcd_remap=xcd, variant=variant)
+    return _check(lib().wl_set_launch(op, nrhs, ctypes.byref(c)), "wl_set_launch")
 
 
 # Stencil code variants per precision (see wl_set_launch in the header):
@@ -234,10 +281,11 @@ VARIANTS = {WL_F64: (0, 1, 4, 5, 6), WL_F32: (0, 1, 2, 4, 5, 6), WL_BF16S: (0, 1
 MAX_VARIANT = {k: max(v) for k, v in VARIANTS.items()}
 
 
-def try_set_launch(op, nrhs, block, rpt, xcd, variant=0):
+def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1):
     """wl_set_launch that returns False (instead of raising) for a configuration
-    the lattice does not admit (e.g. a t-walk column not dividing Lt)."""
-    return lib().wl_set_launch(op, nrhs, block, rpt, xcd, variant) == WL_OK
+    the library rejects."""
+    c = wl_launch(block=block, rhs_per_thread=rpt, rhs_lanes=lanes, xcd_remap=xcd, variant=variant)
+    return lib().wl_set_launch(op, nrhs, ctypes.byref(c)) == WL_OK
 MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
 
 

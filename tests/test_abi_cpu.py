@@ -79,19 +79,41 @@ def test_bad_arguments_rejected_before_launch():
         assert L.wilson_apply(op, 512, 1024, 2, 1, None) == wilson.WL_EINVAL  # dagger flag
         assert L.wilson_apply(op, 512, 1024, 0, 0, None) == wilson.WL_EINVAL  # nrhs
         assert L.wilson_apply(op, 520, 1024, 0, 1, None) == wilson.WL_EALIGN
-        assert L.wl_set_launch(op, 1, 96, 1, 1, 0) == wilson.WL_EINVAL
-        assert L.wl_set_launch(op, 4, 256, 3, 1, 0) == wilson.WL_EINVAL  # 3 does not divide 4
-        assert L.wl_set_launch(op, 4, 256, 4, 1, 0) == wilson.WL_EINVAL  # FP64 offers at most 2
-        assert L.wl_set_launch(op, 4, 256, 2, 0, 1) == wilson.WL_EINVAL  # pipelined variants need 1 RHS/thread
-        assert L.wl_set_launch(op, 1, 256, 1, 0, 2) == wilson.WL_EINVAL  # FP64 offers variants 0, 1
-        assert L.wl_set_launch(op, 1, 256, 1, 0, 1) == wilson.WL_OK
-        assert L.wl_set_launch(op, 4, 256, 2, 0, 0) == wilson.WL_OK
+        def setl(nrhs, block, rpt, xcd, var, lanes=1):
+            c = wilson.wl_launch(block=block, rhs_per_thread=rpt, rhs_lanes=lanes, xcd_remap=xcd, variant=var)
+            return L.wl_set_launch(op, nrhs, ctypes.byref(c))
+        assert setl(1, 96, 1, 1, 0) == wilson.WL_EINVAL
+        assert setl(4, 256, 3, 1, 0) == wilson.WL_EINVAL  # 3 does not divide 4
+        assert setl(4, 256, 4, 1, 0) == wilson.WL_EINVAL  # FP64 offers at most 2
+        assert setl(4, 256, 2, 0, 1) == wilson.WL_EINVAL  # pipelined variants need 1 RHS/thread
+        assert setl(1, 256, 1, 0, 2) == wilson.WL_EINVAL  # FP64 offers variants 0, 1
+        assert setl(4, 256, 1, 0, 1, lanes=3) == wilson.WL_EINVAL  # lanes: 1, 2, 4, 8
+        assert setl(2, 256, 1, 0, 1, lanes=4) == wilson.WL_EINVAL  # lanes must divide nrhs
+        assert setl(4, 256, 2, 0, 0, lanes=2) == wilson.WL_EINVAL  # lanes need 1 RHS/thread
+        assert setl(4, 128, 1, 0, 1, lanes=4) == wilson.WL_EINVAL  # at least 64 sites per workgroup
+        assert setl(1, 256, 1, 6, 1) == wilson.WL_EINVAL  # tile orders 0..5
+        assert setl(1, 256, 1, 2, 1) == wilson.WL_EINVAL  # no z-slabs for Lz = 4
+        assert setl(1, 256, 1, 0, 1) == wilson.WL_OK
+        assert setl(4, 256, 2, 0, 0) == wilson.WL_OK
+        assert setl(4, 256, 1, 1, 1, lanes=4) == wilson.WL_OK
+        got = wilson.wl_launch()
+        assert L.wl_get_launch(op, 4, ctypes.byref(got)) == wilson.WL_OK
+        assert (got.block, got.rhs_per_thread, got.rhs_lanes, got.xcd_remap, got.variant) == (256, 1, 4, 1, 1)
         prm = wilson.wl_solve_params(tol=0.0, maxiter=10)
         assert L.solve_cgnr(op, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
         prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
         assert L.solve_cgnr(op, op, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EPREC
         assert L.solve_cgnr(op, None, 512, 1024, 65, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
         assert L.wilson_gauge_force(op, 512, 1024, 2048, 3, None) == wilson.WL_EINVAL
+        plan = ctypes.c_void_p()
+        d = (wilson.wl_multi_desc * 2)(wilson.wl_multi_desc(op, 512, 1024), wilson.wl_multi_desc(op, 2048, 2048))
+        assert L.wl_multi_plan_create(d, 2, 0, 1, ctypes.byref(plan)) == wilson.WL_EINVAL  # out == in
+        assert L.wl_multi_plan_create(d, 0, 0, 1, ctypes.byref(plan)) == wilson.WL_EINVAL
+        assert L.wl_multi_plan_create(d, 1, 2, 1, ctypes.byref(plan)) == wilson.WL_EINVAL  # dagger flag
+        assert L.wl_multi_plan_create(d, 1, 0, 0, ctypes.byref(plan)) == wilson.WL_EINVAL  # nrhs
+        assert plan.value is None
+        assert L.wl_multi_plan_run(None, None) == wilson.WL_EINVAL
+        assert L.wl_multi_plan_destroy(None) == wilson.WL_EINVAL
     finally:
         L.wl_op_destroy(op)
     for c in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):

@@ -101,6 +101,23 @@ def test_multi_rhs_solve_matches_single(W, oracle_mod, method):
         assert rel(xs[k], x1) < 1e-8
 
 
+@pytest.mark.parametrize("method", ["cgnr", "bicgstab"])
+def test_multi_rhs_solve_ragged_tiles(W, oracle_mod, method):
+    """6 right-hand sides on 6x4x6x6 (tile counts not a multiple of 8, so the
+    multi-RHS stencil pads its grid; 2 right-hand sides across the lanes by
+    default, so the fused reductions are segmented) in FP64 and mixed FP32."""
+    dims = (6, 4, 6, 6)
+    kappa = 0.12
+    U = inputs.near_unity_gauge(dims, 0.3, seed=6)
+    bs = inputs.gaussian_spinor(dims, seed=8, nrhs=6)
+    for prec in ("f64", "mixed-f32"):
+        xs, st = W.solve(dev(U), dev(bs), kappa, method=method, precision=prec, tol=1e-10, return_stats=True)
+        xs = xs.cpu().numpy()
+        assert all(s["converged"] for s in st), (prec, st)
+        for k in range(6):
+            assert true_res(oracle_mod, U, xs[k], bs[k], kappa) <= 1.05e-10
+
+
 def test_free_point_source_propagator_batched(W):
     dims = (8, 8, 8, 16)
     kappa = 0.12

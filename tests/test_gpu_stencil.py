@@ -80,7 +80,7 @@ def test_apply_matches_oracle(W, oracle_mod, dims, kind, prec, dagger):
     p = W.PREC[prec]
     op = W.Operator.create(dev(U), kappa, p)
     for var in W.VARIANTS[p]:
-        for xcd in (0, 1, 2):
+        for xcd in (0, 1, 2, 3, 4, 5):
             if not W.try_set_launch(op.handle, 1, 64, 1, xcd, var):
                 continue  # e.g. a t-walk column length not dividing Lt, or no z-slabs
             out = W.apply(None, dev(psi), kappa, dagger=dagger, op=op).cpu().numpy()
@@ -115,9 +115,12 @@ def test_kappa_zero_identity_and_free_field(W):
     assert np.array_equal(out, psi)
 
 
+@pytest.mark.parametrize("dims", [(8, 4, 6, 8), (8, 4, 8, 8)])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_multi_rhs_columns_equal_single_rhs(W, prec):
-    dims = (8, 4, 6, 8)
+def test_multi_rhs_columns_equal_single_rhs(W, prec, dims):
+    """Every launch shape for 12 right-hand sides (tile counts that are and
+    are not multiples of 8, slab order where Lz allows it) gives the
+    single-RHS result bit for bit."""
     U = inputs.near_unity_gauge(dims, 0.3, seed=3)
     psi = inputs.gaussian_spinor(dims, seed=7, nrhs=12)
     p = W.PREC[prec]
@@ -127,15 +130,16 @@ def test_multi_rhs_columns_equal_single_rhs(W, prec):
     for rpt in (1, 2, 3, 4):
         if rpt > W.MAX_RPT[p]:
             continue
-        for block in (64, 256, 512):
-            for xcd in (0, 1, 2):
-                for var in (W.VARIANTS[p] if rpt == 1 else (0,)):
-                    if not W.try_set_launch(op.handle, 12, block, rpt, xcd, var):
-                        continue
-                    dst = op.new_field(12)
-                    op.apply_packed(dst, src, 12)
-                    outs.append(op.unpack(dst, 12).cpu().numpy())
-                    cfgs.append((block, rpt, xcd, var))
+        for lanes in ((1, 2, 4) if rpt == 1 else (1,)):
+            for block in (64, 256, 512):
+                for xcd in (0, 1, 2, 4, 5):
+                    for var in (W.VARIANTS[p] if rpt == 1 else (0,)):
+                        if not W.try_set_launch(op.handle, 12, block, rpt, xcd, var, lanes):
+                            continue
+                        dst = op.new_field(12)
+                        op.apply_packed(dst, src, 12)
+                        outs.append(op.unpack(dst, 12).cpu().numpy())
+                        cfgs.append((block, rpt, xcd, var, lanes))
     for o, cfg in zip(outs[1:], cfgs[1:]):
         if p in (W.WL_BF16S, W.WL_F16S) and cfg[3] >= 4:
             # t-walk applies a neighbour's 16-bit scale in a different place: equal to rounding
@@ -174,6 +178,56 @@ def test_gamma5_hermiticity_on_gpu(W):
     Ddx = W.apply(U, dev(x), 0.125, dagger=True).cpu().numpy()
     lhs, rhs = np.vdot(x, Dy), np.vdot(Ddx, y)
     assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+def test_multi_lattice_plan_every_shape(W):
+    """A plan run in every launch shape (and again after each run: the
+    queue counter resets itself) reproduces the separate launches."""
+    lattices = [(4, 4, 4, 4), (6, 4, 6, 2), (8, 8, 8, 8)]
+    for prec in ("f64", "f32", "bf16", "f16"):
+        p = W.PREC[prec]
+        ops, srcs, dsts, refs = [], [], [], []
+        for j, dims in enumerate(lattices):
+            op = W.Operator.create(dev(inputs.near_unity_gauge(dims, 0.3, seed=20 + j)), 0.12, p)
+            src = op.pack(dev(inputs.gaussian_spinor(dims, seed=200 + j, nrhs=4)))
+            ref = op.new_field(4)
+            op.apply_packed(ref, src, 4)
+            ops.append(op)
+            srcs.append(src)
+            dsts.append(op.new_field(4))
+            refs.append(op.unpack(ref, 4))
+        for dagger in (0, 1):
+            if dagger:
+                refs = []
+                for o, s_ in zip(ops, srcs):
+                    r = o.new_field(4)
+                    o.apply_packed(r, s_, 4, dagger=True)
+                    refs.append(o.unpack(r, 4))
+            plan = W.MultiPlan([(o.handle, d.data_ptr(), s_.data_ptr()) for o, d, s_ in zip(ops, dsts, srcs)],
+                               dagger, 4)
+            n = 0
+            for block in (64, 256):
+                for rpt in (1, 2, 4):
+                    for var in (0, 1, 2, 3):
+                        if not plan.set_launch(block, rpt, var):
+                            continue
+                        for rep in range(2):
+                            for d in dsts:
+                                d.zero_()
+                            plan.run()
+                            torch.cuda.synchronize()
+                            for o, d, r in zip(ops, dsts, refs):
+                                assert torch.equal(o.unpack(d, 4), r), (prec, dagger, block, rpt, var, rep)
+                        n += 1
+            assert n >= 6
+            plan.tune()
+            for d in dsts:
+                d.zero_()
+            plan.run()
+            torch.cuda.synchronize()
+            for o, d, r in zip(ops, dsts, refs):
+                assert torch.equal(o.unpack(d, 4), r), (prec, dagger, "tuned", plan.launch())
+            del plan
 
 
 def test_multi_lattice_launch_matches_separate(W):
