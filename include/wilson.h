@@ -197,19 +197,22 @@ typedef struct {
  * create: n in [1, 1024], nrhs in [1, 65535]; synchronous.
  * run: async on `stream`.
  * tune: times the launch shapes (sites per workgroup, RHS per thread, code
- *   variant) with HIP events, keeps the fastest (also in $WL_TUNE_CACHE);
- *   synchronous; leaves out_i = D_i in_i.
- * get_launch: current block size, RHS per thread, variant, resident grid.
+ *   variant, persistent or direct form) with HIP events, keeps the fastest
+ *   (also in $WL_TUNE_CACHE); synchronous; leaves out_i = D_i in_i.
+ * get_launch: current block size, RHS per thread, variant, form and grid.
  * set_launch: force a shape: block in {64,...,512} (multiple of 64); RHS per
  *   thread 1, 2 or 4 (WL_F64: 1, 2) dividing nrhs; variant 0 (any RHS per
  *   thread) or a pipelined variant 1..3 the precision offers (1 RHS per
- *   thread); synchronous, the plan must be idle. */
+ *   thread); persistent = 1: resident workgroups pop work items from the
+ *   queue, 0: one workgroup per work item (the same items and results);
+ *   synchronous, the plan must be idle. */
 typedef struct wl_multi_plan wl_multi_plan;
 int wl_multi_plan_create(const wl_multi_desc *d, int n, int dagger, int nrhs, wl_multi_plan **plan);
 int wl_multi_plan_run(wl_multi_plan *plan, void *stream);
 int wl_multi_plan_tune(wl_multi_plan *plan, void *stream);
-int wl_multi_plan_get_launch(const wl_multi_plan *plan, int *block, int *rhs_per_thread, int *variant, int *grid);
-int wl_multi_plan_set_launch(wl_multi_plan *plan, int block, int rhs_per_thread, int variant);
+int wl_multi_plan_get_launch(const wl_multi_plan *plan, int *block, int *rhs_per_thread, int *variant,
+                             int *persistent, int *grid);
+int wl_multi_plan_set_launch(wl_multi_plan *plan, int block, int rhs_per_thread, int variant, int persistent);
 int wl_multi_plan_destroy(wl_multi_plan *plan);
 
 /* One-shot form: create a plan, run it, wait for `stream`, destroy it. */

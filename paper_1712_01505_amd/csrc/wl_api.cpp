@@ -289,10 +289,12 @@ static StencilParams base_params(const wl_op *op, void *out, const void *in, int
 }
 
 // ---------------------------------------------------------------- multi-lattice plans
+// Plan shapes reuse LaunchCfg: block, rpt, var, and xcd = 1 for the
+// persistent work-queue form, 0 for one workgroup per work item.
 static LaunchCfg multi_default(int prec, int nrhs)
 {
     (void)nrhs;
-    return LaunchCfg{256, 1, 0, prec == WL_F64 ? 1 : 2, 1};
+    return LaunchCfg{256, 1, 1, prec == WL_F64 ? 1 : 2, 1};
 }
 
 static std::string multi_key(const wl_multi_plan *pl)
@@ -328,11 +330,14 @@ static int plan_build(wl_multi_plan *pl, const LaunchCfg &c)
             return WL_EINVAL;
     }
     CHECK_HIP(hipMemcpy(pl->dE, E.data(), sizeof(MultiEntry) * pl->n, hipMemcpyHostToDevice));
-    int grid = multi_grid_size(pl->prec, pl->dagger, c.rpt, c.block, c.var);
-    if (grid < 1)
-        return WL_EINVAL;
-    if ((uint64_t)grid > total)
-        grid = (int)total;
+    int grid = 0;  // direct form: one workgroup per item
+    if (c.xcd == 1) {  // persistent form: resident workgroups only
+        grid = multi_grid_size(pl->prec, pl->dagger, c.rpt, c.block, c.var);
+        if (grid < 1)
+            return WL_EINVAL;
+        if ((uint64_t)grid > total)
+            grid = (int)total;
+    }
     pl->cfg = c;
     pl->total = (uint32_t)total;
     pl->grid = grid;
@@ -615,34 +620,35 @@ int wl_multi_plan_tune(wl_multi_plan *pl, void *stream)
     float best_ms = INFINITY;
     const int blocks[] = {64, 128, 256, 512};
     int rc = WL_OK;
-    for (int bi = 0; bi < 4 && e == hipSuccess && rc == WL_OK; ++bi)
-        for (int rpt = 1; rpt <= 4 && e == hipSuccess && rc == WL_OK; ++rpt)
-            for (int var = 0; var <= 3 && e == hipSuccess && rc == WL_OK; ++var) {
-                if (pl->nrhs % rpt != 0 || !multi_launch_ok(pl->prec, rpt, blocks[bi], var))
-                    continue;
-                if ((rc = plan_build(pl, LaunchCfg{blocks[bi], rpt, 0, var, 1})) != WL_OK)
-                    break;
-                for (int w = 0; w < 2 && e == hipSuccess; ++w)
-                    e = launch_multi(pl->prec, pl->dagger, rpt, blocks[bi], var, pl->dE, pl->n, pl->total,
-                                     pl->counter, pl->grid, st);
-                const int reps = 10;
-                if (e == hipSuccess)
-                    e = hipEventRecord(a, st);
-                for (int k = 0; k < reps && e == hipSuccess; ++k)
-                    e = launch_multi(pl->prec, pl->dagger, rpt, blocks[bi], var, pl->dE, pl->n, pl->total,
-                                     pl->counter, pl->grid, st);
-                if (e == hipSuccess)
-                    e = hipEventRecord(b, st);
-                if (e == hipSuccess)
-                    e = hipEventSynchronize(b);
-                float ms = 0.f;
-                if (e == hipSuccess)
-                    e = hipEventElapsedTime(&ms, a, b);
-                if (e == hipSuccess && ms < best_ms) {
-                    best_ms = ms;
-                    best = pl->cfg;
+    for (int pers = 0; pers <= 1 && e == hipSuccess && rc == WL_OK; ++pers)
+        for (int bi = 0; bi < 4 && e == hipSuccess && rc == WL_OK; ++bi)
+            for (int rpt = 1; rpt <= 4 && e == hipSuccess && rc == WL_OK; ++rpt)
+                for (int var = 0; var <= 3 && e == hipSuccess && rc == WL_OK; ++var) {
+                    if (pl->nrhs % rpt != 0 || !multi_launch_ok(pl->prec, rpt, blocks[bi], var))
+                        continue;
+                    if ((rc = plan_build(pl, LaunchCfg{blocks[bi], rpt, pers, var, 1})) != WL_OK)
+                        break;
+                    for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                        e = launch_multi(pl->prec, pl->dagger, rpt, blocks[bi], var, pl->dE, pl->n, pl->total,
+                                         pl->counter, pl->grid, st);
+                    const int reps = 10;
+                    if (e == hipSuccess)
+                        e = hipEventRecord(a, st);
+                    for (int k = 0; k < reps && e == hipSuccess; ++k)
+                        e = launch_multi(pl->prec, pl->dagger, rpt, blocks[bi], var, pl->dE, pl->n, pl->total,
+                                         pl->counter, pl->grid, st);
+                    if (e == hipSuccess)
+                        e = hipEventRecord(b, st);
+                    if (e == hipSuccess)
+                        e = hipEventSynchronize(b);
+                    float ms = 0.f;
+                    if (e == hipSuccess)
+                        e = hipEventElapsedTime(&ms, a, b);
+                    if (e == hipSuccess && ms < best_ms) {
+                        best_ms = ms;
+                        best = pl->cfg;
+                    }
                 }
-            }
     if (a)
         (void)hipEventDestroy(a);
     if (b)
@@ -659,22 +665,24 @@ int wl_multi_plan_tune(wl_multi_plan *pl, void *stream)
     return WL_OK;
 }
 
-int wl_multi_plan_get_launch(const wl_multi_plan *pl, int *block, int *rpt, int *variant, int *grid)
+int wl_multi_plan_get_launch(const wl_multi_plan *pl, int *block, int *rpt, int *variant, int *persistent,
+                             int *grid)
 {
-    if (!pl || !block || !rpt || !variant || !grid)
+    if (!pl || !block || !rpt || !variant || !persistent || !grid)
         return WL_EINVAL;
     *block = pl->cfg.block;
     *rpt = pl->cfg.rpt;
     *variant = pl->cfg.var;
-    *grid = pl->grid;
+    *persistent = pl->cfg.xcd;
+    *grid = pl->grid > 0 ? pl->grid : (int)pl->total;
     return WL_OK;
 }
 
-int wl_multi_plan_set_launch(wl_multi_plan *pl, int block, int rpt, int variant)
+int wl_multi_plan_set_launch(wl_multi_plan *pl, int block, int rpt, int variant, int persistent)
 {
-    if (!pl)
+    if (!pl || (persistent != 0 && persistent != 1))
         return WL_EINVAL;
-    return plan_build(pl, LaunchCfg{block, rpt, 0, variant, 1});
+    return plan_build(pl, LaunchCfg{block, rpt, persistent, variant, 1});
 }
 
 int wl_multi_plan_destroy(wl_multi_plan *pl)

@@ -932,15 +932,66 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
 // the loop: the last one to leave resets both to zero, so the queue is ready
 // for the next launch without a host-side reset.  Every workgroup leaves the
 // loop once the head passes the total, so the grid always drains.
+// One work item: entry (lattice) found by binary search over tile_begin,
+// then site tile and RHS group (the group fastest) within it.
+template <int P, int DAG, int R, int VAR>
+__device__ __forceinline__ void multi_item(const MultiEntry *E, int n, uint32_t t)
+{
+    using T = typename Traits<P>::real;
+    int lo = 0, hi = n - 1;  // last entry with tile_begin <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (E[mid].tile_begin <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const StencilParams &p = E[lo].p;  // fields are read (scalar loads) where used
+    const uint32_t local = t - E[lo].tile_begin;
+    const uint32_t lt = fdiv(local, p.f_ng);
+    const int r0 = (int)(local - lt * p.ng) * R;
+    const uint32_t s = lt * blockDim.x + threadIdx.x;
+    if (s < p.V) {
+        cx<T> acc[R][12];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                acc[r][k] = cx<T>{T(0), T(0)};
+        if constexpr (VAR == 0 || R > 1)
+            hop_site<P, DAG, R>(p, s, r0, acc);
+        else
+            hop_site_pipe<P, DAG, VarG<P, VAR>::G>(p, s, r0, acc[0]);
+        const T kap = (T)p.kappa;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cx<T> in[12], o[12];
+            load_site<P>(p.in, p.V, p.nrhs, s, r0 + r, in);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
+            store_site_q<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
+        }
+    }
+}
+
+// Persistent form: a resident grid whose workgroups pop work items from a
+// device-wide counter until the queue is empty, so uneven lattices share one
+// launch.  counter[0] is the queue head, counter[1] counts workgroups that
+// have left the loop: the last one to leave resets both to zero, so the
+// queue is ready for the next launch without a host-side reset.  Every
+// workgroup leaves the loop once the head passes the total, so the grid
+// always drains.
 template <int P, int DAG, int R, int VAR>
 __global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, uint32_t total, unsigned *counter)
 {
-    using T = typename Traits<P>::real;
     __shared__ unsigned item_s;
     if (threadIdx.x == 0)
         item_s = atomicAdd(&counter[0], 1u);
     __syncthreads();
-    unsigned t = item_s;
+    // the item is uniform across the workgroup: keep it (and the entry
+    // lookup that follows from it) in scalar registers
+    unsigned t = __builtin_amdgcn_readfirstlane(item_s);
     for (;;) {
         __syncthreads();  // everyone has read item_s
         if (t >= total)
@@ -948,43 +999,9 @@ __global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, 
         // pop the next item now, so the atomic's latency overlaps this one
         if (threadIdx.x == 0)
             item_s = atomicAdd(&counter[0], 1u);
-        int lo = 0, hi = n - 1;  // last entry with tile_begin <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (E[mid].tile_begin <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const StencilParams p = E[lo].p;
-        const uint32_t local = t - E[lo].tile_begin;
-        const uint32_t lt = fdiv(local, p.f_ng);
-        const int r0 = (int)(local - lt * p.ng) * R;
-        const uint32_t s = lt * blockDim.x + threadIdx.x;
-        if (s < p.V) {
-            cx<T> acc[R][12];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int k = 0; k < 12; ++k)
-                    acc[r][k] = cx<T>{T(0), T(0)};
-            if constexpr (VAR == 0 || R > 1)
-                hop_site<P, DAG, R>(p, s, r0, acc);
-            else
-                hop_site_pipe<P, DAG, VarG<P, VAR>::G>(p, s, r0, acc[0]);
-            const T kap = (T)p.kappa;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                cx<T> in[12], o[12];
-                load_site<P>(p.in, p.V, p.nrhs, s, r0 + r, in);
-#pragma unroll
-                for (int k = 0; k < 12; ++k)
-                    o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
-                store_site_q<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
-            }
-        }
+        multi_item<P, DAG, R, VAR>(E, n, t);
         __syncthreads();  // item_s written
-        t = item_s;
+        t = __builtin_amdgcn_readfirstlane(item_s);
     }
     if (threadIdx.x == 0) {
         __threadfence();  // this workgroup's last pop precedes its exit count
@@ -993,6 +1010,16 @@ __global__ __launch_bounds__(512) void multi_kernel(const MultiEntry *E, int n, 
             atomicExch(&counter[1], 0u);
         }
     }
+}
+
+// Direct form: one workgroup per work item (the hardware dispatcher is the
+// queue); same items, same results.
+template <int P, int DAG, int R, int VAR>
+__global__ __launch_bounds__(512) void multi_direct_kernel(const MultiEntry *E, int n, uint32_t total)
+{
+    const uint32_t t = blockIdx.x;
+    if (t < total)
+        multi_item<P, DAG, R, VAR>(E, n, t);
 }
 
 // Multi-lattice launch shapes: R in {1, 2, 4} (FP64: 1, 2); R = 1 takes the
@@ -1009,47 +1036,48 @@ static bool multi_shape_ok(int prec, int rpt, int var)
 }
 
 template <int P, int DAG, int R, int VAR>
-static const void *multi_fn()
+static const void *multi_fn(bool persistent)
 {
-    return reinterpret_cast<const void *>(&multi_kernel<P, DAG, R, VAR>);
+    return persistent ? reinterpret_cast<const void *>(&multi_kernel<P, DAG, R, VAR>)
+                      : reinterpret_cast<const void *>(&multi_direct_kernel<P, DAG, R, VAR>);
 }
 
 template <int P, int DAG>
-static const void *multi_pick(int rpt, int var)
+static const void *multi_pick(int rpt, int var, bool persistent)
 {
     if (rpt == 2)
-        return multi_fn<P, DAG, 2, 0>();
+        return multi_fn<P, DAG, 2, 0>(persistent);
     if constexpr (P != F64)
         if (rpt == 4)
-            return multi_fn<P, DAG, 4, 0>();
+            return multi_fn<P, DAG, 4, 0>(persistent);
     switch (var) {
-    case 0: return multi_fn<P, DAG, 1, 0>();
-    case 1: return multi_fn<P, DAG, 1, 1>();
+    case 0: return multi_fn<P, DAG, 1, 0>(persistent);
+    case 1: return multi_fn<P, DAG, 1, 1>(persistent);
     case 2:
         if constexpr (P != F64)
-            return multi_fn<P, DAG, 1, 2>();
+            return multi_fn<P, DAG, 1, 2>(persistent);
         return nullptr;
     case 3:
         if constexpr (P == BF16S || P == F16S)
-            return multi_fn<P, DAG, 1, 3>();
+            return multi_fn<P, DAG, 1, 3>(persistent);
         return nullptr;
     default: return nullptr;
     }
 }
 
-static const void *multi_kernel_ptr(int prec, int dagger, int rpt, int var)
+static const void *multi_kernel_ptr(int prec, int dagger, int rpt, int var, bool persistent)
 {
     if (!multi_shape_ok(prec, rpt, var))
         return nullptr;
     switch (prec * 2 + (dagger ? 1 : 0)) {
-    case 0: return multi_pick<F64, 0>(rpt, var);
-    case 1: return multi_pick<F64, 1>(rpt, var);
-    case 2: return multi_pick<F32, 0>(rpt, var);
-    case 3: return multi_pick<F32, 1>(rpt, var);
-    case 4: return multi_pick<BF16S, 0>(rpt, var);
-    case 5: return multi_pick<BF16S, 1>(rpt, var);
-    case 6: return multi_pick<F16S, 0>(rpt, var);
-    case 7: return multi_pick<F16S, 1>(rpt, var);
+    case 0: return multi_pick<F64, 0>(rpt, var, persistent);
+    case 1: return multi_pick<F64, 1>(rpt, var, persistent);
+    case 2: return multi_pick<F32, 0>(rpt, var, persistent);
+    case 3: return multi_pick<F32, 1>(rpt, var, persistent);
+    case 4: return multi_pick<BF16S, 0>(rpt, var, persistent);
+    case 5: return multi_pick<BF16S, 1>(rpt, var, persistent);
+    case 6: return multi_pick<F16S, 0>(rpt, var, persistent);
+    case 7: return multi_pick<F16S, 1>(rpt, var, persistent);
     default: return nullptr;
     }
 }
@@ -1062,7 +1090,7 @@ bool multi_launch_ok(int prec, int rpt, int block, int var)
 // Resident workgroups for a full machine: occupancy per CU x CUs.
 int multi_grid_size(int prec, int dagger, int rpt, int block, int var)
 {
-    const void *fn = multi_kernel_ptr(prec, dagger, rpt, var);
+    const void *fn = multi_kernel_ptr(prec, dagger, rpt, var, true);
     if (!fn)
         return 0;
     int per_cu = 0;
@@ -1077,11 +1105,18 @@ int multi_grid_size(int prec, int dagger, int rpt, int block, int var)
 hipError_t launch_multi(int prec, int dagger, int rpt, int block, int var, const MultiEntry *E, int n,
                         uint32_t total, unsigned *counter, int grid, hipStream_t st)
 {
-    const void *fn = multi_kernel_ptr(prec, dagger, rpt, var);
-    if (!fn || grid < 1)
+    // grid > 0: persistent form with that many workgroups; grid == 0: one
+    // workgroup per item
+    const bool persistent = grid > 0;
+    const void *fn = multi_kernel_ptr(prec, dagger, rpt, var, persistent);
+    if (!fn || total == 0)
         return hipErrorInvalidValue;
-    void *args[] = {(void *)&E, (void *)&n, (void *)&total, (void *)&counter};
-    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
+    if (persistent) {
+        void *args[] = {(void *)&E, (void *)&n, (void *)&total, (void *)&counter};
+        return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
+    }
+    void *args[] = {(void *)&E, (void *)&n, (void *)&total};
+    return hipLaunchKernel(fn, dim3(total), dim3(block), args, 0, st);
 }
 
 // ---------------------------------------------------------------- link force

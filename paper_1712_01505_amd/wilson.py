@@ -119,8 +119,9 @@ def lib():
         "wl_multi_plan_create": [ctypes.POINTER(wl_multi_desc), I, I, I, ctypes.POINTER(P)],
         "wl_multi_plan_run": [P, P],
         "wl_multi_plan_tune": [P, P],
-        "wl_multi_plan_get_launch": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
-        "wl_multi_plan_set_launch": [P, I, I, I],
+        "wl_multi_plan_get_launch": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                                     ctypes.POINTER(I)],
+        "wl_multi_plan_set_launch": [P, I, I, I, I],
         "wl_multi_plan_destroy": [P],
     }
     for name, args in sig.items():
@@ -243,14 +244,14 @@ class MultiPlan:
         _check(lib().wl_multi_plan_tune(self.handle, _stream() if stream is None else stream), "wl_multi_plan_tune")
 
     def launch(self):
-        b, r, v, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib().wl_multi_plan_get_launch(self.handle, ctypes.byref(b), ctypes.byref(r), ctypes.byref(v),
-                                              ctypes.byref(g)), "wl_multi_plan_get_launch")
-        return b.value, r.value, v.value, g.value
+        """(block, rhs_per_thread, variant, persistent, grid)."""
+        v = [ctypes.c_int() for _ in range(5)]
+        _check(lib().wl_multi_plan_get_launch(self.handle, *[ctypes.byref(x) for x in v]), "wl_multi_plan_get_launch")
+        return tuple(x.value for x in v)
 
-    def set_launch(self, block, rpt, variant):
+    def set_launch(self, block, rpt, variant, persistent=1):
         """Force a launch shape; returns False if the library rejects it."""
-        return lib().wl_multi_plan_set_launch(self.handle, block, rpt, variant) == WL_OK
+        return lib().wl_multi_plan_set_launch(self.handle, block, rpt, variant, int(persistent)) == WL_OK
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

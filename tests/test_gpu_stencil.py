@@ -206,20 +206,21 @@ def test_multi_lattice_plan_every_shape(W):
             plan = W.MultiPlan([(o.handle, d.data_ptr(), s_.data_ptr()) for o, d, s_ in zip(ops, dsts, srcs)],
                                dagger, 4)
             n = 0
-            for block in (64, 256):
-                for rpt in (1, 2, 4):
-                    for var in (0, 1, 2, 3):
-                        if not plan.set_launch(block, rpt, var):
-                            continue
-                        for rep in range(2):
-                            for d in dsts:
-                                d.zero_()
-                            plan.run()
-                            torch.cuda.synchronize()
-                            for o, d, r in zip(ops, dsts, refs):
-                                assert torch.equal(o.unpack(d, 4), r), (prec, dagger, block, rpt, var, rep)
-                        n += 1
-            assert n >= 6
+            for pers in (1, 0):
+                for block in (64, 256):
+                    for rpt in (1, 2, 4):
+                        for var in (0, 1, 2, 3):
+                            if not plan.set_launch(block, rpt, var, pers):
+                                continue
+                            for rep in range(2):
+                                for d in dsts:
+                                    d.zero_()
+                                plan.run()
+                                torch.cuda.synchronize()
+                                for o, d, r in zip(ops, dsts, refs):
+                                    assert torch.equal(o.unpack(d, 4), r), (prec, dagger, pers, block, rpt, var, rep)
+                            n += 1
+            assert n >= 12
             plan.tune()
             for d in dsts:
                 d.zero_()
