@@ -55,12 +55,18 @@ def measured_traffic(prec, dims):
         return None
     tot, n = 0.0, 0
     for k, v in d["kernels"].items():
-        if not k.startswith("wl::stencil_kernel<"):
+        # the solver's stencils of this precision: stencil_kernel<prec, dagger,
+        # rhs/thread, reduction, apply, variant> or twalk_kernel<prec, dagger,
+        # reduction, apply>, with a fused reduction (the profiled run does not
+        # autotune, so these are the timed solve's launches)
+        if k.startswith("wl::stencil_kernel<"):
+            red_at = 3
+        elif k.startswith("wl::twalk_kernel<"):
+            red_at = 2
+        else:
             continue
         targs = [int(a) for a in k[k.index("<") + 1:k.index(">")].split(",")]
-        # <prec, dagger, rhs/thread, reduction, apply, variant>: the solver's
-        # stencils carry a fused reduction (the autotuner's candidates do not)
-        if targs[0] == prec and targs[3] != 0:
+        if targs[0] == prec and targs[red_at] != 0:
             tot += v["hbm_bytes"] * v["dispatches"]
             n += v["dispatches"]
     return round(tot / n) if n else None
@@ -195,6 +201,8 @@ def main():
     ap.add_argument("--inner", type=str, default="f16", choices=["f32", "bf16", "f16"])
     ap.add_argument("--reliable", type=int, default=0, choices=[0, 1],
                     help="timed solve: 1 = reliable updates, 0 = defect correction")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (launch shapes then come from $WL_TUNE_CACHE or the defaults)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and check")
     ap.add_argument("--no-extra", action="store_true", help="skip the measurements outside the timed region")
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-RHS / multi-lattice / autograd extras")
@@ -245,7 +253,8 @@ def main():
     inner = {"f32": W.WL_F32, "bf16": W.WL_BF16S, "f16": W.WL_F16S}[args.inner]
     tuned = {}
     for p, op in ops.items():
-        W.wl_autotune(op.handle, 1, 0, stream)
+        if not args.no_tune:
+            W.wl_autotune(op.handle, 1, 0, stream)
         tuned[PNAME[p]] = W.wl_get_launch(op.handle, 1)
     log(f"[bench] autotuned launch (block, rhs/thread, xcd, variant): {tuned}")
 
@@ -282,7 +291,9 @@ def main():
     avg_ms = ms_l / max(n_l, 1)
     bytes_per_launch = BYTES[dom] * V
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"stencil_kernel<{PNAME[dom]}> (wilson_apply)", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm",
+                "kernel": f"wilson stencil <{PNAME[dom]}> in the solve (stencil_kernel/twalk_kernel, fused reductions)",
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, dims),
                 "bytes_per_site": BYTES[dom], "sites_per_launch": V, "avg_launch_us": round(avg_ms * 1e3, 2),
