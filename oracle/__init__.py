@@ -9,7 +9,9 @@ the few steps written here in numpy are the plain definitions.
 Paper: Kanamori & Matsufuru, arXiv:1712.01505.
   Sec. II-A   field content (4 spin x 3 colour per site, SU(3) links)
   Sec. II-B   eq. (1), the Wilson fermion matrix
+  Sec. II-B   eq. (2), the domain-wall fermion matrix (5-d fields, shape (Ns, Lt, Lz, Ly, Lx, 4, 3))
   Sec. II-C   BiCGStab for the Wilson matrix, CG on the normal equations
+  Sec. V-C    CG on D^dag D for the domain-wall matrix
 
 Array conventions (numpy, complex128, canonical):
   spinor  shape (Lt, Lz, Ly, Lx, 4, 3)
@@ -55,6 +57,10 @@ def _configure(lib):
                                     ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double)]
     lib.oracle_bicgstab.restype = ctypes.c_int
     lib.oracle_force.argtypes = [ip, ip, ctypes.c_double, P, P, P]
+    lib.oracle_dw_apply.argtypes = [ip, ip, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_int]
+    lib.oracle_dw_cgnr.argtypes = [ip, ip, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_double,
+                                   ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_dw_cgnr.restype = ctypes.c_int
     return lib
 
 
@@ -181,3 +187,28 @@ def gradient(U, b, kappa, bc=DEFAULT_BC, tol=1e-13, maxiter=20000):
     G = force(U, x, mu, kappa, bc=bc)
     P = su3_project(U, G)
     return dict(x=x, L=float(np.vdot(x, x).real), grad_b=mu, G=G, P=P, grad_U_tangent=1j * np.matmul(P, U))
+
+
+def dw_apply(U, psi, m0, m, bc=DEFAULT_BC, dagger=False):
+    """D_DW psi (eq. (2)) for a 5-d field psi of shape (Ns, Lt, Lz, Ly, Lx, 4, 3):
+    D_W + 1 on the diagonal in s (D_W = (m0 + 4) - H/2), -P_- above, -P_+ below,
+    m P_+ / m P_- in the corners; P_pm = (1 pm gamma_5)/2.  dagger: D_DW^dag."""
+    U = _c128(U)
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    _load().oracle_dw_apply(_ivec(_dims_of_spinor(psi[0])), _ivec(bc), int(psi.shape[0]), float(m0), float(m),
+                            U.ctypes.data, psi.ctypes.data, out.ctypes.data, int(bool(dagger)))
+    return out
+
+
+def dw_cgnr(U, b, m0, m, bc=DEFAULT_BC, tol=1e-12, maxiter=20000, x0=None):
+    """CG on D_DW^dag D_DW x = D_DW^dag b; returns (x, status, iters, true_relres)."""
+    U = _c128(U)
+    b = _c128(b)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    st = _load().oracle_dw_cgnr(_ivec(_dims_of_spinor(b[0])), _ivec(bc), int(b.shape[0]), float(m0), float(m),
+                                U.ctypes.data, b.ctypes.data, x.ctypes.data, float(tol), int(maxiter),
+                                ctypes.byref(it), ctypes.byref(rel))
+    return x, st, it.value, rel.value

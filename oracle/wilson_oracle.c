@@ -363,3 +363,132 @@ void oracle_force(const int *L, const int *bc, double kappa, const cplx *x, cons
         }
     }
 }
+
+/* ---- Domain-wall operator (Sec. II-B, eq. (2)) ------------------------------
+ * A 5-d field is Ns four-dimensional spinor fields one after the other,
+ * psi[s][t][z][y][x][spin][colour], s = 0..Ns-1.  The matrix is block
+ * tridiagonal in s:
+ *   block (s, s)       D_W + 1,  with D_W = (m0 + 4) - 1/2 H   (eq. (1))
+ *   block (s, s+1)     -P_-          block (s, s-1)     -P_+
+ *   block (0, Ns-1)    m P_+         block (Ns-1, 0)    m P_-
+ * with the chiral projectors P_pm = (1 pm gamma_5)/2 (the paper does not spell
+ * them out; this is their standard meaning).  The links are the same for every
+ * s.  The conjugate transpose has D_W^dag + 1 on the diagonal, -P_+ in block
+ * (s, s+1), -P_- in block (s, s-1), m P_- in block (0, Ns-1) and m P_+ in
+ * block (Ns-1, 0). */
+
+/* gamma_5 as the product gamma_x gamma_y gamma_z gamma_t, by plain 4x4 products. */
+static void gamma5_matrix(cplx g5[4][4])
+{
+    cplx a[4][4], b[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            a[i][j] = GAMMA[0][i][j];
+    for (int mu = 1; mu < 4; ++mu) {
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                cplx acc = 0;
+                for (int k = 0; k < 4; ++k)
+                    acc += a[i][k] * GAMMA[mu][k][j];
+                b[i][j] = acc;
+            }
+        memcpy(a, b, sizeof a);
+    }
+    memcpy(g5, a, sizeof a);
+}
+
+/* out12 += coef * P_pm in12, P_pm = (1 pm gamma_5) / 2 (pm = +1 or -1). */
+static void add_chiral(cplx *out12, const cplx *in12, const cplx g5[4][4], double pm, cplx coef)
+{
+    for (int s = 0; s < 4; ++s)
+        for (int a = 0; a < 3; ++a) {
+            cplx acc = 0.5 * in12[3 * s + a];
+            for (int r = 0; r < 4; ++r)
+                acc += 0.5 * pm * g5[s][r] * in12[3 * r + a];
+            out12[3 * s + a] += coef * acc;
+        }
+}
+
+/* out = D_DW psi (dagger = 0) or D_DW^dag psi (dagger = 1). */
+void oracle_dw_apply(const int *L, const int *bc, int Ns, double m0, double m, const cplx *U, const cplx *psi,
+                     cplx *out, int dagger)
+{
+    const long V = volume(L), n4 = 12 * V;
+    cplx g5[4][4];
+    gamma5_matrix(g5);
+    /* the projector in block (s, s+1) and in block (s, s-1) */
+    const double up = dagger ? +1.0 : -1.0, down = -up;
+    for (int s = 0; s < Ns; ++s) {
+        const cplx *ps = psi + s * n4;
+        cplx *os = out + s * n4;
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < V; ++x) {
+            cplx h[12];
+            hop_site(L, bc, U, ps, x, dagger, h);
+            for (int i = 0; i < 12; ++i)
+                os[12 * x + i] = (m0 + 5.0) * ps[12 * x + i] - 0.5 * h[i];
+            /* block (s, s+1): -P_up psi_{s+1}; for s = Ns-1 the corner m P_up psi_0 */
+            if (s + 1 < Ns)
+                add_chiral(os + 12 * x, psi + (s + 1) * n4 + 12 * x, g5, up, -1.0);
+            else
+                add_chiral(os + 12 * x, psi + 12 * x, g5, up, m);
+            /* block (s, s-1): -P_down psi_{s-1}; for s = 0 the corner m P_down psi_{Ns-1} */
+            if (s > 0)
+                add_chiral(os + 12 * x, psi + (s - 1) * n4 + 12 * x, g5, down, -1.0);
+            else
+                add_chiral(os + 12 * x, psi + (Ns - 1) * n4 + 12 * x, g5, down, m);
+        }
+    }
+}
+
+/* CG on the normal equations of the domain-wall matrix, D^dag D x = D^dag b
+ * (Sec. V-C: the paper applies CG to D^dag D for this operator), following
+ * the same textbook steps as oracle_cgnr (Saad, Alg. 8.4).  x holds the
+ * initial guess.  Returns 0 if the true relative residual ||b - D x|| / ||b||
+ * is <= tol, 1 otherwise. */
+int oracle_dw_cgnr(const int *L, const int *bc, int Ns, double m0, double m, const cplx *U, const cplx *b, cplx *x,
+                   double tol, int maxiter, int *iters, double *true_relres)
+{
+    const long n = 12 * volume(L) * Ns;
+    cplx *r = malloc(n * sizeof(cplx)), *z = malloc(n * sizeof(cplx));
+    cplx *p = malloc(n * sizeof(cplx)), *w = malloc(n * sizeof(cplx));
+    const double bnorm = sqrt(vnorm2(n, b));
+    int k = 0;
+    oracle_dw_apply(L, bc, Ns, m0, m, U, x, w, 0);
+    for (long i = 0; i < n; ++i)
+        r[i] = b[i] - w[i];
+    oracle_dw_apply(L, bc, Ns, m0, m, U, r, z, 1);
+    memcpy(p, z, n * sizeof(cplx));
+    double zz = vnorm2(n, z);
+    double rr = vnorm2(n, r);
+    while (k < maxiter && sqrt(rr) > tol * bnorm) {
+        oracle_dw_apply(L, bc, Ns, m0, m, U, p, w, 0);
+        double ww = vnorm2(n, w);
+        if (ww == 0.0)
+            break;
+        double alpha = zz / ww;
+        for (long i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * w[i];
+        }
+        rr = vnorm2(n, r);
+        oracle_dw_apply(L, bc, Ns, m0, m, U, r, z, 1);
+        double zz_new = vnorm2(n, z);
+        double beta = zz_new / zz;
+        zz = zz_new;
+        for (long i = 0; i < n; ++i)
+            p[i] = z[i] + beta * p[i];
+        ++k;
+    }
+    oracle_dw_apply(L, bc, Ns, m0, m, U, x, w, 0);
+    for (long i = 0; i < n; ++i)
+        r[i] = b[i] - w[i];
+    double rel = bnorm > 0 ? sqrt(vnorm2(n, r)) / bnorm : 0.0;
+    *iters = k;
+    *true_relres = rel;
+    free(r);
+    free(z);
+    free(p);
+    free(w);
+    return rel <= tol ? 0 : 1;
+}

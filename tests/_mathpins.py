@@ -133,3 +133,49 @@ def gauge_transform_links(U, Om, dims):
         Om_fwd = np.roll(Om, -1, axis=axis)
         out[mu] = Om @ U[mu] @ np.conj(np.swapaxes(Om_fwd, -1, -2))
     return out
+
+
+# ---------------------------------------------------------------- domain wall
+# D_DW (paper Sec. II-B, eq. (2)) written as Kronecker products over the fifth
+# index: I_s (x) (D_W + 1) - U_s (x) P_- - L_s (x) P_+ + m E_{0,Ns-1} (x) P_+
+# + m E_{Ns-1,0} (x) P_-, with U_s / L_s the ones just above / below the
+# diagonal, D_W = (m0 + 4) - H/2 and P_pm = (1 pm gamma_5)/2 acting on spin.
+
+P_PLUS = 0.5 * (np.eye(4) + GAMMA5)
+P_MINUS = 0.5 * (np.eye(4) - GAMMA5)
+
+
+def dense_dw(U, m0, m, Ns, dims, bc=(1, 1, 1, -1), dagger=False):
+    """Dense D_DW (or its conjugate transpose), index order s*12V + site*12 + spin*3 + colour."""
+    V = _vol(dims)
+    H = np.eye(12 * V) - dense_wilson(U, 1.0, dims, bc)  # D(kappa=1) = 1 - H
+    DW = (m0 + 4.0) * np.eye(12 * V) - 0.5 * H
+    site_p = lambda P: np.kron(np.eye(V), np.kron(P, np.eye(3)))
+    Pp, Pm = site_p(P_PLUS), site_p(P_MINUS)
+    up = np.eye(Ns, k=1)
+    down = np.eye(Ns, k=-1)
+    corner_top = np.zeros((Ns, Ns))
+    corner_top[0, Ns - 1] = 1.0
+    corner_bot = np.zeros((Ns, Ns))
+    corner_bot[Ns - 1, 0] = 1.0
+    D = (np.kron(np.eye(Ns), DW + np.eye(12 * V)) - np.kron(up, Pm) - np.kron(down, Pp)
+         + m * np.kron(corner_top, Pp) + m * np.kron(corner_bot, Pm))
+    return D.conj().T if dagger else D
+
+
+def dw_symbol(p, m0, m, Ns):
+    """Free-field D_DW on e^{ipx} v (v: Ns x 4 spin vectors), a (4 Ns x 4 Ns) matrix:
+    D_W(p) = (m0 + 4) - sum cos p_mu + i sum gamma_mu sin p_mu in the diagonal blocks."""
+    DWp = (m0 + 4.0 - np.sum(np.cos(p))) * np.eye(4, dtype=np.complex128)
+    for mu in range(4):
+        DWp = DWp + 1j * np.sin(p[mu]) * GAMMAS[mu]
+    M = np.zeros((4 * Ns, 4 * Ns), dtype=np.complex128)
+    for s in range(Ns):
+        M[4 * s:4 * s + 4, 4 * s:4 * s + 4] = DWp + np.eye(4)
+        if s + 1 < Ns:
+            M[4 * s:4 * s + 4, 4 * (s + 1):4 * (s + 2)] = -P_MINUS
+        if s > 0:
+            M[4 * s:4 * s + 4, 4 * (s - 1):4 * s] = -P_PLUS
+    M[0:4, 4 * (Ns - 1):4 * Ns] += m * P_PLUS
+    M[4 * (Ns - 1):4 * Ns, 0:4] += m * P_MINUS
+    return M

@@ -319,6 +319,11 @@ _MUTATIONS = {
     "link_transposed": ("cplx m = adj ? conj(link[3 * b + a]) : link[3 * a + b];",
                         "cplx m = adj ? conj(link[3 * a + b]) : link[3 * b + a];"),
     "force_second_term_dropped": ("acc += mu_adj[12 * nf + 3 * sp + a] * conj(w[sp][b]);", ""),
+    "dw_projectors_swapped": ("const double up = dagger ? +1.0 : -1.0, down = -up;",
+                              "const double up = dagger ? -1.0 : +1.0, down = -up;"),
+    "dw_diagonal_shift": ("(m0 + 5.0) * ps[12 * x + i]", "(m0 + 4.0) * ps[12 * x + i]"),
+    "dw_corner_sign": ("add_chiral(os + 12 * x, psi + 12 * x, g5, up, m);",
+                       "add_chiral(os + 12 * x, psi + 12 * x, g5, up, -m);"),
 }
 
 
@@ -379,3 +384,87 @@ def test_planted_force_mistake_caught_by_fd(planted):
         fd = (np.vdot(muv, o.apply(Up, x, 0.125)).real - np.vdot(muv, o.apply(Um, x, 0.125)).real) / (2 * h)
         worst = max(worst, abs(fd + np.real(np.trace(lam[a] @ P[1, 2, 0, 0, 0]))))
     assert worst > 1e-3
+
+
+# ---------------------------------------------------------------- domain wall (eq. (2))
+DW_M0, DW_M = -1.8, 0.05
+
+
+def _dw_field(dims, Ns, seed):
+    return np.stack([inputs.gaussian_spinor(dims, seed=seed + s) for s in range(Ns)])
+
+
+@pytest.mark.parametrize("dims,Ns", [((2, 2, 2, 2), 4), ((2, 2, 2, 4), 3), ((3, 2, 2, 2), 2)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dw_matches_kronecker_construction(oracle_mod, dims, Ns, dagger):
+    U = inputs.haar_gauge(dims, seed=7)
+    psi = _dw_field(dims, Ns, 40)
+    ref = (mp.dense_dw(U, DW_M0, DW_M, Ns, dims, BC, dagger=dagger) @ psi.ravel()).reshape(psi.shape)
+    assert rel(oracle_mod.dw_apply(U, psi, DW_M0, DW_M, BC, dagger=dagger), ref) < 1e-13
+
+
+def test_dw_free_field_plane_waves(oracle_mod):
+    """U = 1: a plane wave e^{ipx} times spin vectors v_s is mapped to e^{ipx} (M(p) v)_s."""
+    dims, Ns = (4, 4, 4, 4), 5
+    rng = np.random.default_rng(2)
+    moms = mp.momenta(dims, BC)
+    Lx, Ly, Lz, Lt = dims
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    for trial in range(3):
+        p = np.array([moms[mu][rng.integers(0, dims[mu])] for mu in range(4)])
+        wave = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+        v = rng.normal(size=(Ns, 4)) + 1j * rng.normal(size=(Ns, 4))
+        col = rng.normal(size=3) + 1j * rng.normal(size=3)
+        psi = wave[None, ..., None, None] * v[:, None, None, None, None, :, None] * col
+        out = oracle_mod.dw_apply(inputs.unit_gauge(dims), psi, DW_M0, DW_M, BC)
+        w = (mp.dw_symbol(p, DW_M0, DW_M, Ns) @ v.ravel()).reshape(Ns, 4)
+        ref = wave[None, ..., None, None] * w[:, None, None, None, None, :, None] * col
+        assert rel(out, ref) < 1e-12
+
+
+def test_dw_gamma5_reflection_hermiticity(oracle_mod):
+    """D_DW^dag = Gamma D_DW Gamma with Gamma = gamma_5 R_5 (R_5: s -> Ns-1-s), and <x, D y> = <D^dag x, y>."""
+    dims, Ns = (4, 2, 2, 4), 6
+    U = inputs.haar_gauge(dims, seed=11)
+    x = _dw_field(dims, Ns, 60)
+    y = _dw_field(dims, Ns, 70)
+    gam = lambda f: mp.gamma5_spinor(f[::-1])
+    lhs = oracle_mod.dw_apply(U, x, DW_M0, DW_M, BC, dagger=True)
+    assert rel(lhs, gam(oracle_mod.dw_apply(U, gam(x), DW_M0, DW_M, BC))) < 1e-13
+    a = np.vdot(x, oracle_mod.dw_apply(U, y, DW_M0, DW_M, BC))
+    b = np.vdot(lhs, y)
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+def test_dw_cgnr_matches_dense_solve(oracle_mod):
+    dims, Ns = (2, 2, 2, 4), 4
+    U = inputs.haar_gauge(dims, seed=13)
+    b = _dw_field(dims, Ns, 80)
+    x, st, it, relres = oracle_mod.dw_cgnr(U, b, DW_M0, DW_M, BC, tol=1e-12)
+    assert st == 0 and relres <= 1e-12 and it > 0
+    D = mp.dense_dw(U, DW_M0, DW_M, Ns, dims, BC)
+    x_lu = np.linalg.solve(D, b.ravel()).reshape(b.shape)
+    assert rel(x, x_lu) < 1e-9
+
+
+def test_dw_ns1_reduces_to_shifted_wilson(oracle_mod):
+    """Ns = 1: both corners land on the diagonal, D_DW = D_W + 1 + m (P_+ + P_-) = D_W + 1 + m."""
+    dims = (2, 2, 2, 4)
+    U = inputs.haar_gauge(dims, seed=17)
+    psi = _dw_field(dims, 1, 90)
+    kappa = 1.0 / (2 * (DW_M0 + 1 + DW_M) + 8)  # D_W + 1 + m = (m0 + 1 + m + 4) - H/2 = D(kappa) / (2 kappa)
+    ref = oracle_mod.apply(U, psi[0], kappa, BC) / (2 * kappa)
+    assert rel(oracle_mod.dw_apply(U, psi, DW_M0, DW_M, BC)[0], ref) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["dw_projectors_swapped", "dw_diagonal_shift", "dw_corner_sign"])
+def test_planted_dw_mistakes_are_caught(planted, name):
+    o = planted(name)
+    dims, Ns = (2, 2, 2, 2), 3
+    U = inputs.haar_gauge(dims, seed=19)
+    psi = _dw_field(dims, Ns, 95)
+    bad = False
+    for dagger in (False, True):
+        ref = (mp.dense_dw(U, DW_M0, DW_M, Ns, dims, BC, dagger=dagger) @ psi.ravel()).reshape(psi.shape)
+        bad = bad or rel(o.dw_apply(U, psi, DW_M0, DW_M, BC, dagger=dagger), ref) > 1e-6
+    assert bad
