@@ -121,6 +121,31 @@ int wilson_dslash(const wl_op *op, void *out, const void *in, int dagger, int nr
  * (paper Table I).  Same buffer rules as wilson_dslash.  Async. */
 int wilson_apply(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream);
 
+/* ---- Domain-wall operator (Sec. II-B, eq. (2)) ----
+ * D_DW acts on 5-d fields: Ns four-dimensional spinors psi_0 .. psi_{Ns-1}
+ * sharing the links.  In packed form a 5-d field is Ns consecutive
+ * right-hand-side columns ([vec][s][chunk][V]; pack it with
+ * wl_pack_spinor and nrhs = nvec * Ns from a canonical (nvec, Ns, Lt, Lz,
+ * Ly, Lx, 4, 3) array).  Block-tridiagonal in s:
+ *   (D_DW psi)_s = (D_W + 1) psi_s - P_- psi_{s+1} - P_+ psi_{s-1},
+ *   D_W = (m0 + 4) - H/2 (eq. (1)), P_pm = (1 pm gamma_5)/2,
+ * where psi_{Ns} stands for -m psi_0 and psi_{-1} for -m psi_{Ns-1}
+ * (the corner blocks m P_+ and m P_-).  m0 is the Wilson mass of D_W (the
+ * domain-wall height is -m0), m the quark mass.  dagger = 1 applies
+ * D_DW^dag (adjoint hop, P_+ and P_- exchanged).  11520 flop per 4-d site
+ * at Ns = 8, i.e. 1440 per 5-d site (Table I).
+ * The op borrows U_packed like wl_op_create; Ns in [1, 64].  Such an op
+ * takes dwf_apply, solve_cgnr (CG on D_DW^dag D_DW, Sec. V-C; nrhs there
+ * counts 5-d vectors, nrhs * Ns <= 64), wl_autotune / wl_get_launch /
+ * wl_set_launch (nrhs = 5-d vectors; one slice per thread, variants 0..2)
+ * and wl_op_destroy; the Wilson entry points, solve_bicgstab (its spectrum
+ * reaches Re < 0), the force and multi-lattice plans reject it with
+ * WL_EINVAL. */
+int wl_dw_op_create(const wl_geom *g, double m0, double m, int Ns, int prec, const void *U_packed, wl_op **out);
+/* out = D_DW in (dagger: D_DW^dag in) for nvec 5-d vectors (nvec * Ns <= 65535);
+ * buffer rules as wilson_apply.  Async. */
+int dwf_apply(const wl_op *op, void *out, const void *in, int dagger, int nvec, void *stream);
+
 typedef struct {
     double tol;           /* stop when ||b - D x|| <= tol ||b|| (true residual, FP64) */
     int maxiter;          /* Krylov iterations (summed over inner solves when mixed) */
@@ -157,6 +182,8 @@ int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int 
  * CG on D^dag D; BiCGStab: Sec. II-C / V-C).  lo != NULL: mixed precision --
  * FP64 outer true-residual refinement around an inner solve in lo's
  * precision (Sec. II-C: the inner low-precision solver sets the speed).
+ * With domain-wall ops (wl_dw_op_create; hi and lo with equal Ns, m0, m)
+ * only solve_cgnr is offered and nrhs counts 5-d vectors.
  * stats: array of nrhs entries (may be NULL).  Synchronises `stream`.
  * Returns the worst status over right-hand sides. */
 int solve_cgnr(const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *p,

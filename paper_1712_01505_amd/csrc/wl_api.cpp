@@ -214,6 +214,8 @@ static LaunchCfg default_launch(const wl_op *op, int nrhs)
 static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
 {
     const int prec = op->prec;
+    if (op->ns > 0 && (c.rpt != 1 || c.var > 2 || nrhs % op->ns != 0))
+        return false;  // domain wall: one slice per thread, variants 0..2
     const bool lanes_ok = c.lanes == 1 || ((c.lanes == 2 || c.lanes == 4 || c.lanes == 8) && c.rpt == 1 &&
                                            c.var < 4 && nrhs % c.lanes == 0 && c.block / c.lanes >= 64);
     return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
@@ -285,7 +287,20 @@ static StencilParams base_params(const wl_op *op, void *out, const void *in, int
     p.apply = apply;
     p.red = RED_NONE;
     p.one = 1.0f;
+    if (apply)
+        op_apply_params(op, p);
     return p;
+}
+
+void op_apply_params(const wl_op *op, StencilParams &p)
+{
+    if (op->ns > 0) {
+        p.apply = 2;
+        p.ns = op->ns;
+        p.dw_diag = op->m0 + 5.0;
+        p.dw_m = op->mq;
+        p.kappa = 0.5;
+    }
 }
 
 // ---------------------------------------------------------------- multi-lattice plans
@@ -459,6 +474,27 @@ int wl_op_create(const wl_geom *g, double kappa, int prec, const void *U_packed,
     return WL_OK;
 }
 
+int wl_dw_op_create(const wl_geom *g, double m0, double m, int Ns, int prec, const void *U_packed, wl_op **out)
+{
+    if (!geom_ok(g) || !U_packed || !out || !std::isfinite(m0) || !std::isfinite(m) || Ns < 1 || Ns > 64)
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    if (!al16(U_packed))
+        return WL_EALIGN;
+    wl_op *op = new wl_op();
+    op->g = *g;
+    op->kappa = 0.0;
+    op->prec = prec;
+    op->U = U_packed;
+    op->V = vol(g);
+    op->ns = Ns;
+    op->m0 = m0;
+    op->mq = m;
+    *out = op;
+    return WL_OK;
+}
+
 int wl_op_destroy(wl_op *op)
 {
     delete op;
@@ -481,30 +517,44 @@ static int stencil_call(const wl_op *op, void *out, const void *in, int dagger, 
     return WL_OK;
 }
 
+int dwf_apply(const wl_op *op, void *out, const void *in, int dagger, int nvec, void *stream)
+{
+    if (!op || op->ns < 1 || nvec < 1 || (long)nvec * op->ns > 65535)
+        return WL_EINVAL;
+    return stencil_call(op, out, in, dagger, nvec * op->ns, stream, 1);
+}
+
 int wilson_dslash(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream)
 {
+    if (op && op->ns > 0)
+        return WL_EINVAL;  // a domain-wall operator: dwf_apply
     return stencil_call(op, out, in, dagger, nrhs, stream, 0);
 }
 
 int wilson_apply(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream)
 {
+    if (op && op->ns > 0)
+        return WL_EINVAL;
     return stencil_call(op, out, in, dagger, nrhs, stream, 1);
 }
 
 int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs, size_t *out_bytes)
 {
-    if (!hi || !out_bytes || nrhs < 1 || nrhs > 64 || (solver != WL_SOLVER_CGNR && solver != WL_SOLVER_BICGSTAB))
+    if (!hi || !out_bytes || nrhs < 1 || op_cols(hi, nrhs) > 64 ||
+        (solver != WL_SOLVER_CGNR && solver != WL_SOLVER_BICGSTAB))
         return WL_EINVAL;
-    *out_bytes = solver_workspace_bytes(hi, lo, solver, nrhs);
+    *out_bytes = solver_workspace_bytes(hi, lo, solver, op_cols(hi, nrhs));
     return WL_OK;
 }
 
 static int solve_entry(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
                        const wl_solve_params *p, wl_solve_stats *stats, void *stream)
 {
-    if (!hi || !x || !b || !p || nrhs < 1 || nrhs > 64 || x == b || !(p->tol > 0) || p->maxiter < 1 ||
-        (p->dagger != 0 && p->dagger != 1))
+    if (!hi || !x || !b || !p || nrhs < 1 || op_cols(hi, nrhs) > 64 || x == b || !(p->tol > 0) ||
+        p->maxiter < 1 || (p->dagger != 0 && p->dagger != 1))
         return WL_EINVAL;
+    if (hi->ns > 0 && solver != WL_SOLVER_CGNR)
+        return WL_EINVAL;  // domain wall: CG on the normal equations only (Sec. V-C)
     if (!al16(x) || !al16(b))
         return WL_EALIGN;
     if (lo) {
@@ -513,7 +563,7 @@ static int solve_entry(int solver, const wl_op *hi, const wl_op *lo, void *x, co
         for (int i = 0; i < 4; ++i)
             if (lo->g.dims[i] != hi->g.dims[i] || lo->g.bc[i] != hi->g.bc[i])
                 return WL_EINVAL;
-        if (lo->kappa != hi->kappa)
+        if (lo->kappa != hi->kappa || lo->ns != hi->ns || lo->m0 != hi->m0 || lo->mq != hi->mq)
             return WL_EINVAL;
     } else if (hi->prec != WL_F64 && hi->prec != WL_F32) {
         return WL_EPREC;  // plain solves run in FP64 or FP32 storage
@@ -535,7 +585,7 @@ int solve_bicgstab(const wl_op *hi, const wl_op *lo, void *x, const void *b, int
 
 int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const void *mu, int project, void *stream)
 {
-    if (!op || !out_canon || !x || !mu || project < 0 || project > 2)
+    if (!op || !out_canon || !x || !mu || project < 0 || project > 2 || op->ns > 0)
         return WL_EINVAL;
     if (op->prec != WL_F64 && op->prec != WL_F32)
         return WL_EPREC;
@@ -554,7 +604,7 @@ int wl_multi_plan_create(const wl_multi_desc *d, int n, int dagger, int nrhs, wl
         return WL_EINVAL;
     const int prec = d[0].op ? d[0].op->prec : -1;
     for (int i = 0; i < n; ++i) {
-        if (!d[i].op || !d[i].out || !d[i].in || d[i].out == d[i].in)
+        if (!d[i].op || !d[i].out || !d[i].in || d[i].out == d[i].in || d[i].op->ns > 0)
             return WL_EINVAL;
         if (d[i].op->prec != prec)
             return WL_EPREC;
@@ -713,7 +763,7 @@ int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg)
 {
     if (!op || nrhs < 1 || !cfg)
         return WL_EINVAL;
-    const LaunchCfg c = launch_for(op, nrhs, RED_NONE);
+    const LaunchCfg c = launch_for(op, op_cols(op, nrhs), RED_NONE);
     cfg->block = c.block;
     cfg->rhs_per_thread = c.rpt;
     cfg->rhs_lanes = c.lanes;
@@ -726,6 +776,7 @@ int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg)
 {
     if (!op || nrhs < 1 || !cfg)
         return WL_EINVAL;
+    nrhs = op_cols(op, nrhs);
     LaunchCfg c;
     c.block = cfg->block;
     c.rpt = cfg->rhs_per_thread;
@@ -742,8 +793,9 @@ int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg)
 
 int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
 {
-    if (!op || nrhs < 1 || nrhs > 64 || (dagger != 0 && dagger != 1))
+    if (!op || nrhs < 1 || op_cols(op, nrhs) > 64 || (dagger != 0 && dagger != 1))
         return WL_EINVAL;
+    nrhs = op_cols(op, nrhs);
     hipStream_t st = (hipStream_t)stream;
     const size_t vb = (size_t)nrhs * op->V * spinor_site_bytes(op->prec);
     void *in = nullptr, *out = nullptr;
@@ -777,9 +829,15 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     double *parts = nullptr;
     if (e == hipSuccess)
         e = hipMalloc(&parts, 3 * sizeof(double) * (size_t)nrhs * ((op->V + 63) / 64 + op->g.dims[3] + 8));
+    // a domain-wall operator has only the reductions of CG on the normal equations
+    const int last_red = op->ns > 0 ? (int)RED_NORM : (int)RED_DOTIN_NORM;
     for (int red = RED_NONE; red <= RED_DOTIN_NORM && e == hipSuccess; ++red) {
         float best_ms = INFINITY;
         LaunchCfg best = default_launch(op, nrhs);
+        if (red > last_red) {
+            bests[red] = bests[last_red];
+            continue;
+        }
         for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
             const LaunchCfg c = cands[ci];
             StencilParams p = base_params(op, out, in, nrhs, 1);

@@ -288,6 +288,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
 {
     __shared__ double lds[FIN_G * FIN_THREADS / 64];
     __shared__ double sums[3 * FIN_MAX];
+    __shared__ double gsums[3 * FIN_MAX];
     const int nr = p.nrhs;
     const int na = p.nvalA * nr, nb = p.nvalB * nr, ncomb = na + nb + p.nvalC * nr;
     for (int c0 = 0; c0 < ncomb; c0 += FIN_G) {
@@ -326,7 +327,21 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         }
         __syncthreads();
     }
-    const double *sA = sums, *sB = sums + na, *sC = sums + na + nb;
+    const double *S = sums;
+    if (p.group > 1) {
+        // several columns form one linear system (a 5-d domain-wall vector):
+        // every column of a group gets the group's total, in a fixed order
+        __syncthreads();
+        for (int c = threadIdx.x; c < ncomb; c += blockDim.x) {
+            const int first = c - (c % nr) % p.group;  // sets start at multiples of nr
+            double a = 0.0;
+            for (int j = 0; j < p.group; ++j)
+                a += sums[first + j];
+            gsums[c] = a;
+        }
+        S = gsums;
+    }
+    const double *sA = S, *sB = S + na, *sC = S + na + nb;
     __syncthreads();
     const int r = threadIdx.x;
     if (r >= nr)

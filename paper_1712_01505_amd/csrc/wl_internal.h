@@ -29,8 +29,11 @@ struct LaunchCfg {
 
 struct wl_op {
     wl_geom g;
-    double kappa;
+    double kappa;     // Wilson: hopping parameter
     int prec;
+    int ns = 0;       // domain wall: fifth-dimension extent (0 = Wilson operator)
+    double m0 = 0.0;  // domain wall: Wilson mass of D_W and quark mass m
+    double mq = 0.0;
     const void *U;
     uint32_t V;
     std::mutex mu;
@@ -61,7 +64,10 @@ struct StencilParams {
     uint32_t V;
     int nrhs;
     double kappa;
-    int apply;  // 1: out = in - kappa H in; 0: out = H in
+    int apply;  // 1: out = in - kappa H in; 0: out = H in; 2: domain wall (ns, dw_diag, dw_m)
+    int ns;          // apply 2: columns r form 5-d vectors of ns slices (s = r mod ns)
+    double dw_diag;  // apply 2: m0 + 5 (the diagonal of D_W + 1); the hop enters with -1/2
+    double dw_m;     // apply 2: quark mass m of the corner blocks
     int red;
     int xcd;
     int nblk;   // number of site tiles (partials per right-hand side)
@@ -93,6 +99,11 @@ bool multi_launch_ok(int prec, int rpt, int block, int var);
 hipError_t launch_multi(int prec, int dagger, int rpt, int block, int var, const MultiEntry *dev_entries, int n,
                         uint32_t total_items, unsigned *counter, int grid, hipStream_t st);
 int multi_grid_size(int prec, int dagger, int rpt, int block, int var);
+
+// Kind-specific stencil parameters of an operator (domain wall: apply 2).
+void op_apply_params(const wl_op *op, StencilParams &p);
+// Stencil columns of nrhs vectors: nrhs for Wilson, nrhs x ns for domain wall.
+inline int op_cols(const wl_op *op, int nrhs) { return op->ns > 0 ? nrhs * op->ns : nrhs; }
 
 hipError_t launch_force(int prec, const wl_op *op, void *out, const void *x, const void *mu, int project,
                         hipStream_t st);
@@ -180,6 +191,7 @@ struct FinParams {
     int iter;
     double tol2;
     const double *tol2v;  // optional per-column tol2 for the F_INIT_* ops (overrides tol2)
+    int group;            // columns per linear system (domain wall: ns); sums are taken per group
 };
 hipError_t launch_finalize(int op, const FinParams &p, hipStream_t st);
 hipError_t launch_scalars_init(Scalars *sc, int nrhs, double tol2, hipStream_t st);

@@ -152,6 +152,7 @@ struct Engine {
     int lookahead = 2;
     int adj = 0;  // solving with D^dag: every stencil's dagger flag is flipped
     int stencil_calls = 0;
+    int group = 1;  // columns per linear system (domain wall: the fifth-dimension extent)
     const double *tol2v = nullptr;  // optional per-column tolerance^2 (device)
     // Called after each queued BiCGStab iteration that did not stop the run
     // (the reliable-update check of the mixed solver).
@@ -163,6 +164,7 @@ struct Engine {
         solver = solv;
         nrhs = n;
         prec = o->prec;
+        group = o->ns > 0 ? o->ns : 1;
         V = o->V;
         st = s;
         hb = h;
@@ -202,6 +204,7 @@ struct Engine {
         p.kappa = op->kappa;
         p.apply = 1;
         p.red = red;
+        op_apply_params(op, p);
         LaunchCfg cfg = launch_for(op, nrhs, red);
         if (slot >= 0) {
             nblk[slot] = stencil_partials(cfg, p.L, V, nrhs);
@@ -261,6 +264,7 @@ struct Engine {
         p.iter = iter;
         p.tol2 = tol2;
         p.tol2v = tol2v;
+        p.group = group;
         WL_TRY(launch_finalize(fop, p, st));
         return WL_OK;
     }
@@ -703,7 +707,12 @@ int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, 
           wl_solve_stats *stats, hipStream_t st)
 {
     const auto t0 = std::chrono::steady_clock::now();
-    const size_t need = solver_workspace_bytes(hi, lo, solver, nrhs);
+    // a domain-wall system spans ns columns; the engines work on columns and
+    // every reduction is taken over a system's columns, so the per-column
+    // results of one system agree and its first column reports them
+    const int G = hi->ns > 0 ? hi->ns : 1;
+    const int ncols = nrhs * G;
+    const size_t need = solver_workspace_bytes(hi, lo, solver, ncols);
     OwnedWorkspace own;
     Arena arena{nullptr, 0};
     if (prm->workspace) {
@@ -725,13 +734,16 @@ int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, 
     if (mis) {
         arena.off = ALIGN - mis;
     }
-    int rc = lo ? solve_mixed(solver, hi, lo, x, b, nrhs, prm, stats, st, arena)
-                : solve_plain(solver, hi, x, b, nrhs, prm, stats, st, arena);
+    std::vector<wl_solve_stats> cst(ncols);
+    int rc = lo ? solve_mixed(solver, hi, lo, x, b, ncols, prm, cst.data(), st, arena)
+                : solve_plain(solver, hi, x, b, ncols, prm, cst.data(), st, arena);
     (void)hipStreamSynchronize(st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats && rc >= 0)
-        for (int r = 0; r < nrhs; ++r)
+        for (int r = 0; r < nrhs; ++r) {
+            stats[r] = cst[(size_t)r * G];
             stats[r].seconds = secs;
+        }
     return rc;
 }
 

@@ -625,6 +625,41 @@ __device__ __forceinline__ void round_site(cx<float> (&v)[12])
     }
 }
 
+// Domain-wall epilogue (Sec. II-B, eq. (2)) for slice s5 = col mod ns of a
+// 5-d vector: out = (m0 + 5) in - H in / 2 - P_up in(s5 + 1) - P_dn in(s5 - 1),
+// where the neighbour past either end of the fifth dimension is replaced by
+// -m times the slice at the other end.  P_up = P_- and P_dn = P_+ for D_DW;
+// the adjoint swaps them (the hop then already uses the adjoint projectors).
+// With gamma_5 = diag(1, 1, -1, -1), P_+ keeps spins 0, 1 (components 0..5)
+// and P_- spins 2, 3 (components 6..11).
+template <int P, int DAG>
+__device__ __forceinline__ void dw_epilogue(const StencilParams &p, uint32_t s, int col,
+                                            const cx<typename Traits<P>::real> (&in)[12],
+                                            const cx<typename Traits<P>::real> (&acc)[12],
+                                            cx<typename Traits<P>::real> (&o)[12])
+{
+    using T = typename Traits<P>::real;
+    const int ns = p.ns;
+    const int s5 = col % ns, base = col - s5;
+    const bool top = s5 + 1 == ns, bot = s5 == 0;
+    const T cu = top ? (T)p.dw_m : T(-1), cd = bot ? (T)p.dw_m : T(-1);
+    cx<T> up[12], dn[12];
+    load_site<P>(p.in, p.V, p.nrhs, s, top ? base : col + 1, up);
+    load_site<P>(p.in, p.V, p.nrhs, s, bot ? base + ns - 1 : col - 1, dn);
+    const T diag = (T)p.dw_diag, half = T(0.5);
+    // P_up selects components [ub, ub + 6), P_dn the other six
+    constexpr int ub = DAG ? 0 : 6, db = DAG ? 6 : 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        cx<T> v{fma(-half, acc[k].re, diag * in[k].re), fma(-half, acc[k].im, diag * in[k].im)};
+        if (k >= ub && k < ub + 6)
+            v = rfma(cu, up[k], v);
+        if (k >= db && k < db + 6)
+            v = rfma(cd, dn[k], v);
+        o[k] = v;
+    }
+}
+
 template <int P, int DAG, int R, int RED, int APPLY, int VAR>
 __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 {
@@ -674,7 +709,9 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
             if constexpr (APPLY || RED == RED_DOTIN_NORM) {
                 cx<T> in[12];
                 load_site<P>(p.in, p.V, p.nrhs, s, r0 + r, in);
-                if constexpr (APPLY) {
+                if constexpr (APPLY == 2) {
+                    dw_epilogue<P, DAG>(p, s, r0 + r, in, acc[r], o);
+                } else if constexpr (APPLY) {
 #pragma unroll
                     for (int k = 0; k < 12; ++k)
                         o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
@@ -765,6 +802,17 @@ static void set_groups(StencilParams &p, uint32_t tiles, uint32_t ng)
 template <int P, int DAG, int R, int VAR>
 static hipError_t launch_v(dim3 grid, dim3 block, const StencilParams &p, hipStream_t st)
 {
+    if (p.apply == 2) {  // domain wall: R = 1, variants 0..2, the reductions CG needs
+        if constexpr (R == 1 && VAR <= 2) {
+            switch (p.red) {
+            case RED_NONE: hipLaunchKernelGGL((stencil_kernel<P, DAG, 1, RED_NONE, 2, VAR>), grid, block, 0, st, p); break;
+            case RED_NORM: hipLaunchKernelGGL((stencil_kernel<P, DAG, 1, RED_NORM, 2, VAR>), grid, block, 0, st, p); break;
+            default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (!p.apply) {  // the hopping term alone is only offered without fused reductions
         if (p.red != RED_NONE)
             return hipErrorInvalidValue;
@@ -890,6 +938,8 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
         cfg.block % 64 != 0 || lg < 0 ||
         (lg > 0 && (cfg.rpt != 1 || cfg.var >= 4 || p.nrhs % cfg.lanes != 0 || (cfg.block >> lg) < 64)))
         return hipErrorInvalidValue;
+    if (p.apply == 2 && (cfg.rpt != 1 || cfg.var > 2 || p.ns < 1 || p.nrhs % p.ns != 0))
+        return hipErrorInvalidValue;  // domain wall: one slice per thread, variants 0..2
     p.lanes_lg = lg;
     const int tile = cfg.block >> lg;
     p.nblk = (int)((p.V + tile - 1) / tile);

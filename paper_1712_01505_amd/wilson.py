@@ -37,6 +37,7 @@ EXPORTS = [
     "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read",
     "wl_stream_copy", "wl_strerror", "wl_last_hip_error", "wl_multi_plan_create", "wl_multi_plan_run",
     "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
+    "wl_dw_op_create", "dwf_apply",
 ]
 
 
@@ -100,6 +101,8 @@ def lib():
         "wl_convert_spinor": [G, I, I, I, P, P, P],
         "wl_op_create": [G, D, I, P, ctypes.POINTER(P)],
         "wl_op_destroy": [P],
+        "wl_dw_op_create": [G, D, D, I, I, P, ctypes.POINTER(P)],
+        "dwf_apply": [P, P, P, I, I, P],
         "wilson_dslash": [P, P, P, I, I, P],
         "wilson_apply": [P, P, P, I, I, P],
         "wl_solver_workspace_bytes": [P, P, I, I, ctypes.POINTER(SZ)],
@@ -414,6 +417,129 @@ class Operator:
 
     def dslash_packed(self, out, inp, nrhs=1, dagger=False):
         wilson_dslash(self.handle, _ptr(out), _ptr(inp), dagger, nrhs, _stream())
+
+
+@dataclass
+class DWOperator:
+    """Domain-wall D_DW (eq. (2)) with Ns slices on packed links of one
+    precision (owns the packed links).  5-d fields are canonical complex128
+    tensors of shape (Ns, Lt, Lz, Ly, Lx, 4, 3), or (nvec, Ns, ...) for several."""
+
+    dims: tuple
+    m0: float
+    m: float
+    ns: int
+    prec: int
+    bc: tuple
+    U_packed: object
+    handle: int
+
+    @classmethod
+    def create(cls, U, m0, m, Ns, prec=WL_F64, bc=(1, 1, 1, -1)):
+        torch = _torch()
+        if U.dtype != torch.complex128 or not U.is_cuda:
+            raise TypeError("DWOperator.create expects a complex128 CUDA gauge tensor")
+        U = U.contiguous()
+        Lt, Lz, Ly, Lx = U.shape[1:5]
+        dims = (Lx, Ly, Lz, Lt)
+        geom = make_geom(dims, bc)
+        Up = alloc_field(geom, WL_GAUGE, prec, 1, U.device)
+        wl_pack_gauge(geom, prec, _ptr(U), _ptr(Up), _stream())
+        h = ctypes.c_void_p()
+        _check(lib().wl_dw_op_create(ctypes.byref(geom), float(m0), float(m), int(Ns), prec, _ptr(Up),
+                                     ctypes.byref(h)), "wl_dw_op_create")
+        return cls(dims, float(m0), float(m), int(Ns), prec, tuple(bc), Up, h.value)
+
+    @property
+    def geom(self):
+        return make_geom(self.dims, self.bc)
+
+    def close(self):
+        if self.handle:
+            wl_op_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 -- interpreter shutdown
+            pass
+
+    def _nvec(self, psi):
+        if psi.dim() == 7:
+            return None
+        if psi.dim() == 8:
+            return int(psi.shape[0])
+        raise ValueError("a 5-d field has shape (Ns, Lt, Lz, Ly, Lx, 4, 3) or (nvec, Ns, ...)")
+
+    def pack(self, psi):
+        if int(psi.shape[-7]) != self.ns:
+            raise ValueError(f"expected Ns = {self.ns} slices")
+        return pack_spinor(psi.reshape((-1,) + tuple(psi.shape[-6:])), self.prec, self.bc)
+
+    def unpack(self, packed, nvec=None):
+        x = unpack_spinor(packed, self.dims, self.prec, (nvec or 1) * self.ns, self.bc)
+        lead = (nvec, self.ns) if nvec else (self.ns,)
+        return x.reshape(lead + tuple(x.shape[1:]))
+
+    def new_field(self, nvec=1):
+        return alloc_field(self.geom, WL_SPINOR, self.prec, nvec * self.ns, self.U_packed.device)
+
+    def apply_packed(self, out, inp, nvec=1, dagger=False):
+        _check(lib().dwf_apply(self.handle, _ptr(out), _ptr(inp), int(bool(dagger)), int(nvec), _stream()),
+               "dwf_apply")
+
+
+def dw_apply(U, psi, m0, m, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None):
+    """D_DW psi (or D_DW^dag psi) for a canonical 5-d complex128 CUDA tensor."""
+    p = PREC[prec] if isinstance(prec, str) else prec
+    ns = int(psi.shape[-7])
+    op = op or DWOperator.create(U, m0, m, ns, p, bc)
+    nvec = op._nvec(psi)
+    src = op.pack(psi)
+    dst = op.new_field(nvec or 1)
+    op.apply_packed(dst, src, nvec or 1, dagger)
+    return op.unpack(dst, nvec)
+
+
+def dw_solve(U, b, m0, m, precision="f64", tol=1e-10, maxiter=20000, bc=(1, 1, 1, -1), inner_tol=0.0,
+             check_every=0, x0=None, ops=None, return_stats=False):
+    """x = D_DW^{-1} b by CG on D_DW^dag D_DW (Sec. V-C) for a canonical 5-d
+    complex128 CUDA tensor b (Ns, ...) or (nvec, Ns, ...).
+
+    precision: "f64", "f32", or "mixed-f32" / "mixed-bf16" / "mixed-f16" (FP64
+    refinement around an inner CG with that storage).  ops: optional (hi, lo)
+    DWOperators to reuse."""
+    torch = _torch()
+    ns = int(b.shape[-7])
+    if ops is not None:
+        hi, lo = ops
+    elif precision.startswith("mixed-"):
+        hi = DWOperator.create(U, m0, m, ns, WL_F64, bc)
+        lo = DWOperator.create(U, m0, m, ns, PREC[precision.split("-", 1)[1]], bc)
+    else:
+        hi = DWOperator.create(U, m0, m, ns, PREC[precision], bc)
+        lo = None
+    nvec = hi._nvec(b)
+    n = nvec or 1
+    bp = hi.pack(b)
+    xp = hi.pack(x0) if x0 is not None else hi.new_field(n)
+    prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=0,
+                          check_every=check_every, use_x0=1 if x0 is not None else 0, dagger=0,
+                          workspace=None, workspace_bytes=0)
+    ws = wl_solver_workspace_bytes(hi.handle, lo.handle if lo else None, WL_SOLVER_CGNR, n)
+    work = torch.empty(ws, dtype=torch.uint8, device=b.device)
+    prm.workspace = work.data_ptr()
+    prm.workspace_bytes = ws
+    stats = (wl_solve_stats * n)()
+    code = solve_cgnr(hi.handle, lo.handle if lo else None, _ptr(xp), _ptr(bp), n, prm, stats, _stream())
+    x = hi.unpack(xp, nvec)
+    st = [s_.as_dict() for s_ in stats]
+    for s_ in st:
+        s_["status"] = code
+    if return_stats:
+        return x, (st[0] if nvec is None else st)
+    return x
 
 
 def apply(U, psi, kappa, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None):

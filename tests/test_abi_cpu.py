@@ -116,6 +116,27 @@ def test_bad_arguments_rejected_before_launch():
         assert L.wl_multi_plan_destroy(None) == wilson.WL_EINVAL
     finally:
         L.wl_op_destroy(op)
+    # domain-wall operators
+    assert L.wl_dw_op_create(ctypes.byref(g), -1.8, 0.1, 0, 0, 256, ctypes.byref(h)) == wilson.WL_EINVAL  # Ns
+    assert L.wl_dw_op_create(ctypes.byref(g), float("inf"), 0.1, 4, 0, 256, ctypes.byref(h)) == wilson.WL_EINVAL
+    assert L.wl_dw_op_create(ctypes.byref(g), -1.8, 0.1, 4, 0, 8, ctypes.byref(h)) == wilson.WL_EALIGN
+    assert L.wl_dw_op_create(ctypes.byref(g), -1.8, 0.1, 8, 0, 256, ctypes.byref(h)) == wilson.WL_OK
+    dw = h.value
+    try:
+        assert L.wilson_apply(dw, 512, 1024, 0, 8, None) == wilson.WL_EINVAL  # not a Wilson op
+        assert L.dwf_apply(dw, 512, 1024, 0, 0, None) == wilson.WL_EINVAL  # nvec
+        assert L.dwf_apply(dw, 512, 512, 0, 1, None) == wilson.WL_EINVAL  # in == out
+        prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
+        assert L.solve_bicgstab(dw, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
+        assert L.solve_cgnr(dw, None, 512, 1024, 9, ctypes.byref(prm), None, None) == wilson.WL_EINVAL  # 72 columns
+        c = wilson.wl_launch(block=256, rhs_per_thread=2, rhs_lanes=1, xcd_remap=0, variant=0)
+        assert L.wl_set_launch(dw, 1, ctypes.byref(c)) == wilson.WL_EINVAL  # one slice per thread
+        c = wilson.wl_launch(block=256, rhs_per_thread=1, rhs_lanes=4, xcd_remap=0, variant=2)
+        assert L.wl_set_launch(dw, 1, ctypes.byref(c)) == wilson.WL_EINVAL  # FP64 offers variants 0, 1
+        c = wilson.wl_launch(block=512, rhs_per_thread=1, rhs_lanes=8, xcd_remap=0, variant=1)
+        assert L.wl_set_launch(dw, 1, ctypes.byref(c)) == wilson.WL_OK
+    finally:
+        L.wl_op_destroy(dw)
     for c in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):
         assert L.wl_strerror(c).decode() != "unknown error"
 
