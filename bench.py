@@ -165,6 +165,71 @@ def bench_batching(W, inputs, torch, log):
     return out
 
 
+DW_FLOP_PER_5D_SITE = 11520 // 8  # Table I: 11520 flop per 4-d site at Ns = 8
+
+
+def bench_dwf(W, inputs, torch, log):
+    """Domain-wall operator (eq. (2), Ns = 8, m0 = -1.8, m = 0.05): apply
+    throughput per precision on the paper's per-node 16^3 x 32 lattice and on
+    32^3 x 64, and CG on D^dag D (FP64, mixed FP32, mixed FP16) to 1e-10 at
+    16^3 x 32.  Compulsory bytes per 5-d site: two spinors plus the links
+    shared by the Ns slices (FP64 384 + 384/Ns, FP32 192 + 192/Ns, 16-bit
+    104 + 96/Ns)."""
+    out = {}
+    Ns, m0, mq = 8, -1.8, 0.05
+    spin = {0: 192, 1: 96, 2: 52, 3: 52}
+    link4 = {0: 384, 1: 192, 2: 96, 3: 96}
+    st = W._stream()
+    for dims in ((16, 16, 16, 32), (32, 32, 32, 64)):
+        V = inputs.volume(dims)
+        log(f"[bench] domain wall: generating {dims} x Ns={Ns}")
+        Ud = torch.from_numpy(inputs.near_unity_gauge(dims, 0.3, seed=inputs.GAUGE_SEED)).cuda()
+        src = torch.stack([torch.from_numpy(inputs.gaussian_spinor(dims, seed=s)) for s in range(Ns)]).cuda()
+        res = {}
+        for p in (0, 1, 3):
+            op = W.DWOperator.create(Ud, m0, mq, Ns, p)
+            W.wl_autotune(op.handle, 1, 0, st)
+            a = op.pack(src)
+            b = op.new_field()
+            ms = _time_ms(torch, lambda: op.apply_packed(b, a), 10)
+            nbytes = (2 * spin[p] + link4[p] / Ns) * V * Ns
+            res[PNAME[p]] = {"us": round(ms * 1e3, 1),
+                             "GFLOP/s": round(DW_FLOP_PER_5D_SITE * V * Ns / (ms * 1e-3) / 1e9, 1),
+                             "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                             "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "launch": W.wl_get_launch(op.handle, 1)}
+            log(f"[bench] dw apply {dims} {PNAME[p]}: {res[PNAME[p]]}")
+            del op, a, b
+        out["apply_%dx%dx%dx%d" % dims] = res
+        if dims == (16, 16, 16, 32):
+            solves = {}
+            hi = W.DWOperator.create(Ud, m0, mq, Ns, W.WL_F64)
+            W.wl_autotune(hi.handle, 1, 0, st)
+            for prec in ("f64", "mixed-f32", "mixed-f16"):
+                lo = None
+                if prec != "f64":
+                    lo = W.DWOperator.create(Ud, m0, mq, Ns, W.PREC[prec.split("-")[1]])
+                    W.wl_autotune(lo.handle, 1, 0, st)
+                W.dw_solve(None, src, m0, mq, precision=prec, tol=1e-10, ops=(hi, lo))  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, stt = W.dw_solve(None, src, m0, mq, precision=prec, tol=1e-10, ops=(hi, lo), return_stats=True)
+                dt = time.perf_counter() - t0
+                solves[prec] = {"seconds": round(dt, 4), "status": stt["status"], "iters": stt["iters"],
+                                "outer": stt["outer"], "true_rel_res": stt["true_rel_res"]}
+                log(f"[bench] dw cgnr {prec}: {solves[prec]}")
+            base = solves["f64"]["seconds"]
+            for v in solves.values():
+                v["speedup_vs_f64"] = round(base / v["seconds"], 3)
+            out["cgnr_16x16x16x32"] = solves
+            del hi
+        del Ud, src
+        torch.cuda.empty_cache()
+    out["paper_knl_context"] = {"dw_mult_GFLOPs_16x16x16x32": 155.2, "dw_mult_GFLOPs_32x32x32x64": 211.8,
+                                "note": "single KNL node, single precision, boundary copy enforced (context only)"}
+    return out
+
+
 def bench_autograd(W, inputs, torch, log):
     """Differentiable solve at 16^3 x 32, kappa 0.12: L = ||D^{-1} b||^2,
     forward (mixed FP32/FP64) + backward (adjoint solve + link force)."""
@@ -359,6 +424,7 @@ def main():
         torch.cuda.empty_cache()
         result["batching"] = bench_batching(W, inputs, torch, log)
         result["differentiable"] = bench_autograd(W, inputs, torch, log)
+        result["domain_wall"] = bench_dwf(W, inputs, torch, log)
 
     if not args.no_cpu:
         import oracle
