@@ -205,19 +205,25 @@ def bench_dwf(W, inputs, torch, log):
             solves = {}
             hi = W.DWOperator.create(Ud, m0, mq, Ns, W.WL_F64)
             W.wl_autotune(hi.handle, 1, 0, st)
-            for prec in ("f64", "mixed-f32", "mixed-f16"):
+            los = {}
+            for prec, rel in (("f64", 0), ("mixed-f32", 0), ("mixed-f16", 0), ("mixed-f32", 1)):
                 lo = None
                 if prec != "f64":
-                    lo = W.DWOperator.create(Ud, m0, mq, Ns, W.PREC[prec.split("-")[1]])
-                    W.wl_autotune(lo.handle, 1, 0, st)
-                W.dw_solve(None, src, m0, mq, precision=prec, tol=1e-10, ops=(hi, lo))  # warm-up
+                    if prec not in los:
+                        los[prec] = W.DWOperator.create(Ud, m0, mq, Ns, W.PREC[prec.split("-")[1]])
+                        W.wl_autotune(los[prec].handle, 1, 0, st)
+                    lo = los[prec]
+                W.dw_solve(None, src, m0, mq, precision=prec, tol=1e-10, ops=(hi, lo), reliable=bool(rel))  # warm-up
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                x, stt = W.dw_solve(None, src, m0, mq, precision=prec, tol=1e-10, ops=(hi, lo), return_stats=True)
+                x, stt = W.dw_solve(None, src, m0, mq, precision=prec, tol=1e-10, ops=(hi, lo), return_stats=True,
+                                    reliable=bool(rel))
                 dt = time.perf_counter() - t0
-                solves[prec] = {"seconds": round(dt, 4), "status": stt["status"], "iters": stt["iters"],
-                                "outer": stt["outer"], "true_rel_res": stt["true_rel_res"]}
-                log(f"[bench] dw cgnr {prec}: {solves[prec]}")
+                key = prec + ("_reliable" if rel else "")
+                solves[key] = {"seconds": round(dt, 4), "status": stt["status"], "iters": stt["iters"],
+                               "outer": stt["outer"], "true_rel_res": stt["true_rel_res"]}
+                log(f"[bench] dw cgnr {key}: {solves[key]}")
+            del los
             base = solves["f64"]["seconds"]
             for v in solves.values():
                 v["speedup_vs_f64"] = round(base / v["seconds"], 3)
@@ -405,7 +411,8 @@ def main():
         solves = {}
         for method, lo, rel in (("bicgstab", None, 0), ("cgnr", None, 0), ("bicgstab", W.WL_F32, 0),
                                 ("bicgstab", W.WL_BF16S, 0), ("bicgstab", W.WL_F16S, 0), ("cgnr", W.WL_F16S, 0),
-                                ("bicgstab", W.WL_F32, 1), ("bicgstab", W.WL_BF16S, 1), ("bicgstab", W.WL_F16S, 1)):
+                                ("bicgstab", W.WL_F32, 1), ("bicgstab", W.WL_BF16S, 1), ("bicgstab", W.WL_F16S, 1),
+                                ("cgnr", W.WL_F32, 0), ("cgnr", W.WL_F32, 1)):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             code, st = run_solve(method, lo, rel)

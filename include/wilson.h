@@ -153,9 +153,12 @@ typedef struct {
                              reliable updates: residual drop that triggers an FP64 update
                              (0 = default: 1e-5 FP32 / 3e-2 16-bit; 0.1 for reliable updates) */
     int max_outer;        /* mixed: maximum outer (refinement) cycles (0 = default 50) */
-    int reliable;         /* mixed BiCGStab: 0 = defect correction (restart the inner solve per
-                             cycle), 1 = reliable updates (one inner run, FP64 solution and
-                             residual refreshed in place).  Ignored by CGNR. */
+    int reliable;         /* mixed: 0 = defect correction (restart the inner solve per cycle),
+                             1 = reliable updates (one inner run, FP64 solution and residual
+                             refreshed in place; BiCGStab re-derives rho and beta, CGNR
+                             recomputes z = D^dag r and keeps its search direction unless
+                             |r| has grown since the previous update).  CGNR with a
+                             16-bit inner op keeps defect correction. */
     int check_every;      /* host convergence check period in iterations (0 = default) */
     int use_x0;           /* 1 = x holds the initial guess on entry, 0 = start from x = 0 */
     int dagger;           /* 1 = solve D^dag x = b (the adjoint system; D^dag = gamma5 D gamma5) */

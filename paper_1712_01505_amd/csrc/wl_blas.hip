@@ -62,6 +62,8 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
     const int nr = p.nrhs;
     if (p.skip_frozen && p.sc[r].frozen)  // whole workgroup: one column per blockIdx.y
         return;
+    if (OP == B_CG_RESTART && !p.sc[r].restart)
+        return;
     double red[3] = {0.0, 0.0, 0.0};
     if (s < V) {
         const Scalars &sc = p.sc[r];
@@ -157,6 +159,10 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             cx<T> v[12];
             load_site<P>(p.a0, V, nr, s, r, v);
             red[0] = n2(v);
+        } else if constexpr (OP == B_CG_RESTART) {  // p = z
+            cx<T> v[12];
+            load_site<P>(p.a0, V, nr, s, r, v);
+            store_site<P>(p.y0, V, nr, s, r, v);
         } else if constexpr (OP == B_DOT_NORM) {
             cx<T> a[12], b[12];
             load_site<P>(p.a0, V, nr, s, r, a);
@@ -201,6 +207,7 @@ static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hip
     case B_ZERO: hipLaunchKernelGGL((blas_kernel<P, B_ZERO>), g, b, 0, st, p); break;
     case B_NORM: hipLaunchKernelGGL((blas_kernel<P, B_NORM>), g, b, 0, st, p); break;
     case B_DOT_NORM: hipLaunchKernelGGL((blas_kernel<P, B_DOT_NORM>), g, b, 0, st, p); break;
+    case B_CG_RESTART: hipLaunchKernelGGL((blas_kernel<P, B_CG_RESTART>), g, b, 0, st, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -358,6 +365,8 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         sc.rr = sA[r];
         sc.zz = sB[r];
         sc.bb = sC[r];
+        sc.rr_upd = sc.rr;
+        sc.restart = 0;
         sc.tol2 = p.tol2v ? p.tol2v[r] : p.tol2;
         sc.alpha = sc.beta = zero;
         sc.flag = 0;
@@ -401,6 +410,32 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         }
         sc.beta = zero;
         sc.frozen = 1;  // end of the iteration with flag != 0
+        break;
+    }
+    case F_CG_RELIABLE: {
+        // r was replaced by the (converted) true residual and z = D^dag r
+        // recomputed; the search direction is kept
+        if (sc.flag == 0) {
+            const double rr = sA[r], zz = sB[r];
+            sc.rr = rr;
+            if (!finite2(rr) || !finite2(zz))
+                sc.flag = 3;
+            else if (rr <= sc.tol2 * sc.bb) {
+                sc.flag = 1;
+                sc.conv_iter = p.iter + 1;
+            } else if (zz > 0.0) {
+                sc.zz = zz;
+                // |r| has grown since the previous update: the low-precision
+                // recurrence has lost its search space; start it again from z
+                sc.restart = rr > sc.rr_upd;
+                sc.rr_upd = rr;
+            } else
+                sc.flag = 2;
+            if (sc.flag != 0) {
+                sc.alpha = sc.beta = zero;
+                sc.frozen = 1;
+            }
+        }
         break;
     }
     case F_INIT_BI: {

@@ -141,6 +141,45 @@ struct CField {
     int nrhs;
 };
 
+// Stores of a kernel's final output that nothing in the same kernel reads
+// again can bypass the caches' allocation (non-temporal), leaving L2 to the
+// neighbour data the stencil re-reads.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned nt_u4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ void st16(double2 *p, double2 v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(nt_d2{v.x, v.y}, reinterpret_cast<nt_d2 *>(p));
+    else
+        *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st16(float4 *p, float4 v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(nt_f4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_f4 *>(p));
+    else
+        *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st16(uint4 *p, uint4 v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(nt_u4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_u4 *>(p));
+    else
+        *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st4(float *p, float v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <int P>
 __device__ __forceinline__ const float *scale_ptr(const void *base, uint32_t V, int nrhs)
 {
@@ -207,7 +246,7 @@ __device__ __forceinline__ void load_site_unscaled(const void *base, uint32_t V,
     }
 }
 
-template <int P>
+template <int P, bool NT = false>
 __device__ __forceinline__ void store_site(void *base, uint32_t V, int nrhs, uint32_t s, int rhs,
                                            const cx<typename Traits<P>::real> (&v)[12])
 {
@@ -216,12 +255,12 @@ __device__ __forceinline__ void store_site(void *base, uint32_t V, int nrhs, uin
         double2 *b = reinterpret_cast<double2 *>(base) + off;
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-            b[(size_t)k * V] = make_double2(v[k].re, v[k].im);
+            st16<NT>(&b[(size_t)k * V], make_double2(v[k].re, v[k].im));
     } else if constexpr (P == F32) {
         float4 *b = reinterpret_cast<float4 *>(base) + off;
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            b[(size_t)k * V] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+            st16<NT>(&b[(size_t)k * V], make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
     } else {
         float m = 0.f;
 #pragma unroll
@@ -236,16 +275,16 @@ __device__ __forceinline__ void store_site(void *base, uint32_t V, int nrhs, uin
             d.y = pack2<P>(v[4 * k + 1].re * inv, v[4 * k + 1].im * inv);
             d.z = pack2<P>(v[4 * k + 2].re * inv, v[4 * k + 2].im * inv);
             d.w = pack2<P>(v[4 * k + 3].re * inv, v[4 * k + 3].im * inv);
-            b[(size_t)k * V] = d;
+            st16<NT>(&b[(size_t)k * V], d);
         }
         float *scp = const_cast<float *>(scale_ptr<P>(base, V, nrhs));
-        scp[(size_t)rhs * V + s] = m;
+        st4<NT>(&scp[(size_t)rhs * V + s], m);
     }
 }
 
 // Store a site and replace v by exactly what was stored (16-bit formats
 // quantise once: site maximum, scale, round to nearest even).
-template <int P>
+template <int P, bool NT = false>
 __device__ __forceinline__ void store_site_q(void *base, uint32_t V, int nrhs, uint32_t s, int rhs,
                                              cx<typename Traits<P>::real> (&v)[12])
 {
@@ -266,12 +305,12 @@ __device__ __forceinline__ void store_site_q(void *base, uint32_t V, int nrhs, u
                 const cx<float> q = unpack2<P>(w[j]);
                 v[4 * k + j] = cx<float>{q.re * m, q.im * m};
             }
-            b[(size_t)k * V] = make_uint4(w[0], w[1], w[2], w[3]);
+            st16<NT>(&b[(size_t)k * V], make_uint4(w[0], w[1], w[2], w[3]));
         }
         float *scp = const_cast<float *>(scale_ptr<P>(base, V, nrhs));
-        scp[(size_t)rhs * V + s] = m;
+        st4<NT>(&scp[(size_t)rhs * V + s], m);
     } else {
-        store_site<P>(base, V, nrhs, s, rhs, v);
+        store_site<P, NT>(base, V, nrhs, s, rhs, v);
     }
 }
 

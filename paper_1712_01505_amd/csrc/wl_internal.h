@@ -129,10 +129,11 @@ struct Scalars {
     double2 alpha, beta, omega, rho;
     double2 rho_prev;     // BiCGStab: rho before the last F_BI_RHO (for reliable updates)
     double tol2;          // converge when rr <= tol2 * bb
+    double rr_upd;        // reliable updates: |r|^2 after the previous update (or at the start)
     int flag;             // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
     int conv_iter;
     int frozen;           // set at the end of an iteration once flag != 0: loop kernels skip the column
-    int pad;
+    int restart;          // CGNR reliable update without progress: restart the search direction
 };
 
 enum BlasOp {
@@ -145,7 +146,8 @@ enum BlasOp {
     B_COPY = 6,       // y = x
     B_ZERO = 7,       // y = 0
     B_NORM = 8,       // |x|^2
-    B_DOT_NORM = 9    // <a0, a1> and |a1|^2  (3 values)
+    B_DOT_NORM = 9,   // <a0, a1> and |a1|^2  (3 values)
+    B_CG_RESTART = 10 // p = z for columns whose restart flag is set
 };
 struct BlasParams {
     void *y0;          // first output / in-out vector
@@ -174,8 +176,9 @@ enum FinOp {
     F_BI_OMEGA = 5,   // vals: |s|^2 (A), <s,t>, |t|^2 (B)
     F_BI_RHO = 6,     // vals: |r|^2, <rh, r> (A)
     F_SUM = 7,        // just reduce set A into out[] (nval x nrhs)
-    F_BI_RELIABLE = 8 // after a reliable update replaced r: A = (<rh, r>, |r|^2) -> rr,
-                      // convergence, rho and beta = (rho'/rho_prev)(alpha/omega)
+    F_BI_RELIABLE = 8, // after a reliable update replaced r: A = (<rh, r>, |r|^2) -> rr,
+                       // convergence, rho and beta = (rho'/rho_prev)(alpha/omega)
+    F_CG_RELIABLE = 9  // CGNR after a reliable update replaced r and z = D^dag r: A = |r|^2, B = |z|^2
 };
 struct FinParams {
     const double *A;

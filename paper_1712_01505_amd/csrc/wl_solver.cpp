@@ -12,6 +12,7 @@
 // or broken-down column is frozen by zeroing its coefficients on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -360,6 +361,8 @@ struct Engine {
                     return rc;
                 if ((rc = mark(it, &stop)))
                     return rc;
+                if (!stop && on_iter && (rc = on_iter(it)))
+                    return rc;
                 ++it;
             }
         } else {
@@ -529,14 +532,15 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
 // fixing one):
 //  * defect correction (reliable = 0): each cycle solves D e = r/|r| to the
 //    relative tolerance delta from e = 0, then x += |r| e;
-//  * reliable updates (reliable = 1, BiCGStab): one inner Krylov run is
-//    continued across cycles.  Whenever the iterated low-precision residual
-//    has fallen by delta below its largest value since the last update, the
-//    partial solution is folded into x (FP64), the residual is recomputed as
-//    b - D x in FP64 and replaces the iterated one, and rho, beta are
-//    re-derived from it (Sleijpen & van der Vorst's reliable updates).  The
-//    inner run then stops on the global tolerance; the outer loop confirms
-//    it with a last FP64 residual.  CGNR ignores the flag (defect correction).
+//  * reliable updates (reliable = 1): one inner Krylov run is continued
+//    across cycles.  Whenever the iterated low-precision residual has fallen
+//    by delta below its largest value since the last update, the partial
+//    solution is folded into x (FP64), the residual is recomputed as b - D x
+//    in FP64 and replaces the iterated one (Sleijpen & van der Vorst's
+//    reliable updates); BiCGStab re-derives rho and beta from it, CGNR
+//    recomputes z = D^dag r and its norm and keeps the search direction.
+//    The inner run then stops on the global tolerance; the outer loop
+//    confirms it with a last FP64 residual.
 int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
                 const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena)
 {
@@ -566,7 +570,11 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         if ((rc = H.blas(B_ZERO, x, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
             return rc;
     const double tol = prm->tol;
-    const bool reliable = prm->reliable && solver == WL_SOLVER_BICGSTAB;
+    // CG on the normal equations with 16-bit storage cannot keep its
+    // recurrence going between updates (measured: BF16 stalls, FP16 drifts
+    // into thousands of iterations or overflow); those pairs keep defect
+    // correction, which restarts the recurrence every cycle
+    const bool reliable = prm->reliable != 0 && !(solver == WL_SOLVER_CGNR && lo->prec != WL_F32);
     const double delta = prm->inner_tol > 0 ? prm->inner_tol
                          : reliable        ? 0.1
                          : lo->prec == WL_F32 ? 1e-5
@@ -575,7 +583,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     std::vector<int> iters(nrhs, 0);
     std::vector<double> best(nrhs, INFINITY), rmax(nrhs, 0.0);
     std::vector<int> stall(nrhs, 0);
-    int total = 0, outer = 0, updates = 0, worst_flag = 0, next_read = 0;
+    int total = 0, outer = 0, updates = 0, worst_flag = 0, next_read = 0, last_update = 0, last_gap = 0;
     bool stagnated = false;
     if (reliable) {
         // the inner run's stopping rule is the global one, in units of the
@@ -588,7 +596,12 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
                 return WL_OK;
             const volatile int *hf = lease.b->hflag;
             const volatile double *hr = lease.b->hrr;
-            bool need = false;
+            // update when the iterated residual has dropped by delta, and also
+            // when that has taken three times longer than the previous drop
+            // (at least 64 iterations): a low-precision recurrence can stall
+            // while the true residual drifts away
+            const int gap = std::max(64, 3 * last_gap);
+            bool need = it - last_update >= gap;
             for (int r = 0; r < nrhs; ++r) {
                 if (hf[r] != 0)
                     continue;
@@ -600,6 +613,8 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
             }
             if (!need)
                 return WL_OK;
+            last_gap = it - last_update;
+            last_update = it;
             int e;
             // x64 += sigma e ; e = 0 ; r64 = b - D64 x ; r_lo = r64 / sigma
             WL_TRY(launch_accum(lo->prec, hi->V, nrhs, x, e_lo, sig_dev, 1, st));
@@ -610,11 +625,23 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
             if ((e = H.blas(B_RES, H.v[0], nullptr, b, H.v[1], nullptr, nullptr, 0)))
                 return e;
             WL_TRY(launch_convert(WL_F64, lo->prec, hi->V, nrhs, H.v[0], L.v[0], sig_dev, 1, 2, st));
-            // rho = <rh, r>, |r|^2 of the replaced residual, then beta
-            if ((e = L.blas(B_DOT_NORM, nullptr, nullptr, L.v[1], L.v[0], nullptr, nullptr, 0)))
-                return e;
-            if ((e = L.fin(F_BI_RELIABLE, 0, -1, -1, it, 0.0)))
-                return e;
+            if (solver == WL_SOLVER_BICGSTAB) {
+                // rho = <rh, r>, |r|^2 of the replaced residual, then beta
+                if ((e = L.blas(B_DOT_NORM, nullptr, nullptr, L.v[1], L.v[0], nullptr, nullptr, 0)))
+                    return e;
+                if ((e = L.fin(F_BI_RELIABLE, 0, -1, -1, it, 0.0)))
+                    return e;
+            } else {
+                // |r|^2, then z = D^dag r with |z|^2; the search direction stays
+                if ((e = L.blas(B_NORM, nullptr, nullptr, L.v[0], nullptr, nullptr, nullptr, 0)))
+                    return e;
+                if ((e = L.stencil(L.v[1], L.v[0], 1, RED_NORM, nullptr, 1)))
+                    return e;
+                if ((e = L.fin(F_CG_RELIABLE, 0, 1, -1, it, 0.0)))
+                    return e;
+                if ((e = L.blas(B_CG_RESTART, L.v[2], nullptr, L.v[1], nullptr, nullptr, nullptr, -1)))
+                    return e;
+            }
             ++updates;
             // the status mirrored by iteration it + 1 onwards includes this
             // update; observations before that are skipped
@@ -656,6 +683,8 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         WL_TRY(launch_convert(WL_F64, lo->prec, hi->V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
         int done = 0;
         next_read = 0;
+        last_update = 0;
+        last_gap = 0;
         for (int r = 0; r < nrhs; ++r)
             rmax[r] = 0.0;
         if ((rc = L.run(e_lo, r_lo, true, delta, prm->maxiter - total, &done)))

@@ -562,7 +562,7 @@ __global__ __launch_bounds__(512) void twalk_kernel(StencilParams p, int T, uint
                 for (int i = 0; i < 12; ++i)
                     o[i] = acc[i];
             }
-            store_site_q<P>(p.out, p.V, p.nrhs, s, rhs, o);
+            store_site_q<P, true>(p.out, p.V, p.nrhs, s, rhs, o);
             if constexpr (RED == RED_NORM || RED == RED_DOTIN_NORM) {
 #pragma unroll
                 for (int i = 0; i < 12; ++i)
@@ -737,7 +737,7 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
                     o[k] = acc[r][k];
 
             }
-            store_site_q<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
+            store_site_q<P, true>(p.out, p.V, p.nrhs, s, r0 + r, o);
             if constexpr (RED == RED_NORM || RED == RED_DOTIN_NORM) {
                 double n2 = 0.0;
 #pragma unroll
@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void multi_item(const MultiEntry *E, int n, uint32_t 
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
-            store_site_q<P>(p.out, p.V, p.nrhs, s, r0 + r, o);
+            store_site_q<P, true>(p.out, p.V, p.nrhs, s, r0 + r, o);
         }
     }
 }

@@ -503,13 +503,13 @@ def dw_apply(U, psi, m0, m, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None)
 
 
 def dw_solve(U, b, m0, m, precision="f64", tol=1e-10, maxiter=20000, bc=(1, 1, 1, -1), inner_tol=0.0,
-             check_every=0, x0=None, ops=None, return_stats=False):
+             check_every=0, x0=None, ops=None, return_stats=False, reliable=False):
     """x = D_DW^{-1} b by CG on D_DW^dag D_DW (Sec. V-C) for a canonical 5-d
     complex128 CUDA tensor b (Ns, ...) or (nvec, Ns, ...).
 
     precision: "f64", "f32", or "mixed-f32" / "mixed-bf16" / "mixed-f16" (FP64
-    refinement around an inner CG with that storage).  ops: optional (hi, lo)
-    DWOperators to reuse."""
+    refinement around an inner CG with that storage; reliable: reliable
+    updates instead of restarts).  ops: optional (hi, lo) DWOperators to reuse."""
     torch = _torch()
     ns = int(b.shape[-7])
     if ops is not None:
@@ -524,7 +524,7 @@ def dw_solve(U, b, m0, m, precision="f64", tol=1e-10, maxiter=20000, bc=(1, 1, 1
     n = nvec or 1
     bp = hi.pack(b)
     xp = hi.pack(x0) if x0 is not None else hi.new_field(n)
-    prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=0,
+    prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=int(reliable),
                           check_every=check_every, use_x0=1 if x0 is not None else 0, dagger=0,
                           workspace=None, workspace_bytes=0)
     ws = wl_solver_workspace_bytes(hi.handle, lo.handle if lo else None, WL_SOLVER_CGNR, n)

@@ -105,12 +105,14 @@ def test_dw_apply_16x32_full_compare(W, oracle_mod):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("precision", ["f64", "mixed-f32", "mixed-f16"])
-def test_dw_cgnr_reaches_tolerance(W, oracle_mod, precision):
+@pytest.mark.parametrize("precision,reliable", [("f64", 0), ("mixed-f32", 0), ("mixed-f16", 0),
+                                                ("mixed-f32", 1), ("mixed-f16", 1)])  # f16 + reliable: defect correction
+def test_dw_cgnr_reaches_tolerance(W, oracle_mod, precision, reliable):
     dims, Ns = (8, 8, 8, 8), 8
     U = inputs.near_unity_gauge(dims, 0.3, seed=1)
     b = field5(dims, Ns, 0)
-    x, st = W.dw_solve(dev(U), dev(b), M0, MQ, precision=precision, tol=1e-10, return_stats=True)
+    x, st = W.dw_solve(dev(U), dev(b), M0, MQ, precision=precision, tol=1e-10, return_stats=True,
+                       reliable=bool(reliable))
     assert st["status"] == 0 and st["converged"], st
     x = x.cpu().numpy()
     r = rel(oracle_mod.dw_apply(U, x, M0, MQ), b)
