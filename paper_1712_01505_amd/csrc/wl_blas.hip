@@ -269,8 +269,8 @@ hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e,
 // flight per row, so a pass costs about one memory latency.
 constexpr int FIN_THREADS = 1024;
 constexpr int FIN_MAX = 3 * 64;  // values x right-hand sides per partial set
-constexpr int FIN_G = 2;         // rows summed per pass
-constexpr int FIN_U = 16;        // independent loads per thread per row and pass
+constexpr int FIN_G = 4;         // rows summed per pass (one pass for the usual 1..4 rows)
+constexpr int FIN_U = 8;         // independent loads per thread per row and pass
 
 __device__ __forceinline__ bool finite2(double a) { return isfinite(a); }
 

@@ -259,8 +259,11 @@ struct Engine {
         }
         p.sc = sc;
         p.out = sums;
-        p.hflag = hb->dflag;
-        p.hrr = hb->drr;
+        // the host reads the status at iteration ends only: the mid-iteration
+        // steps skip the (PCIe) mirror writes
+        const bool mid = fop == F_CG_ALPHA || fop == F_BI_ALPHA || fop == F_BI_OMEGA;
+        p.hflag = mid ? nullptr : hb->dflag;
+        p.hrr = mid ? nullptr : hb->drr;
         p.nrhs = nrhs;
         p.iter = iter;
         p.tol2 = tol2;
