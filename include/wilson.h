@@ -121,6 +121,23 @@ int wilson_dslash(const wl_op *op, void *out, const void *in, int dagger, int nr
  * (paper Table I).  Same buffer rules as wilson_dslash.  Async. */
 int wilson_apply(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *stream);
 
+/* ---- Enforced halo (Sec. IV: single-node runs with the boundary copy
+ * enforced) ----
+ * out = D in (dagger: D^dag in) computed as one rank of a lattice decomposed
+ * in t whose neighbours are itself: the projected half-spinors of the two t
+ * faces are packed into buffers (12 reals per face site; the t = Lt-1 face
+ * already multiplied by its link) and copied device to device on a library
+ * stream while the caller's stream runs the interior stencil with the
+ * wrapping t hops left out; a last kernel on the caller's stream adds the
+ * received faces to the t = 0 and t = Lt-1 slices.  The result equals
+ * wilson_apply's up to the order of the additions.  halo: device buffer of
+ * wl_halo_bytes (send and receive regions; FP64 ops use double, the others
+ * float), owned by the caller and not used concurrently by two calls.
+ * Wilson ops only.  Async with respect to the host. */
+int wl_halo_bytes(const wl_op *op, int nrhs, size_t *out_bytes);
+int wilson_apply_halo(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *halo,
+                      size_t halo_bytes, void *stream);
+
 /* ---- Domain-wall operator (Sec. II-B, eq. (2)) ----
  * D_DW acts on 5-d fields: Ns four-dimensional spinors psi_0 .. psi_{Ns-1}
  * sharing the links.  In packed form a 5-d field is Ns consecutive

@@ -517,6 +517,63 @@ static int stencil_call(const wl_op *op, void *out, const void *in, int dagger, 
     return WL_OK;
 }
 
+// Enforced halo: a library stream (default priority) carries the face pack
+// and copy beside the caller's stream, which runs the interior.
+static std::mutex g_halo_mu;
+static hipStream_t g_halo_stream = nullptr;
+static hipEvent_t g_halo_ev[2] = {nullptr, nullptr};
+
+int wl_halo_bytes(const wl_op *op, int nrhs, size_t *out_bytes)
+{
+    if (!op || op->ns > 0 || nrhs < 1 || nrhs > 65535 || !out_bytes)
+        return WL_EINVAL;
+    const uint32_t vs = (uint32_t)op->g.dims[0] * op->g.dims[1] * op->g.dims[2];
+    *out_bytes = 4 * halo_face_bytes(op->prec, vs, nrhs);  // send and receive, two faces each
+    return WL_OK;
+}
+
+int wilson_apply_halo(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *halo,
+                      size_t halo_bytes, void *stream)
+{
+    size_t need = 0;
+    if (!op || !out || !in || !halo || out == in || (dagger != 0 && dagger != 1) ||
+        wl_halo_bytes(op, nrhs, &need) != WL_OK)
+        return WL_EINVAL;
+    if (halo_bytes < need)
+        return WL_EWORKSPACE;
+    if (!al16(out) || !al16(in) || !al16(halo))
+        return WL_EALIGN;
+    LaunchCfg cfg = launch_for(op, nrhs, RED_NONE);
+    if (cfg.rpt == 1 && cfg.var >= 4) {  // the t-walk keeps its t hops in registers: use the hop loop
+        cfg.var = op->prec == WL_F64 ? 1 : 2;
+        cfg.xcd = cfg.xcd ? 1 : 0;
+    }
+    StencilParams p = base_params(op, out, in, nrhs, 1);
+    p.halo_t = 1;
+    p.halo_send = halo;
+    p.halo_recv = (char *)halo + need / 2;
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_halo_mu);
+    if (!g_halo_stream) {
+        CHECK_HIP(hipStreamCreateWithFlags(&g_halo_stream, hipStreamNonBlocking));
+        CHECK_HIP(hipEventCreateWithFlags(&g_halo_ev[0], hipEventDisableTiming));
+        CHECK_HIP(hipEventCreateWithFlags(&g_halo_ev[1], hipEventDisableTiming));
+    }
+    // faces: pack and copy on the side stream once the caller's prior work is done
+    CHECK_HIP(hipEventRecord(g_halo_ev[0], st));
+    CHECK_HIP(hipStreamWaitEvent(g_halo_stream, g_halo_ev[0], 0));
+    CHECK_HIP(launch_halo_pack(op->prec, dagger, p, g_halo_stream));
+    CHECK_HIP(hipMemcpyAsync(const_cast<void *>(p.halo_recv), p.halo_send, need / 2, hipMemcpyDeviceToDevice,
+                             g_halo_stream));
+    CHECK_HIP(hipEventRecord(g_halo_ev[1], g_halo_stream));
+    // interior (every site, wrapping t hops cut) on the caller's stream meanwhile
+    CHECK_HIP(prof_stencil(op->prec, op, dagger, cfg, p, st));
+    // then the received faces into the boundary slices
+    CHECK_HIP(hipStreamWaitEvent(st, g_halo_ev[1], 0));
+    CHECK_HIP(launch_halo_finish(op->prec, dagger, p, st));
+    return WL_OK;
+}
+
 int dwf_apply(const wl_op *op, void *out, const void *in, int dagger, int nvec, void *stream)
 {
     if (!op || op->ns < 1 || nvec < 1 || (long)nvec * op->ns > 65535)

@@ -80,10 +80,20 @@ struct StencilParams {
     SlabOrder slab;  // xcd >= 2
     const struct Scalars *skip;  // in a solver loop: skip a workgroup whose columns are all frozen
     float one;                   // 1.0 (see project())
+    // enforced halo: the t hops that wrap around the lattice are left out
+    // here (halo_t = 1) and come from face buffers (halo_pack / halo_finish)
+    int halo_t;
+    void *halo_send;             // [face 2][rhs][6 complex][Vs], real = double (FP64) or float
+    const void *halo_recv;       // same layout, filled by the face copy
 };
 
 // ---- stencil (wl_stencil.hip)
 hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st);
+// enforced halo: pack the two t faces' projected half-spinors, and add the
+// received faces' hops to the boundary slices
+hipError_t launch_halo_pack(int prec, int dagger, const StencilParams &p, hipStream_t st);
+hipError_t launch_halo_finish(int prec, int dagger, const StencilParams &p, hipStream_t st);
+size_t halo_face_bytes(int prec, uint32_t vs, int nrhs);  // one face, all right-hand sides
 int stencil_nval(int red);
 int max_rpt(int prec);  // largest right-hand sides per thread the stencil offers
 int max_var(int prec);  // largest stencil code variant for R = 1

@@ -19,6 +19,8 @@
 //   * the antiperiodic boundary sign multiplies the hop (never the link,
 //     since -U has det -1 and would rebuild a wrong third row);
 //   * XCD-aware tile order and fused reductions for the solvers.
+#include <type_traits>
+
 #include "wl_internal.h"
 
 namespace wl {
@@ -119,8 +121,10 @@ __device__ __forceinline__ void hop_dir(const StencilParams &p, uint32_t s, int 
     const uint32_t sf = wf ? s - span : s + stride;
     const uint32_t sb = wb ? s + span : s - stride;
     const bool anti = p.bc[MU] < 0;
-    const T gf = (wf && anti) ? T(-1) : T(1);
-    const T gb = (wb && anti) ? T(-1) : T(1);
+    // an enforced halo takes the t hops that wrap out of the face buffers
+    const bool cut = MU == 3 && p.halo_t;
+    const T gf = (wf && cut) ? T(0) : (wf && anti) ? T(-1) : T(1);
+    const T gb = (wb && cut) ? T(0) : (wb && anti) ? T(-1) : T(1);
     cx<T> u[9];
     load_link<P>(p.U, p.V, MU, s, u);
 #pragma unroll
@@ -222,8 +226,9 @@ __device__ __forceinline__ void make_hops(const StencilParams &p, uint32_t s, Ho
         h.nb[2 * mu] = wf ? s - span : s + stride;
         h.nb[2 * mu + 1] = wb ? s + span : s - stride;
         const bool anti = p.bc[mu] < 0;
-        h.sg[2 * mu] = (wf && anti) ? -1.f : 1.f;
-        h.sg[2 * mu + 1] = (wb && anti) ? -1.f : 1.f;
+        const bool cut = mu == 3 && p.halo_t;  // enforced halo: face buffers carry these hops
+        h.sg[2 * mu] = (wf && cut) ? 0.f : (wf && anti) ? -1.f : 1.f;
+        h.sg[2 * mu + 1] = (wb && cut) ? 0.f : (wb && anti) ? -1.f : 1.f;
         stride *= (uint32_t)L;
     }
 }
@@ -940,6 +945,8 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
         return hipErrorInvalidValue;
     if (p.apply == 2 && (cfg.rpt != 1 || cfg.var > 2 || p.ns < 1 || p.nrhs % p.ns != 0))
         return hipErrorInvalidValue;  // domain wall: one slice per thread, variants 0..2
+    if (p.halo_t && cfg.rpt == 1 && cfg.var >= 4)
+        return hipErrorInvalidValue;  // the t-walk carries its t hops in registers
     p.lanes_lg = lg;
     const int tile = cfg.block >> lg;
     p.nblk = (int)((p.V + tile - 1) / tile);
@@ -1167,6 +1174,137 @@ hipError_t launch_multi(int prec, int dagger, int rpt, int block, int var, const
     }
     void *args[] = {(void *)&E, (void *)&n, (void *)&total};
     return hipLaunchKernel(fn, dim3(total), dim3(block), args, 0, st);
+}
+
+// ---------------------------------------------------------------- enforced halo
+// The paper's single-node mode with the boundary copy enforced (Sec. IV): the
+// lattice is treated as one rank of a t-decomposition whose neighbours are
+// itself.  halo_pack writes, per face site j (Vs = Lx Ly Lz sites per slice),
+//   face 0: the projected half-spinor of the t = 0 slice that the forward t
+//           hop of t = Lt-1 needs (the receiver multiplies by its link), and
+//   face 1: U_t^dag times the projected half-spinor of the t = Lt-1 slice, the
+//           whole backward t hop of t = 0 (the sender owns that link);
+// a device copy moves them to the receive buffer (on several GPUs: the
+// exchange with the t neighbours), and halo_finish adds the received hops to
+// the boundary slices of an output the stencil computed with those hops cut.
+template <int P>
+using HaloReal = typename std::conditional<P == F64, double, float>::type;
+
+size_t halo_face_bytes(int prec, uint32_t vs, int nrhs)
+{
+    const size_t real = prec == F64 ? 8 : 4;
+    return (size_t)nrhs * 12 * vs * real;
+}
+
+template <int P, int DAG>
+__global__ __launch_bounds__(256) void halo_pack_kernel(StencilParams p)
+{
+    using T = typename Traits<P>::real;
+    using H = HaloReal<P>;
+    constexpr int SF = DAG ? 1 : -1;
+    const uint32_t vs = (uint32_t)p.L[0] * p.L[1] * p.L[2];
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int face = blockIdx.y, rhs = blockIdx.z;
+    if (j >= vs)
+        return;
+    const uint32_t s = face == 0 ? j : j + (uint32_t)(p.L[3] - 1) * vs;
+    cx<T> ps[12], h[6], g[6];
+    load_site<P>(p.in, p.V, p.nrhs, s, rhs, ps);
+    if (face == 0) {
+        project<3, SF>(ps, h, (T)1);  // the forward t hop's projection
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            g[k] = h[k];
+    } else {
+        project<3, -SF>(ps, h, (T)1);  // the backward t hop: U_t(s)^dag (projected)
+        cx<T> u[9];
+        load_link<P>(p.U, p.V, 3, s, u);
+        su3_adj_mv(u, h, g);
+    }
+    H *b = reinterpret_cast<H *>(p.halo_send) + ((size_t)(face * p.nrhs + rhs) * 12) * vs;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        b[(size_t)(2 * k) * vs + j] = (H)g[k].re;
+        b[(size_t)(2 * k + 1) * vs + j] = (H)g[k].im;
+    }
+}
+
+template <int P, int DAG>
+__global__ __launch_bounds__(256) void halo_finish_kernel(StencilParams p)
+{
+    using T = typename Traits<P>::real;
+    using H = HaloReal<P>;
+    constexpr int SF = DAG ? 1 : -1;
+    const uint32_t vs = (uint32_t)p.L[0] * p.L[1] * p.L[2];
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int face = blockIdx.y, rhs = blockIdx.z;
+    if (j >= vs)
+        return;
+    const H *b = reinterpret_cast<const H *>(p.halo_recv) + ((size_t)(face * p.nrhs + rhs) * 12) * vs;
+    cx<T> h[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        h[k] = cx<T>{(T)b[(size_t)(2 * k) * vs + j], (T)b[(size_t)(2 * k + 1) * vs + j]};
+    const T sg = p.bc[3] < 0 ? T(-1) : T(1);  // both faces' hops wrap around the lattice
+    cx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        acc[k] = cx<T>{T(0), T(0)};
+    uint32_t s;
+    if (face == 0) {  // received t = 0 half-spinors: the forward hop of t = Lt-1
+        s = j + (uint32_t)(p.L[3] - 1) * vs;
+        cx<T> u[9], g[6];
+        load_link<P>(p.U, p.V, 3, s, u);
+        su3_mv(u, h, g);
+        accum<3, SF>(acc, g, sg);
+    } else {  // received backward hops into t = 0
+        s = j;
+        accum<3, -SF>(acc, h, sg);
+    }
+    cx<T> o[12];
+    load_site<P>(p.out, p.V, p.nrhs, s, rhs, o);
+    const T c = p.apply ? -(T)p.kappa : T(1);  // D: out = in - kappa H in;  H alone: out = H in
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        o[k] = cx<T>{fma(c, acc[k].re, o[k].re), fma(c, acc[k].im, o[k].im)};
+    store_site_q<P>(p.out, p.V, p.nrhs, s, rhs, o);
+}
+
+template <int DAG>
+static hipError_t halo_launch(int prec, bool finish, const StencilParams &p, hipStream_t st)
+{
+    const uint32_t vs = (uint32_t)p.L[0] * p.L[1] * p.L[2];
+    dim3 g((vs + 255) / 256, 2, p.nrhs), b(256);
+    switch (prec) {
+    case F64:
+        if (finish) hipLaunchKernelGGL((halo_finish_kernel<F64, DAG>), g, b, 0, st, p);
+        else hipLaunchKernelGGL((halo_pack_kernel<F64, DAG>), g, b, 0, st, p);
+        break;
+    case F32:
+        if (finish) hipLaunchKernelGGL((halo_finish_kernel<F32, DAG>), g, b, 0, st, p);
+        else hipLaunchKernelGGL((halo_pack_kernel<F32, DAG>), g, b, 0, st, p);
+        break;
+    case BF16S:
+        if (finish) hipLaunchKernelGGL((halo_finish_kernel<BF16S, DAG>), g, b, 0, st, p);
+        else hipLaunchKernelGGL((halo_pack_kernel<BF16S, DAG>), g, b, 0, st, p);
+        break;
+    case F16S:
+        if (finish) hipLaunchKernelGGL((halo_finish_kernel<F16S, DAG>), g, b, 0, st, p);
+        else hipLaunchKernelGGL((halo_pack_kernel<F16S, DAG>), g, b, 0, st, p);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_halo_pack(int prec, int dagger, const StencilParams &p, hipStream_t st)
+{
+    return dagger ? halo_launch<1>(prec, false, p, st) : halo_launch<0>(prec, false, p, st);
+}
+
+hipError_t launch_halo_finish(int prec, int dagger, const StencilParams &p, hipStream_t st)
+{
+    return dagger ? halo_launch<1>(prec, true, p, st) : halo_launch<0>(prec, true, p, st);
 }
 
 // ---------------------------------------------------------------- link force

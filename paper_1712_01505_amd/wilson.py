@@ -37,7 +37,7 @@ EXPORTS = [
     "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read",
     "wl_stream_copy", "wl_strerror", "wl_last_hip_error", "wl_multi_plan_create", "wl_multi_plan_run",
     "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
-    "wl_dw_op_create", "dwf_apply",
+    "wl_dw_op_create", "dwf_apply", "wl_halo_bytes", "wilson_apply_halo",
 ]
 
 
@@ -103,6 +103,8 @@ def lib():
         "wl_op_destroy": [P],
         "wl_dw_op_create": [G, D, D, I, I, P, ctypes.POINTER(P)],
         "dwf_apply": [P, P, P, I, I, P],
+        "wl_halo_bytes": [P, I, ctypes.POINTER(SZ)],
+        "wilson_apply_halo": [P, P, P, I, I, P, SZ, P],
         "wilson_dslash": [P, P, P, I, I, P],
         "wilson_apply": [P, P, P, I, I, P],
         "wl_solver_workspace_bytes": [P, P, I, I, ctypes.POINTER(SZ)],
@@ -417,6 +419,16 @@ class Operator:
 
     def dslash_packed(self, out, inp, nrhs=1, dagger=False):
         wilson_dslash(self.handle, _ptr(out), _ptr(inp), dagger, nrhs, _stream())
+
+    def halo_buffer(self, nrhs=1):
+        n = ctypes.c_size_t(0)
+        _check(lib().wl_halo_bytes(self.handle, int(nrhs), ctypes.byref(n)), "wl_halo_bytes")
+        return _torch().empty(max(n.value, 16), dtype=_torch().uint8, device=self.U_packed.device)
+
+    def apply_halo_packed(self, out, inp, halo, nrhs=1, dagger=False):
+        """D in through the enforced-halo path (face pack, copy, interior, finish)."""
+        _check(lib().wilson_apply_halo(self.handle, _ptr(out), _ptr(inp), int(bool(dagger)), int(nrhs), _ptr(halo),
+                                       halo.numel(), _stream()), "wilson_apply_halo")
 
 
 @dataclass

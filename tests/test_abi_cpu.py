@@ -105,6 +105,12 @@ def test_bad_arguments_rejected_before_launch():
         assert L.solve_cgnr(op, op, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EPREC
         assert L.solve_cgnr(op, None, 512, 1024, 65, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
         assert L.wilson_gauge_force(op, 512, 1024, 2048, 3, None) == wilson.WL_EINVAL
+        hb = ctypes.c_size_t(0)
+        assert L.wl_halo_bytes(op, 2, ctypes.byref(hb)) == wilson.WL_OK
+        assert hb.value == 4 * 2 * 12 * 4 * 4 * 4 * 8  # send + receive, 2 faces, 2 RHS, 12 doubles per face site
+        assert L.wilson_apply_halo(op, 512, 1024, 0, 2, None, hb.value, None) == wilson.WL_EINVAL
+        assert L.wilson_apply_halo(op, 512, 1024, 0, 2, 4096, hb.value - 16, None) == wilson.WL_EWORKSPACE
+        assert L.wilson_apply_halo(op, 512, 1024, 0, 2, 4104, hb.value, None) == wilson.WL_EALIGN
         plan = ctypes.c_void_p()
         d = (wilson.wl_multi_desc * 2)(wilson.wl_multi_desc(op, 512, 1024), wilson.wl_multi_desc(op, 2048, 2048))
         assert L.wl_multi_plan_create(d, 2, 0, 1, ctypes.byref(plan)) == wilson.WL_EINVAL  # out == in
@@ -135,6 +141,8 @@ def test_bad_arguments_rejected_before_launch():
         assert L.wl_set_launch(dw, 1, ctypes.byref(c)) == wilson.WL_EINVAL  # FP64 offers variants 0, 1
         c = wilson.wl_launch(block=512, rhs_per_thread=1, rhs_lanes=8, xcd_remap=0, variant=1)
         assert L.wl_set_launch(dw, 1, ctypes.byref(c)) == wilson.WL_OK
+        n = ctypes.c_size_t(0)
+        assert L.wl_halo_bytes(dw, 1, ctypes.byref(n)) == wilson.WL_EINVAL  # Wilson ops only
     finally:
         L.wl_op_destroy(dw)
     for c in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):
