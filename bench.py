@@ -165,6 +165,39 @@ def bench_batching(W, inputs, torch, log):
     return out
 
 
+def bench_halo(W, inputs, torch, log):
+    """Enforced-halo apply (t faces through buffers on a side stream, interior
+    meanwhile, boundary finish) against the plain apply, FP32 and FP64, at the
+    paper's 16^3 x 32 and 32^3 x 64 Wilson lattices."""
+    out = {}
+    for dims in ((16, 16, 16, 32), (32, 32, 32, 64)):
+        V = inputs.volume(dims)
+        Ud = torch.from_numpy(inputs.near_unity_gauge(dims, 0.3, seed=inputs.GAUGE_SEED)).cuda()
+        src = torch.from_numpy(inputs.gaussian_spinor(dims, seed=inputs.SOURCE_SEED)).cuda()
+        res = {}
+        for p in (0, 1):
+            op = W.Operator.create(Ud, 0.1255, p)
+            W.wl_autotune(op.handle, 1, 0, W._stream())
+            a = op.pack(src)
+            b = op.new_field()
+            halo = op.halo_buffer()
+            ms_plain = _time_ms(torch, lambda: op.apply_packed(b, a), 20)
+            ms_halo = _time_ms(torch, lambda: op.apply_halo_packed(b, a, halo), 20)
+            res[PNAME[p]] = {"plain_us": round(ms_plain * 1e3, 1), "halo_us": round(ms_halo * 1e3, 1),
+                             "halo_GFLOP/s": round(FLOP_APPLY * V / (ms_halo * 1e-3) / 1e9, 1),
+                             "overhead": round(ms_halo / ms_plain - 1.0, 3),
+                             "face_bytes": int(halo.numel() // 2)}
+            log(f"[bench] halo apply {dims} {PNAME[p]}: {res[PNAME[p]]}")
+            del op, a, b, halo
+        out["%dx%dx%dx%d" % dims] = res
+        del Ud, src
+        torch.cuda.empty_cache()
+    out["paper_knl_context"] = {"wilson_copy_enforced_GFLOPs_16x16x16x32": 100.4,
+                                "wilson_copy_enforced_GFLOPs_32x32x32x64": 176.0,
+                                "note": "single KNL node, single precision, boundary copy enforced (context only)"}
+    return out
+
+
 DW_FLOP_PER_5D_SITE = 11520 // 8  # Table I: 11520 flop per 4-d site at Ns = 8
 
 
@@ -432,6 +465,7 @@ def main():
         result["batching"] = bench_batching(W, inputs, torch, log)
         result["differentiable"] = bench_autograd(W, inputs, torch, log)
         result["domain_wall"] = bench_dwf(W, inputs, torch, log)
+        result["enforced_halo"] = bench_halo(W, inputs, torch, log)
 
     if not args.no_cpu:
         import oracle
