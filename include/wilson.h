@@ -138,6 +138,23 @@ int wl_halo_bytes(const wl_op *op, int nrhs, size_t *out_bytes);
 int wilson_apply_halo(const wl_op *op, void *out, const void *in, int dagger, int nrhs, void *halo,
                       size_t halo_bytes, void *stream);
 
+/* ---- Even-odd (red-black) decomposition ----
+ * Sites of even and odd parity of x + y + z + t; the hopping term couples
+ * only opposite parities, D = [[1, -kappa H_eo], [-kappa H_oe, 1]].  A half
+ * field holds the V/2 sites of one parity in the packed spinor format with
+ * V/2 in place of V (wl_field_bytes / 2 bytes); site s of parity p sits at
+ * half index s / 2.  Needs every extent even (a hop wrapping around an odd
+ * extent keeps the parity); WL_EINVAL otherwise.
+ * wl_eo_split / wl_eo_merge: full packed field <-> its two halves (bit-exact
+ * copies).  wilson_schur_apply: out_e = M in_e with the Schur complement
+ * M = 1 - kappa^2 H_eo H_oe (dagger: M^dag = 1 - kappa^2 H'_eo H'_oe with
+ * the adjoint hops); tmp_o is a caller half field receiving H_oe in_e.
+ * Wilson ops only; async. */
+int wl_eo_split(const wl_geom *g, int prec, int nrhs, const void *full, void *even, void *odd, void *stream);
+int wl_eo_merge(const wl_geom *g, int prec, int nrhs, const void *even, const void *odd, void *full, void *stream);
+int wilson_schur_apply(const wl_op *op, void *out_e, const void *in_e, void *tmp_o, int dagger, int nrhs,
+                       void *stream);
+
 /* ---- Domain-wall operator (Sec. II-B, eq. (2)) ----
  * D_DW acts on 5-d fields: Ns four-dimensional spinors psi_0 .. psi_{Ns-1}
  * sharing the links.  In packed form a 5-d field is Ns consecutive
@@ -181,6 +198,11 @@ typedef struct {
     int dagger;           /* 1 = solve D^dag x = b (the adjoint system; D^dag = gamma5 D gamma5) */
     void *workspace;      /* device scratch, NULL = library allocates for the call */
     size_t workspace_bytes;
+    int eo;               /* 1 = even-odd preconditioned: solve the Schur system
+                             (1 - kappa^2 H_eo H_oe) x_e = b_e + kappa H_eo b_o on the even
+                             sites, then x_o = b_o + kappa H_oe x_e; Wilson ops with every
+                             extent even.  x, b stay full packed fields; tol applies to
+                             the full system, whose residual is recomputed at the end. */
 } wl_solve_params;
 
 typedef struct {

@@ -574,6 +574,62 @@ int wilson_apply_halo(const wl_op *op, void *out, const void *in, int dagger, in
     return WL_OK;
 }
 
+// ---------------------------------------------------------------- even-odd
+// the hopping term couples only opposite parities when every extent is even
+static bool eo_geom_ok(const wl_geom *g)
+{
+    return geom_ok(g) && g->dims[0] % 2 == 0 && g->dims[1] % 2 == 0 && g->dims[2] % 2 == 0 && g->dims[3] % 2 == 0;
+}
+
+int wl_eo_split(const wl_geom *g, int prec, int nrhs, const void *full, void *even, void *odd, void *stream)
+{
+    if (!eo_geom_ok(g) || !full || !even || !odd || nrhs < 1 || nrhs > 65535 || even == odd)
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    if (!al16(full) || !al16(even) || !al16(odd))
+        return WL_EALIGN;
+    CHECK_HIP(launch_eo_copy(prec, true, g->dims, nrhs, full, nullptr, even, odd, (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wl_eo_merge(const wl_geom *g, int prec, int nrhs, const void *even, const void *odd, void *full, void *stream)
+{
+    if (!eo_geom_ok(g) || !full || !even || !odd || nrhs < 1 || nrhs > 65535 || even == odd)
+        return WL_EINVAL;
+    if (!prec_ok(prec))
+        return WL_EPREC;
+    if (!al16(full) || !al16(even) || !al16(odd))
+        return WL_EALIGN;
+    CHECK_HIP(launch_eo_copy(prec, false, g->dims, nrhs, nullptr, full, const_cast<void *>(even),
+                             const_cast<void *>(odd), (hipStream_t)stream));
+    return WL_OK;
+}
+
+int wilson_schur_apply(const wl_op *op, void *out_e, const void *in_e, void *tmp_o, int dagger, int nrhs,
+                       void *stream)
+{
+    if (!op || op->ns > 0 || !eo_geom_ok(&op->g) || !out_e || !in_e || !tmp_o || out_e == in_e ||
+        tmp_o == in_e || tmp_o == out_e || nrhs < 1 || nrhs > 65535 || (dagger != 0 && dagger != 1))
+        return WL_EINVAL;
+    if (!al16(out_e) || !al16(in_e) || !al16(tmp_o))
+        return WL_EALIGN;
+    hipStream_t st = (hipStream_t)stream;
+    EoParams a = eo_params(op, 1, nrhs);  // tmp_o = H_oe in_e
+    a.in = in_e;
+    a.out = tmp_o;
+    a.c_hop = 1.0;
+    CHECK_HIP(launch_eo_hop(op->prec, dagger, RED_NONE, a, st));
+    EoParams b = eo_params(op, 0, nrhs);  // out_e = in_e - kappa^2 H_eo tmp_o
+    b.in = tmp_o;
+    b.self = in_e;
+    b.out = out_e;
+    b.c_self = 1.0;
+    b.c_hop = -op->kappa * op->kappa;
+    CHECK_HIP(launch_eo_hop(op->prec, dagger, RED_NONE, b, st));
+    return WL_OK;
+}
+
 int dwf_apply(const wl_op *op, void *out, const void *in, int dagger, int nvec, void *stream)
 {
     if (!op || op->ns < 1 || nvec < 1 || (long)nvec * op->ns > 65535)

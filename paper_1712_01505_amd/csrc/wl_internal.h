@@ -87,6 +87,29 @@ struct StencilParams {
     const void *halo_recv;       // same layout, filled by the face copy
 };
 
+// ---- even-odd (wl_eo.hip)
+struct EoParams {
+    const void *U;
+    const void *in;      // half field of the other parity
+    const void *self;    // half field of the output parity (c_self term, <self, out>), or null
+    const void *dotv;    // RED_DOTV: the v of <v, out>
+    void *out;           // half field of the output parity
+    double *partials;
+    const struct Scalars *skip;
+    int L[4], bc[4];
+    int parity;          // of the output sites
+    int nrhs;
+    double c_self, c_hop;  // out = c_self self + c_hop H in
+    uint32_t V, Vh;      // set by the launcher
+    FastDiv fxh, fy, fz;
+    int nblk;
+};
+hipError_t launch_eo_hop(int prec, int dagger, int red, EoParams p, hipStream_t st);
+hipError_t launch_eo_copy(int prec, bool split, const int *L, int nrhs, const void *full_in, void *full_out,
+                          void *even, void *odd, hipStream_t st);
+int eo_partials(uint32_t Vh);  // per-right-hand-side partials of one eo_hop launch
+EoParams eo_params(const wl_op *op, int parity, int nrhs);  // links, extents, parity
+
 // ---- stencil (wl_stencil.hip)
 hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st);
 // enforced halo: pack the two t faces' projected half-spinors, and add the

@@ -154,19 +154,24 @@ struct Engine {
     int adj = 0;  // solving with D^dag: every stencil's dagger flag is flipped
     int stencil_calls = 0;
     int group = 1;  // columns per linear system (domain wall: the fifth-dimension extent)
+    bool eo = false;       // even-odd: vectors are even half fields, the operator is the Schur complement
+    void *eo_tmp = nullptr;  // odd half field for H_oe in
     const double *tol2v = nullptr;  // optional per-column tolerance^2 (device)
     // Called after each queued BiCGStab iteration that did not stop the run
     // (the reliable-update check of the mixed solver).
     std::function<int(int)> on_iter;
 
-    int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, HostBufs *h)
+    int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, HostBufs *h, bool even_odd = false)
     {
         op = o;
         solver = solv;
         nrhs = n;
         prec = o->prec;
         group = o->ns > 0 ? o->ns : 1;
-        V = o->V;
+        eo = even_odd;
+        V = eo ? o->V / 2 : o->V;
+        if (eo && !(eo_tmp = a.take(vec_bytes(prec, V, nrhs))))
+            return WL_EWORKSPACE;
         st = s;
         hb = h;
         sc_host = h->sc;
@@ -186,6 +191,30 @@ struct Engine {
 
     int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot, bool loop = false)
     {
+        if (eo) {  // out = (1 - kappa^2 H_eo H_oe) in on even half fields
+            EoParams a = eo_params(op, 1, nrhs);
+            a.in = in;
+            a.out = eo_tmp;
+            a.c_hop = 1.0;
+            a.skip = loop ? sc : nullptr;
+            WL_TRY(launch_eo_hop(prec, dagger ^ adj, RED_NONE, a, st));
+            EoParams b = eo_params(op, 0, nrhs);
+            b.in = eo_tmp;
+            b.self = in;
+            b.dotv = aux;
+            b.out = out;
+            b.c_self = 1.0;
+            b.c_hop = -op->kappa * op->kappa;
+            b.skip = loop ? sc : nullptr;
+            b.partials = slot >= 0 ? part[slot] : nullptr;
+            if (slot >= 0) {
+                nblk[slot] = eo_partials(V);
+                nval[slot] = stencil_nval(red);
+            }
+            ++stencil_calls;
+            WL_TRY(launch_eo_hop(prec, dagger ^ adj, red, b, st));
+            return WL_OK;
+        }
         StencilParams p{};
         p.skip = loop ? sc : nullptr;
         p.U = op->U;
@@ -467,15 +496,29 @@ int status_of(const wl_solve_stats &s, int flag)
 
 // Plain solve in the op's own precision.
 int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, const wl_solve_params *prm,
-                wl_solve_stats *stats, hipStream_t st, Arena &arena)
+                wl_solve_stats *stats, hipStream_t st, Arena &arena, bool eo = false, const double *tolc = nullptr)
 {
     HostLease lease;
     if (!lease.b->ok)
         return WL_EHIP;
     Engine E{};
-    int rc = E.init(arena, op, solver, nrhs, st, lease.b);
+    int rc = E.init(arena, op, solver, nrhs, st, lease.b, eo);
     if (rc)
         return rc;
+    // per-column tolerance (even-odd: scaled to the Schur right-hand side)
+    std::vector<double> tol(nrhs, prm->tol);
+    if (tolc) {
+        double *t2d = (double *)arena.take(sizeof(double) * nrhs);
+        if (!t2d)
+            return WL_EWORKSPACE;
+        double *t2h = lease.b->d + 3 * nrhs;
+        for (int r = 0; r < nrhs; ++r) {
+            tol[r] = tolc[r];
+            t2h[r] = tolc[r] * tolc[r];
+        }
+        WL_TRY(hipMemcpyAsync(t2d, t2h, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+        E.tol2v = t2d;
+    }
     E.adj = prm->dagger;
     E.lookahead = lookahead_of(prm);
     double *bb = lease.b->d, *rr = lease.b->d + nrhs;
@@ -505,7 +548,7 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
         for (int r = 0; r < nrhs; ++r) {
             if (!std::isfinite(rr[r]))
                 return WL_ENAN;
-            if (!(rr[r] <= prm->tol * prm->tol * bb[r]))
+            if (!(rr[r] <= tol[r] * tol[r] * bb[r]))
                 all_ok = false;
         }
         if (all_ok)
@@ -520,7 +563,7 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
         s.stencil_calls = E.stencil_calls;
         s.true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
         s.iter_rel_res = itres[r];
-        s.converged = s.true_rel_res <= prm->tol;
+        s.converged = s.true_rel_res <= tol[r];
         const int code = status_of(s, flags[r]);
         if (code > worst)
             worst = code;
@@ -545,7 +588,8 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
 //    The inner run then stops on the global tolerance; the outer loop
 //    confirms it with a last FP64 residual.
 int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
-                const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena)
+                const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena, bool eo = false,
+                const double *tolc = nullptr)
 {
     HostLease lease;
     if (!lease.b->ok)
@@ -554,13 +598,13 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     int rc;
     // the outer engine only needs r, w and the partial/scalar buffers; it is
     // initialised as a CGNR engine (4 vectors) for simplicity of layout
-    if ((rc = H.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, lease.b)))
+    if ((rc = H.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, lease.b, eo)))
         return rc;
-    if ((rc = L.init(arena, lo, solver, nrhs, st, lease.b)))
+    if ((rc = L.init(arena, lo, solver, nrhs, st, lease.b, eo)))
         return rc;
     H.adj = L.adj = prm->dagger;
-    void *r_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
-    void *e_lo = arena.take(vec_bytes(lo->prec, lo->V, nrhs));
+    void *r_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
+    void *e_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
     double *sig_dev = (double *)arena.take(sizeof(double) * nrhs);
     double *tol2_dev = (double *)arena.take(sizeof(double) * nrhs);
     if (!r_lo || !e_lo || !sig_dev || !tol2_dev)
@@ -572,7 +616,10 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     if (!prm->use_x0)
         if ((rc = H.blas(B_ZERO, x, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
             return rc;
-    const double tol = prm->tol;
+    std::vector<double> tolv(nrhs, prm->tol);  // per column (even-odd: scaled to the Schur system)
+    if (tolc)
+        for (int r = 0; r < nrhs; ++r)
+            tolv[r] = tolc[r];
     // CG on the normal equations with 16-bit storage cannot keep its
     // recurrence going between updates (measured: BF16 stalls, FP16 drifts
     // into thousands of iterations or overflow); those pairs keep defect
@@ -620,14 +667,14 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
             last_update = it;
             int e;
             // x64 += sigma e ; e = 0 ; r64 = b - D64 x ; r_lo = r64 / sigma
-            WL_TRY(launch_accum(lo->prec, hi->V, nrhs, x, e_lo, sig_dev, 1, st));
+            WL_TRY(launch_accum(lo->prec, H.V, nrhs, x, e_lo, sig_dev, 1, st));
             if ((e = L.blas(B_ZERO, e_lo, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return e;
             if ((e = H.stencil(H.v[1], x, 0, RED_NONE, nullptr, -1)))
                 return e;
             if ((e = H.blas(B_RES, H.v[0], nullptr, b, H.v[1], nullptr, nullptr, 0)))
                 return e;
-            WL_TRY(launch_convert(WL_F64, lo->prec, hi->V, nrhs, H.v[0], L.v[0], sig_dev, 1, 2, st));
+            WL_TRY(launch_convert(WL_F64, lo->prec, H.V, nrhs, H.v[0], L.v[0], sig_dev, 1, 2, st));
             if (solver == WL_SOLVER_BICGSTAB) {
                 // rho = <rh, r>, |r|^2 of the replaced residual, then beta
                 if ((e = L.blas(B_DOT_NORM, nullptr, nullptr, L.v[1], L.v[0], nullptr, nullptr, 0)))
@@ -661,6 +708,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         for (int r = 0; r < nrhs; ++r) {
             if (!std::isfinite(rr[r]))
                 return WL_ENAN;
+            const double tol = tolv[r];
             const bool ok = rr[r] <= tol * tol * bb[r];
             sig[r] = ok ? 0.0 : std::sqrt(rr[r]);
             t2[r] = ok ? 0.0 : 0.64 * tol * tol * bb[r] / rr[r];
@@ -683,7 +731,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         if (reliable)
             WL_TRY(hipMemcpyAsync(tol2_dev, t2, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
         // r_lo = r64 / sigma (0 for converged columns)
-        WL_TRY(launch_convert(WL_F64, lo->prec, hi->V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
+        WL_TRY(launch_convert(WL_F64, lo->prec, H.V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
         int done = 0;
         next_read = 0;
         last_update = 0;
@@ -703,7 +751,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         }
         total += done;
         // x64 += sigma e
-        WL_TRY(launch_accum(lo->prec, hi->V, nrhs, x, e_lo, sig_dev, 1, st));
+        WL_TRY(launch_accum(lo->prec, H.V, nrhs, x, e_lo, sig_dev, 1, st));
         ++outer;
     }
     int worst = WL_OK;
@@ -714,7 +762,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         s.stencil_calls = H.stencil_calls + L.stencil_calls;
         s.true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
         s.iter_rel_res = s.true_rel_res;
-        s.converged = s.true_rel_res <= tol;
+        s.converged = s.true_rel_res <= tolv[r];
         int code = s.converged ? WL_OK : (stagnated ? WL_STAGNATED : worst_flag == 2 ? WL_BREAKDOWN : WL_NOT_CONVERGED);
         if (code > worst)
             worst = code;
@@ -724,15 +772,131 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     return worst;
 }
 
+size_t plain_or_mixed_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs, uint32_t V)
+{
+    const int Lt = hi->g.dims[3];
+    if (!lo)
+        return engine_bytes(solver, hi->prec, V, Lt, nrhs) + 4 * ALIGN;
+    return engine_bytes(WL_SOLVER_CGNR, hi->prec, V, Lt, nrhs) + engine_bytes(solver, lo->prec, V, Lt, nrhs) +
+           2 * align_up(vec_bytes(lo->prec, V, nrhs)) + 2 * align_up(sizeof(double) * nrhs) + 8 * ALIGN;
+}
+
+// Even-odd solves: engines on half fields (plus each engine's odd scratch),
+// five half fields in hi's precision for the split, the Schur right-hand side
+// and the reconstruction, a half engine for |bh|, a full engine for the final
+// residual of D x = b, and the per-column tolerances.
+size_t eo_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs)
+{
+    const uint32_t Vh = hi->V / 2;
+    const int Lt = hi->g.dims[3];
+    size_t n = plain_or_mixed_bytes(hi, lo, solver, nrhs, Vh) + align_up(vec_bytes(hi->prec, Vh, nrhs)) +
+               (lo ? align_up(vec_bytes(lo->prec, Vh, nrhs)) : 0);
+    n += 5 * align_up(vec_bytes(hi->prec, Vh, nrhs));
+    n += engine_bytes(WL_SOLVER_CGNR, hi->prec, Vh, Lt, nrhs) + align_up(vec_bytes(hi->prec, Vh, nrhs));
+    n += engine_bytes(WL_SOLVER_CGNR, hi->prec, hi->V, Lt, nrhs);
+    n += 2 * align_up(sizeof(double) * nrhs) + 16 * ALIGN;
+    return n;
+}
+
+// Even-odd preconditioned solve (Schur complement on the even sites):
+//   b_e, b_o = split(b);  bh = b_e + kappa H_eo b_o;  M x_e = bh;
+//   x_o = b_o + kappa H_oe x_e;  x = merge(x_e, x_o)
+// (with the adjoint hops for D^dag).  The Schur system is solved to
+// |bh - M x_e| <= 0.9 tol |b| per column, which is the residual of D x = b
+// on the even sites (the odd ones vanish by construction); the reported
+// residual is recomputed on the full system.
+int solve_eo(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
+             const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena)
+{
+    for (int i = 0; i < 4; ++i)
+        if (hi->g.dims[i] % 2 != 0)
+            return WL_EINVAL;
+    if (hi->ns > 0)
+        return WL_EINVAL;
+    const uint32_t Vh = hi->V / 2;
+    const size_t hb = vec_bytes(hi->prec, Vh, nrhs);
+    void *b_e = arena.take(hb), *b_o = arena.take(hb), *bh = arena.take(hb), *x_e = arena.take(hb),
+         *x_o = arena.take(hb);
+    if (!b_e || !b_o || !bh || !x_e || !x_o)
+        return WL_EWORKSPACE;
+    HostLease lease;
+    if (!lease.b->ok)
+        return WL_EHIP;
+    Engine F{};  // full lattice: |b| and the final true residual
+    int rc = F.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, lease.b, false);
+    if (rc)
+        return rc;
+    F.adj = prm->dagger;
+    Engine Hh{};  // half lattice: |bh|
+    if ((rc = Hh.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, lease.b, true)))
+        return rc;
+    WL_TRY(launch_eo_copy(hi->prec, true, hi->g.dims, nrhs, b, nullptr, b_e, b_o, st));
+    EoParams pp = eo_params(hi, 0, nrhs);  // bh = b_e + kappa H_eo b_o
+    pp.in = b_o;
+    pp.self = b_e;
+    pp.out = bh;
+    pp.c_self = 1.0;
+    pp.c_hop = hi->kappa;
+    WL_TRY(launch_eo_hop(hi->prec, prm->dagger, RED_NONE, pp, st));
+    if (prm->use_x0)
+        WL_TRY(launch_eo_copy(hi->prec, true, hi->g.dims, nrhs, x, nullptr, x_e, x_o, st));
+    // per-column tolerance of the Schur system: 0.9 tol |b| / |bh|
+    std::vector<double> nb(nrhs), nh(nrhs), tolc(nrhs);
+    double *tmp = lease.b->d;
+    if ((rc = F.norm2(b, tmp)))
+        return rc;
+    for (int r = 0; r < nrhs; ++r)
+        nb[r] = tmp[r];
+    if ((rc = Hh.norm2(bh, tmp)))
+        return rc;
+    for (int r = 0; r < nrhs; ++r) {
+        nh[r] = tmp[r];
+        tolc[r] = nh[r] > 0 ? 0.9 * prm->tol * std::sqrt(nb[r] / nh[r]) : prm->tol;
+    }
+    std::vector<wl_solve_stats> es(nrhs);
+    const int src = lo ? solve_mixed(solver, hi, lo, x_e, bh, nrhs, prm, es.data(), st, arena, true, tolc.data())
+                       : solve_plain(solver, hi, x_e, bh, nrhs, prm, es.data(), st, arena, true, tolc.data());
+    if (src < 0)
+        return src;
+    EoParams pr = eo_params(hi, 1, nrhs);  // x_o = b_o + kappa H_oe x_e
+    pr.in = x_e;
+    pr.self = b_o;
+    pr.out = x_o;
+    pr.c_self = 1.0;
+    pr.c_hop = hi->kappa;
+    WL_TRY(launch_eo_hop(hi->prec, prm->dagger, RED_NONE, pr, st));
+    WL_TRY(launch_eo_copy(hi->prec, false, hi->g.dims, nrhs, nullptr, x, x_e, x_o, st));
+    double *rr = lease.b->d + nrhs;
+    if ((rc = F.true_res2(x, b, rr)))
+        return rc;
+    int worst = WL_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        if (!std::isfinite(rr[r]))
+            return WL_ENAN;
+        wl_solve_stats s = es[r];
+        s.true_rel_res = nb[r] > 0 ? std::sqrt(rr[r] / nb[r]) : 0.0;
+        s.iter_rel_res = nb[r] > 0 ? es[r].iter_rel_res * std::sqrt(nh[r] / nb[r]) : 0.0;
+        s.converged = s.true_rel_res <= prm->tol;
+        const int code = s.converged ? WL_OK : (src > 0 ? src : WL_NOT_CONVERGED);
+        if (code > worst)
+            worst = code;
+        stats[r] = s;
+    }
+    return worst;
+}
+
 }  // namespace
 
 size_t solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs)
 {
-    const int Lt = hi->g.dims[3];
-    if (!lo)
-        return engine_bytes(solver, hi->prec, hi->V, Lt, nrhs) + 4 * ALIGN;
-    return engine_bytes(WL_SOLVER_CGNR, hi->prec, hi->V, Lt, nrhs) + engine_bytes(solver, lo->prec, lo->V, Lt, nrhs) +
-           2 * align_up(vec_bytes(lo->prec, lo->V, nrhs)) + 2 * align_up(sizeof(double) * nrhs) + 8 * ALIGN;
+    const size_t plain = plain_or_mixed_bytes(hi, lo, solver, nrhs, hi->V);
+    bool even = hi->ns == 0;
+    for (int i = 0; i < 4; ++i)
+        even = even && hi->g.dims[i] % 2 == 0;
+    if (!even)
+        return plain;
+    const size_t e = eo_bytes(hi, lo, solver, nrhs);
+    return plain > e ? plain : e;
 }
 
 int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *prm,
@@ -767,8 +931,9 @@ int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, 
         arena.off = ALIGN - mis;
     }
     std::vector<wl_solve_stats> cst(ncols);
-    int rc = lo ? solve_mixed(solver, hi, lo, x, b, ncols, prm, cst.data(), st, arena)
-                : solve_plain(solver, hi, x, b, ncols, prm, cst.data(), st, arena);
+    int rc = prm->eo ? solve_eo(solver, hi, lo, x, b, ncols, prm, cst.data(), st, arena)
+             : lo    ? solve_mixed(solver, hi, lo, x, b, ncols, prm, cst.data(), st, arena)
+                     : solve_plain(solver, hi, x, b, ncols, prm, cst.data(), st, arena);
     (void)hipStreamSynchronize(st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats && rc >= 0)

@@ -37,7 +37,8 @@ EXPORTS = [
     "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read",
     "wl_stream_copy", "wl_strerror", "wl_last_hip_error", "wl_multi_plan_create", "wl_multi_plan_run",
     "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
-    "wl_dw_op_create", "dwf_apply", "wl_halo_bytes", "wilson_apply_halo",
+    "wl_dw_op_create", "dwf_apply", "wl_halo_bytes", "wilson_apply_halo", "wl_eo_split", "wl_eo_merge",
+    "wilson_schur_apply",
 ]
 
 
@@ -49,7 +50,7 @@ class wl_solve_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("reliable", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("dagger", ctypes.c_int), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("eo", ctypes.c_int)]
 
 
 class wl_solve_stats(ctypes.Structure):
@@ -104,6 +105,9 @@ def lib():
         "wl_dw_op_create": [G, D, D, I, I, P, ctypes.POINTER(P)],
         "dwf_apply": [P, P, P, I, I, P],
         "wl_halo_bytes": [P, I, ctypes.POINTER(SZ)],
+        "wl_eo_split": [G, I, I, P, P, P, P],
+        "wl_eo_merge": [G, I, I, P, P, P, P],
+        "wilson_schur_apply": [P, P, P, P, I, I, P],
         "wilson_apply_halo": [P, P, P, I, I, P, SZ, P],
         "wilson_dslash": [P, P, P, I, I, P],
         "wilson_apply": [P, P, P, I, I, P],
@@ -420,6 +424,30 @@ class Operator:
     def dslash_packed(self, out, inp, nrhs=1, dagger=False):
         wilson_dslash(self.handle, _ptr(out), _ptr(inp), dagger, nrhs, _stream())
 
+    def new_half(self, nrhs=1):
+        """A packed half field (the V/2 sites of one parity)."""
+        n = wl_field_bytes(self.geom, WL_SPINOR, self.prec, nrhs) // 2
+        return _torch().empty(max(n, 16), dtype=_torch().uint8, device=self.U_packed.device)
+
+    def eo_split(self, packed, nrhs=1):
+        even, odd = self.new_half(nrhs), self.new_half(nrhs)
+        g = self.geom
+        _check(lib().wl_eo_split(ctypes.byref(g), self.prec, int(nrhs), _ptr(packed), _ptr(even), _ptr(odd),
+                                 _stream()), "wl_eo_split")
+        return even, odd
+
+    def eo_merge(self, even, odd, nrhs=1):
+        out = self.new_field(nrhs)
+        g = self.geom
+        _check(lib().wl_eo_merge(ctypes.byref(g), self.prec, int(nrhs), _ptr(even), _ptr(odd), _ptr(out),
+                                 _stream()), "wl_eo_merge")
+        return out
+
+    def schur_packed(self, out_e, in_e, tmp_o, nrhs=1, dagger=False):
+        """out_e = (1 - kappa^2 H_eo H_oe) in_e on packed even half fields."""
+        _check(lib().wilson_schur_apply(self.handle, _ptr(out_e), _ptr(in_e), _ptr(tmp_o), int(bool(dagger)),
+                                        int(nrhs), _stream()), "wilson_schur_apply")
+
     def halo_buffer(self, nrhs=1):
         n = ctypes.c_size_t(0)
         _check(lib().wl_halo_bytes(self.handle, int(nrhs), ctypes.byref(n)), "wl_halo_bytes")
@@ -577,12 +605,14 @@ def dslash(U, psi, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None):
 
 
 def solve(U, b, kappa, method="bicgstab", precision="f64", tol=1e-10, maxiter=10000, bc=(1, 1, 1, -1),
-          inner_tol=0.0, check_every=0, x0=None, ops=None, return_stats=False, dagger=False, reliable=False):
+          inner_tol=0.0, check_every=0, x0=None, ops=None, return_stats=False, dagger=False, reliable=False,
+          eo=False):
     """x = D^{-1} b (dagger: x = D^{-dag} b) for canonical complex128 CUDA tensors.
 
     precision: "f64" (plain FP64), "f32" (plain FP32), or "mixed-f32", "mixed-bf16",
     "mixed-f16" (FP64 refinement around an inner solve with that storage).
-    ops: optional (hi, lo) Operators to reuse (lo None for a plain solve)."""
+    ops: optional (hi, lo) Operators to reuse (lo None for a plain solve).
+    eo: even-odd preconditioning (Schur complement on the even sites)."""
     torch = _torch()
     nrhs = None if b.dim() == 6 else int(b.shape[0])
     n = nrhs or 1
@@ -599,7 +629,7 @@ def solve(U, b, kappa, method="bicgstab", precision="f64", tol=1e-10, maxiter=10
     xp = hi.pack(x0) if x0 is not None else hi.new_field(n)
     prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=int(reliable),
                           check_every=check_every, use_x0=1 if x0 is not None else 0, dagger=int(dagger),
-                          workspace=None, workspace_bytes=0)
+                          workspace=None, workspace_bytes=0, eo=int(eo))
     ws = wl_solver_workspace_bytes(hi.handle, lo.handle if lo else None, SOLVER[method], n)
     work = torch.empty(ws, dtype=torch.uint8, device=b.device)
     prm.workspace = work.data_ptr()

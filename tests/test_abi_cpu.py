@@ -145,6 +145,10 @@ def test_bad_arguments_rejected_before_launch():
         assert L.wl_halo_bytes(dw, 1, ctypes.byref(n)) == wilson.WL_EINVAL  # Wilson ops only
     finally:
         L.wl_op_destroy(dw)
+    godd = wilson.make_geom((4, 4, 3, 4))  # even-odd needs every extent even
+    assert L.wl_eo_split(ctypes.byref(godd), 0, 1, 256, 512, 768, None) == wilson.WL_EINVAL
+    assert L.wl_eo_split(ctypes.byref(g), 0, 1, 256, 512, 512, None) == wilson.WL_EINVAL  # even == odd
+    assert L.wl_eo_merge(ctypes.byref(g), 0, 1, 256, 512, 8, None) == wilson.WL_EALIGN
     for c in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):
         assert L.wl_strerror(c).decode() != "unknown error"
 

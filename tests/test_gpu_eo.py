@@ -1,0 +1,119 @@
+"""Even-odd decomposition on the GPU: half-field split/merge and the Schur
+complement M = 1 - kappa^2 H_eo H_oe against its definition through the
+oracle's hopping term (the oracle itself is unchanged)."""
+import numpy as np
+import pytest
+
+from paper_1712_01505_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "f16": 3e-3}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def parity_mask(dims):
+    Lx, Ly, Lz, Lt = dims
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    return ((x + y + z + t) % 2)[..., None, None]
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1712_01505_amd import wilson
+    assert torch.cuda.is_available()
+    wilson.lib()
+    return wilson
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
+def test_split_merge_roundtrip_is_exact(W, prec):
+    dims = (4, 6, 2, 6)
+    U = inputs.haar_gauge(dims, seed=1)
+    psi = inputs.gaussian_spinor(dims, seed=2, nrhs=3)
+    op = W.Operator.create(dev(U), 0.12, W.PREC[prec])
+    full = op.pack(dev(psi))
+    even, odd = op.eo_split(full, 3)
+    back = op.eo_merge(even, odd, 3)
+    assert torch.equal(back, full)
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 8), (1, 1, 1, -1)), ((6, 4, 2, 6), (1, 1, 1, -1)),
+                                     ((2, 4, 2, 4), (-1, 1, 1, 1))])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
+def test_schur_apply_matches_definition(W, oracle_mod, dims, bc, prec):
+    kappa = 0.1255
+    U = inputs.haar_gauge(dims, seed=3)
+    psi = inputs.gaussian_spinor(dims, seed=4, nrhs=2)
+    odd = parity_mask(dims) == 1
+    x_e = np.where(odd, 0.0, psi)
+    op = W.Operator.create(dev(U), kappa, W.PREC[prec], bc)
+    ev, _ = op.eo_split(op.pack(dev(x_e)), 2)
+    zero_o = op.new_half(2)
+    zero_o.zero_()
+    for dagger in (False, True):
+        ref = []
+        for k in range(2):
+            tmp = np.where(odd, oracle_mod.hop(U, x_e[k], bc=bc, dagger=dagger), 0.0)
+            w = oracle_mod.hop(U, tmp, bc=bc, dagger=dagger)
+            ref.append(np.where(odd, 0.0, x_e[k] - kappa ** 2 * w))
+        ref = np.stack(ref)
+        out_e, tmp_o = op.new_half(2), op.new_half(2)
+        op.schur_packed(out_e, ev, tmp_o, 2, dagger)
+        got = op.unpack(op.eo_merge(out_e, zero_o, 2), 2).cpu().numpy()
+        assert rel(got, ref) < TOL[prec], dagger
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "cgnr"])
+@pytest.mark.parametrize("precision,reliable", [("f64", False), ("mixed-f32", False), ("mixed-f16", False),
+                                                ("mixed-f32", True)])
+def test_eo_solve_reaches_tolerance(W, oracle_mod, method, precision, reliable):
+    """Even-odd preconditioned solves meet the full-system bar with fewer iterations."""
+    dims = (8, 8, 8, 16)
+    kappa = 0.1255
+    U = inputs.near_unity_gauge(dims, 0.3, seed=1)
+    b = inputs.gaussian_spinor(dims, seed=0)
+    x, st = W.solve(dev(U), dev(b), kappa, method=method, precision=precision, tol=1e-10, return_stats=True,
+                    eo=True, reliable=reliable)
+    assert st["status"] == 0 and st["converged"], st
+    x = x.cpu().numpy()
+    r = rel(oracle_mod.apply(U, x, kappa), b)
+    assert r <= 1.05e-10
+    assert abs(r - st["true_rel_res"]) < 1e-12
+    x_ref, _, _, _ = oracle_mod.bicgstab(U, b, kappa, tol=1e-13)
+    assert rel(x, x_ref) < 1e-8
+    if precision == "f64":
+        _, st_full = W.solve(dev(U), dev(b), kappa, method=method, precision="f64", tol=1e-10, return_stats=True)
+        assert st["iters"] < st_full["iters"]
+
+
+def test_eo_solve_several_rhs_adjoint_and_warm_start(W, oracle_mod):
+    dims = (4, 4, 4, 8)
+    kappa = 0.12
+    U = inputs.haar_gauge(dims, seed=6)
+    bs = inputs.gaussian_spinor(dims, seed=7, nrhs=3)
+    xs, st = W.solve(dev(U), dev(bs), kappa, method="bicgstab", tol=1e-11, eo=True, return_stats=True)
+    assert all(s["converged"] for s in st)
+    for k in range(3):
+        assert rel(oracle_mod.apply(U, xs[k].cpu().numpy(), kappa), bs[k]) <= 1.05e-11
+    y = W.solve(dev(U), dev(bs[0]), kappa, method="cgnr", tol=1e-11, eo=True, dagger=True).cpu().numpy()
+    assert rel(oracle_mod.apply(U, y, kappa, dagger=True), bs[0]) <= 1.05e-11
+    x2, st2 = W.solve(dev(U), dev(bs[1]), kappa, method="bicgstab", tol=1e-11, eo=True, x0=xs[1], return_stats=True)
+    assert st2["iters"] <= 1 and rel(x2.cpu().numpy(), xs[1].cpu().numpy()) < 1e-9
+
+
+def test_eo_rejects_odd_extent(W):
+    dims = (4, 4, 4, 5)
+    U = dev(inputs.haar_gauge(dims, seed=8))
+    b = dev(inputs.gaussian_spinor(dims, seed=9))
+    with pytest.raises(W.WilsonError) as e:
+        W.solve(U, b, 0.12, eo=True)
+    assert e.value.code == W.WL_EINVAL
