@@ -344,9 +344,9 @@ def main():
                    for lo in [None] + [ops[p].handle for p in (1, 2, 3)] for s in (0, 1))
     work = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
-    def run_solve(method, lo_prec, reliable=args.reliable):
+    def run_solve(method, lo_prec, reliable=args.reliable, eo=0):
         prm = W.wl_solve_params(tol=tol, maxiter=20000, inner_tol=0.0, max_outer=0, reliable=int(reliable),
-                                check_every=0,
+                                eo=int(eo), check_every=0,
                                 use_x0=0, workspace=work.data_ptr(), workspace_bytes=ws_bytes)
         st = (W.wl_solve_stats * 1)()
         fn = W.solve_cgnr if method == "cgnr" else W.solve_bicgstab
@@ -442,15 +442,19 @@ def main():
             log(f"[bench] apply {PNAME[p]}: {dsl[PNAME[p]]}")
         result["dslash"] = dsl
         solves = {}
-        for method, lo, rel in (("bicgstab", None, 0), ("cgnr", None, 0), ("bicgstab", W.WL_F32, 0),
-                                ("bicgstab", W.WL_BF16S, 0), ("bicgstab", W.WL_F16S, 0), ("cgnr", W.WL_F16S, 0),
-                                ("bicgstab", W.WL_F32, 1), ("bicgstab", W.WL_BF16S, 1), ("bicgstab", W.WL_F16S, 1),
-                                ("cgnr", W.WL_F32, 0), ("cgnr", W.WL_F32, 1)):
+        for method, lo, rel, eo in (("bicgstab", None, 0, 0), ("cgnr", None, 0, 0), ("bicgstab", W.WL_F32, 0, 0),
+                                    ("bicgstab", W.WL_BF16S, 0, 0), ("bicgstab", W.WL_F16S, 0, 0),
+                                    ("cgnr", W.WL_F16S, 0, 0), ("bicgstab", W.WL_F32, 1, 0),
+                                    ("bicgstab", W.WL_BF16S, 1, 0), ("bicgstab", W.WL_F16S, 1, 0),
+                                    ("cgnr", W.WL_F32, 0, 0), ("cgnr", W.WL_F32, 1, 0),
+                                    ("bicgstab", None, 0, 1), ("cgnr", None, 0, 1), ("bicgstab", W.WL_F32, 1, 1),
+                                    ("bicgstab", W.WL_F16S, 0, 1), ("bicgstab", W.WL_F16S, 1, 1)):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            code, st = run_solve(method, lo, rel)
+            code, st = run_solve(method, lo, rel, eo)
             dt = time.perf_counter() - t1
-            key = f"{method}_{'f64' if lo is None else 'mixed_' + PNAME[lo]}{'_reliable' if rel else ''}"
+            key = (f"{method}_{'f64' if lo is None else 'mixed_' + PNAME[lo]}{'_reliable' if rel else ''}"
+                   f"{'_evenodd' if eo else ''}")
             solves[key] = {"seconds": round(dt, 4), "status": code, "iters": st["iters"], "outer": st["outer"],
                            "true_rel_res": st["true_rel_res"]}
             log(f"[bench] solve {key}: {solves[key]}")
