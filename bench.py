@@ -162,6 +162,32 @@ def bench_batching(W, inputs, torch, log):
                                 "speedup": round(ms_sep / ms_multi, 3),
                                 "GFLOP/s": round(1368 * Vt * 4 / (ms_multi * 1e-3) / 1e9, 1)}
     log(f"[bench] multi-lattice: {out['multi_lattice_f32']}")
+    del ops, srcs, dsts, plan
+    torch.cuda.empty_cache()
+    # an ensemble of small lattices (64 of 4^4 .. 8^4), where separate
+    # launches are bound by their fixed cost
+    shapes = [(4, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8), (4, 4, 4, 8)]
+    ens = [shapes[j % 4] for j in range(64)]
+    ops, srcs, dsts = [], [], []
+    for j, dj in enumerate(ens):
+        op = W.Operator.create(torch.from_numpy(inputs.near_unity_gauge(dj, 0.3, seed=300 + j)).cuda(), kappa,
+                               W.WL_F32)
+        srcs.append(op.pack(torch.from_numpy(inputs.gaussian_spinor(dj, seed=400 + j, nrhs=4)).cuda()))
+        dsts.append(op.new_field(4))
+        ops.append(op)
+    plan = W.MultiPlan([(o.handle, d.data_ptr(), s_.data_ptr()) for o, d, s_ in zip(ops, dsts, srcs)], 0, 4)
+    plan.tune(st)
+    ms_multi = _time_ms(torch, lambda: plan.run(st), 50)
+    for o in ops[:4]:
+        W.wl_autotune(o.handle, 4, 0, st)
+    ms_sep = _time_ms(torch, separate, 20)
+    Vt = sum(inputs.volume(d) for d in ens)
+    out["ensemble_64_small_f32"] = {"lattices": "16 each of 4^4, 6^4, 8^4, 4^3x8", "nrhs": 4, "V_total": Vt,
+                                    "one_launch_us": round(ms_multi * 1e3, 1), "plan_launch": plan.launch(),
+                                    "separate_launches_us": round(ms_sep * 1e3, 1),
+                                    "speedup": round(ms_sep / ms_multi, 3),
+                                    "GFLOP/s": round(1368 * Vt * 4 / (ms_multi * 1e-3) / 1e9, 1)}
+    log(f"[bench] ensemble of small lattices: {out['ensemble_64_small_f32']}")
     return out
 
 

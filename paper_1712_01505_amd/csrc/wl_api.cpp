@@ -939,9 +939,11 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     // the plain apply, then each fused reduction of the solvers (partials
     // and the <v, out> operand in scratch)
     LaunchCfg bests[4];
-    double *parts = nullptr;
+    double *parts = nullptr, *sums = nullptr;
     if (e == hipSuccess)
         e = hipMalloc(&parts, 3 * sizeof(double) * (size_t)nrhs * ((op->V + 63) / 64 + op->g.dims[3] + 8));
+    if (e == hipSuccess)
+        e = hipMalloc(&sums, 3 * sizeof(double) * (size_t)nrhs);
     // a domain-wall operator has only the reductions of CG on the normal equations
     const int last_red = op->ns > 0 ? (int)RED_NORM : (int)RED_DOTIN_NORM;
     for (int red = RED_NONE; red <= RED_DOTIN_NORM && e == hipSuccess; ++red) {
@@ -957,13 +959,28 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
             p.red = red;
             p.partials = parts;
             p.aux = in;
+            // a fused reduction is timed with the finalize that sums its
+            // partials: fewer, larger workgroups leave it less to read
+            FinParams fp{};
+            fp.A = parts;
+            fp.nblkA = stencil_partials(c, p.L, op->V, nrhs);
+            fp.nvalA = stencil_nval(red);
+            fp.out = sums;
+            fp.nrhs = nrhs;
+            fp.group = 1;
+            auto step = [&]() {
+                hipError_t r = launch_stencil(op->prec, dagger, c, p, st);
+                if (r == hipSuccess && red != RED_NONE)
+                    r = launch_finalize(F_SUM, fp, st);
+                return r;
+            };
             for (int w = 0; w < 2 && e == hipSuccess; ++w)
-                e = launch_stencil(op->prec, dagger, c, p, st);
+                e = step();
             const int reps = 10;
             if (e == hipSuccess)
                 e = hipEventRecord(a, st);
             for (int k = 0; k < reps && e == hipSuccess; ++k)
-                e = launch_stencil(op->prec, dagger, c, p, st);
+                e = step();
             if (e == hipSuccess)
                 e = hipEventRecord(b, st);
             if (e == hipSuccess)
@@ -984,6 +1001,8 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
         (void)hipEventDestroy(b);
     if (parts)
         (void)hipFree(parts);
+    if (sums)
+        (void)hipFree(sums);
     (void)hipFree(in);
     (void)hipFree(out);
     CHECK_HIP(e);

@@ -56,7 +56,6 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
 {
     using T = typename Traits<P>::real;
     __shared__ double lds[3 * 4];
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     const uint32_t V = p.V;
     const int nr = p.nrhs;
@@ -65,6 +64,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
     if (OP == B_CG_RESTART && !p.sc[r].restart)
         return;
     double red[3] = {0.0, 0.0, 0.0};
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < V) {
         const Scalars &sc = p.sc[r];
         if constexpr (OP == B_RES) {  // r = b - w
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
                 o[k] = cx<T>{b[k].re - w[k].re, b[k].im - w[k].im};
             round_if_scaled<P>(o);
             store_site<P>(p.y0, V, nr, s, r, o);
-            red[0] = n2(o);
+            red[0] += n2(o);
         } else if constexpr (OP == B_CG_XR) {  // x += a p ; r -= a w
             const T a = (T)sc.alpha.x;
             cx<T> x[12], rr[12], pp[12], w[12];
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             round_if_scaled<P>(rr);
             store_site<P>(p.y0, V, nr, s, r, x);
             store_site<P>(p.y1, V, nr, s, r, rr);
-            red[0] = n2(rr);
+            red[0] += n2(rr);
         } else if constexpr (OP == B_CG_P) {  // p = z + beta p
             const T b = (T)sc.beta.x;
             cx<T> pp[12], z[12];
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
                 rr[k] = cfma(cx<T>{-a.re, -a.im}, v[k], rr[k]);
             round_if_scaled<P>(rr);
             store_site<P>(p.y0, V, nr, s, r, rr);
-            red[0] = n2(rr);
+            red[0] += n2(rr);
         } else if constexpr (OP == B_BI_XR) {  // x += alpha p + omega s ; r = s - omega t
             const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
             cx<T> x[12], pp[12], ss[12], t[12];
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             round_if_scaled<P>(ss);
             store_site<P>(p.y0, V, nr, s, r, x);
             store_site<P>(p.y1, V, nr, s, r, ss);
-            red[0] = n2(ss);
+            red[0] += n2(ss);
             cx<T> rh[12];
             load_site<P>(p.a3, V, nr, s, r, rh);
             dot(rh, ss, red[1], red[2]);
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
         } else if constexpr (OP == B_NORM) {
             cx<T> v[12];
             load_site<P>(p.a0, V, nr, s, r, v);
-            red[0] = n2(v);
+            red[0] += n2(v);
         } else if constexpr (OP == B_CG_RESTART) {  // p = z
             cx<T> v[12];
             load_site<P>(p.a0, V, nr, s, r, v);
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             load_site<P>(p.a0, V, nr, s, r, a);
             load_site<P>(p.a1, V, nr, s, r, b);
             dot(a, b, red[0], red[1]);
-            red[2] = n2(b);
+            red[2] += n2(b);
         }
     }
     constexpr int NV = (OP == B_RES || OP == B_CG_XR || OP == B_BI_S || OP == B_NORM) ? 1
@@ -213,10 +213,19 @@ static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hip
     return hipGetLastError();
 }
 
+// One workgroup per `block` sites and column.  (A grid-stride variant capped
+// at 2048 workgroups, which shrinks the finalize's input, measured slower
+// overall: the streaming kernels lost more than the finalize gained.)
+int blas_partials(uint32_t V, int nrhs, int block)
+{
+    (void)nrhs;
+    return (int)((V + block - 1) / (uint32_t)block);
+}
+
 hipError_t launch_blas(int prec, int op, const BlasParams &p0, int block, hipStream_t st)
 {
     BlasParams p = p0;
-    p.nblk = (int)((p.V + block - 1) / block);
+    p.nblk = blas_partials(p.V, p.nrhs, block);
     dim3 g(p.nblk, p.nrhs), b(block);
     switch (prec) {
     case F64: return launch_blas_p<F64>(op, p, g, b, st);
@@ -265,12 +274,12 @@ hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e,
 // ---------------------------------------------------------------- finalize
 // One workgroup sums every (value, right-hand side) row of the partial
 // arrays in a fixed order and then runs the scalar recurrence per column.
-// Rows are summed G at a time; each thread keeps 8 independent loads in
-// flight per row, so a pass costs about one memory latency.
+// Rows are summed G at a time; a pass loads U values of each of the G rows
+// per thread before it adds any of them.
 constexpr int FIN_THREADS = 1024;
 constexpr int FIN_MAX = 3 * 64;  // values x right-hand sides per partial set
 constexpr int FIN_G = 4;         // rows summed per pass (one pass for the usual 1..4 rows)
-constexpr int FIN_U = 8;         // independent loads per thread per row and pass
+constexpr int FIN_U = 4;         // loads per thread per row and pass
 
 __device__ __forceinline__ bool finite2(double a) { return isfinite(a); }
 
@@ -299,31 +308,49 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
     const int nr = p.nrhs;
     const int na = p.nvalA * nr, nb = p.nvalB * nr, ncomb = na + nb + p.nvalC * nr;
     for (int c0 = 0; c0 < ncomb; c0 += FIN_G) {
-        double v[FIN_G];
+        // one pass issues the loads of all G rows before any add: a single
+        // workgroup is bound by its load issue rate, not by latency
+        RowRef row[FIN_G];
+        int nmax = 0;
 #pragma unroll
         for (int g = 0; g < FIN_G; ++g) {
-            double a[FIN_U];
+            row[g] = c0 + g < ncomb ? fin_row(p, c0 + g) : RowRef{nullptr, 0};
+            nmax = max(nmax, row[g].n);
+        }
+        double v[FIN_G];
 #pragma unroll
-            for (int j = 0; j < FIN_U; ++j)
-                a[j] = 0.0;
-            if (c0 + g < ncomb) {
-                const RowRef row = fin_row(p, c0 + g);
-                for (int base = 0; base < row.n; base += FIN_U * FIN_THREADS) {
+        for (int g = 0; g < FIN_G; ++g)
+            v[g] = 0.0;
+        for (int base = 0; base < nmax; base += FIN_U * FIN_THREADS) {
+            double x[FIN_G][FIN_U];
+#pragma unroll
+            for (int g = 0; g < FIN_G; ++g) {
+                if (base < row[g].n) {  // uniform: rows shorter than nmax stop early
 #pragma unroll
                     for (int j = 0; j < FIN_U; ++j) {
-                        const int i = base + j * FIN_THREADS + threadIdx.x;
-                        if (i < row.n)
-                            a[j] += row.p[i];
+                        const int i = base + j * FIN_THREADS + (int)threadIdx.x;
+                        x[g][j] = row[g].p[i < row[g].n ? i : 0];
                     }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < FIN_U; ++j)
+                        x[g][j] = 0.0;
                 }
             }
-            // fixed pairwise order
 #pragma unroll
-            for (int w = FIN_U / 2; w > 0; w >>= 1)
+            for (int g = 0; g < FIN_G; ++g) {
 #pragma unroll
-                for (int j = 0; j < w; ++j)
-                    a[j] += a[j + w];
-            v[g] = a[0];
+                for (int j = 0; j < FIN_U; ++j)
+                    if (base + j * FIN_THREADS + (int)threadIdx.x >= row[g].n)
+                        x[g][j] = 0.0;
+                // fixed pairwise order within a pass
+#pragma unroll
+                for (int w = FIN_U / 2; w > 0; w >>= 1)
+#pragma unroll
+                    for (int j = 0; j < w; ++j)
+                        x[g][j] += x[g][j + w];
+                v[g] += x[g][0];
+            }
         }
         block_sum<FIN_G>(v, lds);
         if (threadIdx.x == 0) {

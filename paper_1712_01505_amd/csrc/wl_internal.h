@@ -194,6 +194,7 @@ struct BlasParams {
     int skip_frozen;   // in a solver loop: skip frozen columns
 };
 hipError_t launch_blas(int prec, int op, const BlasParams &p, int block, hipStream_t st);
+int blas_partials(uint32_t V, int nrhs, int block);  // workgroups (= partial sums per RHS) of one launch
 int blas_nval(int op);
 
 // x64 += s[rhs] * e (e in precision pin); s read from device with stride.

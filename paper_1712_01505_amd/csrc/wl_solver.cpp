@@ -261,7 +261,7 @@ struct Engine {
         p.V = V;
         p.nrhs = nrhs;
         if (slot >= 0) {
-            nblk[slot] = (int)((V + BLAS_BLOCK - 1) / BLAS_BLOCK);
+            nblk[slot] = blas_partials(V, nrhs, BLAS_BLOCK);
             nval[slot] = blas_nval(bop);
         }
         WL_TRY(launch_blas(prec, bop, p, BLAS_BLOCK, st));

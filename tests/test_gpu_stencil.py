@@ -231,6 +231,34 @@ def test_multi_lattice_plan_every_shape(W):
             del plan
 
 
+def test_multi_lattice_plan_many_small(W):
+    """An ensemble of 40 small lattices of four shapes in one plan (tuned,
+    then run twice) equals the separate launches bit for bit."""
+    shapes = [(4, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8), (4, 4, 4, 8)]
+    for prec in ("f32", "f16"):
+        p = W.PREC[prec]
+        ops, srcs, dsts, refs = [], [], [], []
+        for j in range(40):
+            dims = shapes[j % 4]
+            op = W.Operator.create(dev(inputs.near_unity_gauge(dims, 0.3, seed=300 + j)), 0.12, p)
+            src = op.pack(dev(inputs.gaussian_spinor(dims, seed=400 + j, nrhs=4)))
+            ref = op.new_field(4)
+            op.apply_packed(ref, src, 4)
+            ops.append(op)
+            srcs.append(src)
+            dsts.append(op.new_field(4))
+            refs.append(op.unpack(ref, 4))
+        plan = W.MultiPlan([(o.handle, d.data_ptr(), s_.data_ptr()) for o, d, s_ in zip(ops, dsts, srcs)], 0, 4)
+        plan.tune()
+        for rep in range(2):
+            for d in dsts:
+                d.zero_()
+            plan.run()
+            torch.cuda.synchronize()
+            for j, (o, d, r) in enumerate(zip(ops, dsts, refs)):
+                assert torch.equal(o.unpack(d, 4), r), (prec, rep, j, plan.launch())
+
+
 def test_multi_lattice_launch_matches_separate(W):
     lattices = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (20, 20, 20, 20)]
     for prec in ("f64", "f32"):
