@@ -34,6 +34,8 @@ if ROOT not in sys.path:
 FLOP_APPLY = 1368
 # compulsory bytes per site per right-hand side (spinor in + 4 two-row links + spinor out)
 BYTES = {0: 192 + 4 * 96 + 192, 1: 96 + 4 * 48 + 96, 2: 52 + 4 * 24 + 52, 3: 52 + 4 * 24 + 52}
+# one spinor field per site (a fused reduction <rh, .> reads rh on top of BYTES)
+SPINOR = {0: 192, 1: 96, 2: 52, 3: 52}
 PNAME = {0: "f64", 1: "f32", 2: "bf16", 3: "f16"}
 HBM_PEAK_GBS = 8000.0
 
@@ -408,6 +410,7 @@ def main():
     elapsed = time.perf_counter() - t0
     W.wl_prof_enable(0)
     prof = {p: W.wl_prof_read(p) for p in range(4)}
+    prof_aux = {p: W.wl_prof_read_aux(p) for p in range(4)}
     log(f"[bench] {args.steps} steps in {elapsed:.3f}s")
     ms_per_step = 1e3 * elapsed / args.steps
     calls = sum(s["stencil_calls"] for s in stats) / args.steps
@@ -419,14 +422,18 @@ def main():
     dom = max(prof, key=lambda p: prof[p][1])
     n_l, ms_l, sites_l = prof[dom]
     avg_ms = ms_l / max(n_l, 1)
-    bytes_per_launch = BYTES[dom] * V
+    # compulsory bytes of the launches: the stencil's own, plus the rh field
+    # read by the launches whose fused reduction takes <rh, out>
+    bytes_per_launch = (BYTES[dom] * sites_l + SPINOR[dom] * prof_aux[dom]) / max(n_l, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm",
                 "kernel": f"wilson stencil <{PNAME[dom]}> in the solve (stencil_kernel/twalk_kernel, fused reductions)",
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, dims),
-                "bytes_per_site": BYTES[dom], "sites_per_launch": V, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "bytes_per_site": round(bytes_per_launch / V, 1), "stencil_bytes_per_site": BYTES[dom],
+                "fused_rh_read_fraction": round(prof_aux[dom] / max(sites_l, 1), 3),
+                "sites_per_launch": V, "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": n_l}
 
     result = {

@@ -226,6 +226,11 @@ int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int 
  * precision (Sec. II-C: the inner low-precision solver sets the speed).
  * With domain-wall ops (wl_dw_op_create; hi and lo with equal Ns, m0, m)
  * only solve_cgnr is offered and nrhs counts 5-d vectors.
+ * Without reliable updates BiCGStab runs a merged iteration: the second
+ * product also returns <rh, s> and <rh, t>, so rho' = <rh, s> - omega <rh, t>
+ * and beta are known before r' = s - omega t is formed, and one pass updates
+ * x, r and the next p (the same recurrences; two vector passes and one
+ * kernel fewer per iteration).
  * stats: array of nrhs entries (may be NULL).  Synchronises `stream`.
  * Returns the worst status over right-hand sides. */
 int solve_cgnr(const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *p,
@@ -332,6 +337,11 @@ int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg);
 int wl_prof_enable(int on);
 int wl_prof_reset(void);
 int wl_prof_read(int prec, long *launches, double *total_ms, double *site_rhs);
+/* Of those sites x right-hand sides, the ones whose launch also read a
+ * further spinor field for its fused reduction (the solvers' <rh, D p> and
+ * <rh, D s>, with rh the BiCGStab shadow residual): one more field of
+ * compulsory traffic per site.  WL_EINVAL for a bad precision or null. */
+int wl_prof_read_aux(int prec, double *aux_site_rhs);
 
 /* Plain device-to-device streaming copy of `bytes` (a multiple of 16, no
  * overlap): the reference point for achievable HBM bandwidth and for

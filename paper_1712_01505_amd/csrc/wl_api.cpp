@@ -69,11 +69,12 @@ struct ProfRec {
     int prec;
     hipEvent_t a, b;
     double sites;
+    double aux_sites;  // sites x RHS of launches whose reduction reads a further field (aux)
 };
 static std::atomic<int> g_prof_on{0};
 static std::mutex g_prof_mu;
 static std::vector<ProfRec> g_prof_pending;
-static double g_prof_ms[4] = {0, 0, 0, 0}, g_prof_sites[4] = {0, 0, 0, 0};
+static double g_prof_ms[4] = {0, 0, 0, 0}, g_prof_sites[4] = {0, 0, 0, 0}, g_prof_aux[4] = {0, 0, 0, 0};
 static long g_prof_n[4] = {0, 0, 0, 0};
 static std::vector<hipEvent_t> g_event_pool;
 
@@ -97,6 +98,7 @@ static void drain_prof_locked()
         if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             g_prof_ms[r.prec] += ms;
             g_prof_sites[r.prec] += r.sites;
+            g_prof_aux[r.prec] += r.aux_sites;
             g_prof_n[r.prec] += 1;
         }
         g_event_pool.push_back(r.a);
@@ -120,8 +122,9 @@ hipError_t prof_stencil(int prec, const wl_op *op, int dagger, const LaunchCfg &
         e = launch_stencil(prec, dagger, cfg, p, st);
     if (e == hipSuccess)
         e = hipEventRecord(b, st);
+    const bool aux = p.aux && (p.red == RED_DOTV || p.red == RED_BICG);
     if (e == hipSuccess)
-        g_prof_pending.push_back(ProfRec{prec, a, b, (double)p.V * p.nrhs});
+        g_prof_pending.push_back(ProfRec{prec, a, b, (double)p.V * p.nrhs, aux ? (double)p.V * p.nrhs : 0.0});
     (void)op;
     return e;
 }
@@ -228,7 +231,7 @@ static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
 // Launch configurations are kept per (nrhs, fused reduction): the solver's
 // stencils with a reduction epilogue are tuned separately from the plain
 // apply.  A reduction kind without its own entry uses the plain one.
-static int launch_key(int nrhs, int red) { return nrhs * 4 + red; }
+static int launch_key(int nrhs, int red) { return nrhs * 8 + red; }
 
 static std::string tune_key_red(const wl_op *op, int nrhs, int red)
 {
@@ -899,7 +902,7 @@ int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg)
     if (!launch_ok(op, nrhs, c))
         return WL_EINVAL;
     std::lock_guard<std::mutex> lk(op->mu);
-    for (int red = RED_NONE; red <= RED_DOTIN_NORM; ++red)  // every stencil of this nrhs
+    for (int red = RED_NONE; red <= RED_BICG; ++red)  // every stencil of this nrhs
         op->launch[launch_key(nrhs, red)] = c;
     return WL_OK;
 }
@@ -938,15 +941,15 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
                     }
     // the plain apply, then each fused reduction of the solvers (partials
     // and the <v, out> operand in scratch)
-    LaunchCfg bests[4];
+    LaunchCfg bests[RED_BICG + 1];
     double *parts = nullptr, *sums = nullptr;
     if (e == hipSuccess)
-        e = hipMalloc(&parts, 3 * sizeof(double) * (size_t)nrhs * ((op->V + 63) / 64 + op->g.dims[3] + 8));
+        e = hipMalloc(&parts, RED_NVAL_MAX * sizeof(double) * (size_t)nrhs * ((op->V + 63) / 64 + op->g.dims[3] + 8));
     if (e == hipSuccess)
-        e = hipMalloc(&sums, 3 * sizeof(double) * (size_t)nrhs);
+        e = hipMalloc(&sums, RED_NVAL_MAX * sizeof(double) * (size_t)nrhs);
     // a domain-wall operator has only the reductions of CG on the normal equations
-    const int last_red = op->ns > 0 ? (int)RED_NORM : (int)RED_DOTIN_NORM;
-    for (int red = RED_NONE; red <= RED_DOTIN_NORM && e == hipSuccess; ++red) {
+    const int last_red = op->ns > 0 ? (int)RED_NORM : (int)RED_BICG;
+    for (int red = RED_NONE; red <= RED_BICG && e == hipSuccess; ++red) {
         float best_ms = INFINITY;
         LaunchCfg best = default_launch(op, nrhs);
         if (red > last_red) {
@@ -1009,12 +1012,12 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     {
         wl_op *o = const_cast<wl_op *>(op);
         std::lock_guard<std::mutex> lk(o->mu);
-        for (int red = RED_NONE; red <= RED_DOTIN_NORM; ++red)
+        for (int red = RED_NONE; red <= RED_BICG; ++red)
             o->launch[launch_key(nrhs, red)] = bests[red];
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache_locked();
-    for (int red = RED_NONE; red <= RED_DOTIN_NORM; ++red)
+    for (int red = RED_NONE; red <= RED_BICG; ++red)
         g_tune[tune_key_red(op, nrhs, red)] = bests[red];
     save_tune_cache_locked();
     return WL_OK;
@@ -1048,6 +1051,7 @@ int wl_prof_reset(void)
     for (int i = 0; i < 4; ++i) {
         g_prof_ms[i] = 0;
         g_prof_sites[i] = 0;
+        g_prof_aux[i] = 0;
         g_prof_n[i] = 0;
     }
     return WL_OK;
@@ -1062,6 +1066,16 @@ int wl_prof_read(int prec, long *launches, double *total_ms, double *site_rhs)
     *launches = g_prof_n[prec];
     *total_ms = g_prof_ms[prec];
     *site_rhs = g_prof_sites[prec];
+    return WL_OK;
+}
+
+int wl_prof_read_aux(int prec, double *aux_site_rhs)
+{
+    if (!prec_ok(prec) || !aux_site_rhs)
+        return WL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drain_prof_locked();
+    *aux_site_rhs = g_prof_aux[prec];
     return WL_OK;
 }
 

@@ -145,6 +145,35 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             cx<T> rh[12];
             load_site<P>(p.a3, V, nr, s, r, rh);
             dot(rh, ss, red[1], red[2]);
+        } else if constexpr (OP == B_BI_XRP) {
+            // B_BI_XR and the next B_BI_P in one pass (beta is known before r
+            // is formed, see F_BI_OMEGA_RHO); p' is formed from the r that is
+            // stored, as a separate B_BI_P would load it
+            const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
+            const cx<T> b{(T)sc.beta.x, (T)sc.beta.y};
+            cx<T> x[12], pp[12], ss[12], t[12];
+            load_site<P>(p.y0, V, nr, s, r, x);
+            load_site<P>(p.y2, V, nr, s, r, pp);
+            load_site<P>(p.a1, V, nr, s, r, ss);
+            load_site<P>(p.a2, V, nr, s, r, t);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                x[k] = cfma(a, pp[k], x[k]);
+                x[k] = cfma(om, ss[k], x[k]);
+                ss[k] = cfma(cx<T>{-om.re, -om.im}, t[k], ss[k]);
+            }
+            round_if_scaled<P>(ss);
+            store_site<P>(p.y0, V, nr, s, r, x);
+            store_site<P>(p.y1, V, nr, s, r, ss);
+            red[0] += n2(ss);
+            cx<T> v[12];
+            load_site<P>(p.a3, V, nr, s, r, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const cx<T> d = cfma(cx<T>{-om.re, -om.im}, v[k], pp[k]);
+                pp[k] = cfma(b, d, ss[k]);
+            }
+            store_site<P>(p.y2, V, nr, s, r, pp);
         } else if constexpr (OP == B_COPY) {
             cx<T> v[12];
             load_site<P>(p.a0, V, nr, s, r, v);
@@ -171,7 +200,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             red[2] += n2(b);
         }
     }
-    constexpr int NV = (OP == B_RES || OP == B_CG_XR || OP == B_BI_S || OP == B_NORM) ? 1
+    constexpr int NV = (OP == B_RES || OP == B_CG_XR || OP == B_BI_S || OP == B_NORM || OP == B_BI_XRP) ? 1
                        : (OP == B_BI_XR || OP == B_DOT_NORM)                          ? 3
                                                                                        : 0;
     if constexpr (NV > 0) {
@@ -187,7 +216,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
 int blas_nval(int op)
 {
     switch (op) {
-    case B_RES: case B_CG_XR: case B_BI_S: case B_NORM: return 1;
+    case B_RES: case B_CG_XR: case B_BI_S: case B_NORM: case B_BI_XRP: return 1;
     case B_BI_XR: case B_DOT_NORM: return 3;
     default: return 0;
     }
@@ -208,6 +237,7 @@ static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hip
     case B_NORM: hipLaunchKernelGGL((blas_kernel<P, B_NORM>), g, b, 0, st, p); break;
     case B_DOT_NORM: hipLaunchKernelGGL((blas_kernel<P, B_DOT_NORM>), g, b, 0, st, p); break;
     case B_CG_RESTART: hipLaunchKernelGGL((blas_kernel<P, B_CG_RESTART>), g, b, 0, st, p); break;
+    case B_BI_XRP: hipLaunchKernelGGL((blas_kernel<P, B_BI_XRP>), g, b, 0, st, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -277,7 +307,7 @@ hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e,
 // Rows are summed G at a time; a pass loads U values of each of the G rows
 // per thread before it adds any of them.
 constexpr int FIN_THREADS = 1024;
-constexpr int FIN_MAX = 3 * 64;  // values x right-hand sides per partial set
+constexpr int FIN_MAX = RED_NVAL_MAX * 64;  // values x right-hand sides per partial set
 constexpr int FIN_G = 4;         // rows summed per pass (one pass for the usual 1..4 rows)
 constexpr int FIN_U = 4;         // loads per thread per row and pass
 
@@ -473,6 +503,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         sc.rho_prev = sc.rho;  // <rh, r0> with rh = r0
         sc.alpha = sc.omega = one;
         sc.beta = zero;  // p = v = 0 -> first p = r
+        sc.brk = 0;
         sc.flag = 0;
         sc.conv_iter = 0;
         if (!finite2(sc.rr) || !finite2(sc.bb))
@@ -541,6 +572,70 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
                 break;
             } else
                 sc.flag = 2;
+        } else if (sc.flag == 1 && sc.conv_iter == p.iter + 1) {
+            sc.rr = rr;  // converged on |s| this iteration: r = s
+        }
+        sc.beta = zero;
+        sc.alpha = zero;
+        sc.omega = zero;
+        sc.frozen = 1;  // end of the iteration with flag != 0
+        break;
+    }
+    case F_BI_OMEGA_RHO: {
+        // as F_BI_OMEGA; then, with r' = s - omega t still to be formed,
+        // rho' = <rh, r'> = <rh, s> - omega <rh, t> and beta = (rho'/rho)(alpha/omega)
+        const double ss = sA[r];
+        const double st_re = sB[r], st_im = sB[nr + r], tt = sB[2 * nr + r];
+        const double2 hs = make_double2(sB[3 * nr + r], sB[4 * nr + r]);
+        const double2 ht = make_double2(sB[5 * nr + r], sB[6 * nr + r]);
+        sc.ss = ss;
+        sc.brk = 0;
+        sc.beta = zero;
+        if (sc.flag == 0) {
+            if (!finite2(ss) || !finite2(tt) || !finite2(st_re) || !finite2(st_im))
+                sc.flag = 3;
+            else if (ss <= sc.tol2 * sc.bb) {  // x += alpha p ; r = s  (omega = 0)
+                sc.flag = 1;
+                sc.conv_iter = p.iter + 1;
+            } else if (tt > 0.0) {
+                const double2 om = make_double2(st_re / tt, -st_im / tt);
+                sc.omega = om;
+                const double2 rho_new = make_double2(hs.x - (om.x * ht.x - om.y * ht.y), hs.y - (om.x * ht.y + om.y * ht.x));
+                const double om2 = om.x * om.x + om.y * om.y;
+                const double rho2 = sc.rho.x * sc.rho.x + sc.rho.y * sc.rho.y;
+                if (!finite2(rho_new.x) || !finite2(rho_new.y))
+                    sc.brk = 2;
+                else if (om2 > 0.0 && rho2 > 0.0 && (rho_new.x != 0.0 || rho_new.y != 0.0)) {
+                    const double2 q1 = make_double2((rho_new.x * sc.rho.x + rho_new.y * sc.rho.y) / rho2,
+                                                    (rho_new.y * sc.rho.x - rho_new.x * sc.rho.y) / rho2);
+                    const double2 q2 = make_double2((sc.alpha.x * om.x + sc.alpha.y * om.y) / om2,
+                                                    (sc.alpha.y * om.x - sc.alpha.x * om.y) / om2);
+                    sc.beta = make_double2(q1.x * q2.x - q1.y * q2.y, q1.x * q2.y + q1.y * q2.x);
+                    sc.rho_prev = sc.rho;
+                    sc.rho = rho_new;
+                } else
+                    sc.brk = 1;
+                break;
+            } else
+                sc.flag = 2;
+        } else
+            sc.alpha = zero;
+        sc.omega = zero;
+        break;
+    }
+    case F_BI_CONV: {
+        const double rr = sA[r];
+        if (sc.flag == 0) {
+            sc.rr = rr;
+            if (!finite2(rr) || sc.brk == 2)
+                sc.flag = 3;
+            else if (rr <= sc.tol2 * sc.bb) {
+                sc.flag = 1;
+                sc.conv_iter = p.iter + 1;
+            } else if (sc.brk == 1)
+                sc.flag = 2;
+            else
+                break;
         } else if (sc.flag == 1 && sc.conv_iter == p.iter + 1) {
             sc.rr = rr;  // converged on |s| this iteration: r = s
         }

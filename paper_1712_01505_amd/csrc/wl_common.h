@@ -416,6 +416,24 @@ __device__ __forceinline__ uint32_t slab_site(uint32_t b, uint32_t tid, uint32_t
 }
 
 // ---------------------------------------------------------------- reductions
+// RED_BICG values of one site, added to r[0..6]: <in, out> (re, im), |out|^2,
+// <v, in> (re, im), <v, out> (re, im); <a, b> = sum conj(a) b, in FP64.
+template <typename T>
+__device__ __forceinline__ void bicg_values(const cx<T> (&in)[12], const cx<T> (&out)[12], const cx<T> (&v)[12],
+                                            double *r)
+{
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const double ir = in[k].re, ii = in[k].im, orr = out[k].re, oi = out[k].im, vr = v[k].re, vi = v[k].im;
+        r[0] = fma(ir, orr, fma(ii, oi, r[0]));
+        r[1] = fma(ir, oi, fma(-ii, orr, r[1]));
+        r[2] = fma(orr, orr, fma(oi, oi, r[2]));
+        r[3] = fma(vr, ir, fma(vi, ii, r[3]));
+        r[4] = fma(vr, ii, fma(-vi, ir, r[4]));
+        r[5] = fma(vr, orr, fma(vi, oi, r[5]));
+        r[6] = fma(vr, oi, fma(-vi, orr, r[6]));
+    }
+}
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll

@@ -135,7 +135,7 @@ template <int P, int DAG, int RED>
 __global__ __launch_bounds__(256) void eo_hop_kernel(EoParams p)
 {
     using T = typename Traits<P>::real;
-    constexpr int NV = RED == RED_NORM ? 1 : RED == RED_DOTV ? 2 : RED == RED_DOTIN_NORM ? 3 : 0;
+    constexpr int NV = red_nval(RED);
     __shared__ double lds[(NV > 0 ? NV : 1) * 4];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
@@ -201,6 +201,11 @@ __global__ __launch_bounds__(256) void eo_hop_kernel(EoParams p)
             red[0] = re;
             red[1] = im;
         }
+        if constexpr (RED == RED_BICG) {  // self = the Schur input s, dotv = rh
+            cx<T> v[12];
+            load_site<P>(p.dotv, p.Vh, p.nrhs, i, rhs, v);
+            bicg_values(sf, o, v, red);
+        }
     }
     if constexpr (NV > 0) {
         block_sum<NV>(red, lds);
@@ -244,6 +249,7 @@ hipError_t launch_eo_hop(int prec, int dagger, int red, EoParams p, hipStream_t 
     case RED_NORM: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_NORM>), g, b, 0, st, p); break;              \
     case RED_DOTV: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_DOTV>), g, b, 0, st, p); break;              \
     case RED_DOTIN_NORM: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_DOTIN_NORM>), g, b, 0, st, p); break;  \
+    case RED_BICG: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_BICG>), g, b, 0, st, p); break;              \
     default: return hipErrorInvalidValue;                                                                      \
     }
     switch (prec * 2 + (dagger ? 1 : 0)) {

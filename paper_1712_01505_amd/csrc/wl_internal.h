@@ -49,8 +49,15 @@ enum Red {
     RED_NONE = 0,
     RED_NORM = 1,      // |out|^2                           (1 value)
     RED_DOTV = 2,      // <v, out> with v = aux              (2 values: re, im)
-    RED_DOTIN_NORM = 3 // <in, out> and |out|^2              (3 values)
+    RED_DOTIN_NORM = 3,// <in, out> and |out|^2              (3 values)
+    RED_BICG = 4       // <in, out>, |out|^2, <v, in>, <v, out> with v = aux (7 values;
+                       // BiCGStab's second product: omega and the next rho together)
 };
+constexpr int RED_NVAL_MAX = 7;  // values per right-hand side of the largest reduction
+__host__ __device__ constexpr int red_nval(int red)
+{
+    return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : red == RED_BICG ? 7 : 0;
+}
 
 struct StencilParams {
     const void *U;
@@ -167,6 +174,7 @@ struct Scalars {
     int conv_iter;
     int frozen;           // set at the end of an iteration once flag != 0: loop kernels skip the column
     int restart;          // CGNR reliable update without progress: restart the search direction
+    int brk;              // merged BiCGStab: 1 rho or omega degenerate, 2 non-finite (acted on at F_BI_CONV)
 };
 
 enum BlasOp {
@@ -180,11 +188,14 @@ enum BlasOp {
     B_ZERO = 7,       // y = 0
     B_NORM = 8,       // |x|^2
     B_DOT_NORM = 9,   // <a0, a1> and |a1|^2  (3 values)
-    B_CG_RESTART = 10 // p = z for columns whose restart flag is set
+    B_CG_RESTART = 10,// p = z for columns whose restart flag is set
+    B_BI_XRP = 11     // x += alpha p + omega s ; r = s - omega t ; p = r + beta (p - omega v) ; |r|^2
+                      // (y0 = x, y1 = r, y2 = p, a1 = s, a2 = t, a3 = v)
 };
 struct BlasParams {
     void *y0;          // first output / in-out vector
     void *y1;          // second output / in-out vector
+    void *y2;          // third in-out vector (B_BI_XRP: p)
     const void *a0, *a1, *a2, *a3;  // inputs
     const Scalars *sc;
     double *partials;
@@ -212,7 +223,10 @@ enum FinOp {
     F_SUM = 7,        // just reduce set A into out[] (nval x nrhs)
     F_BI_RELIABLE = 8, // after a reliable update replaced r: A = (<rh, r>, |r|^2) -> rr,
                        // convergence, rho and beta = (rho'/rho_prev)(alpha/omega)
-    F_CG_RELIABLE = 9  // CGNR after a reliable update replaced r and z = D^dag r: A = |r|^2, B = |z|^2
+    F_CG_RELIABLE = 9, // CGNR after a reliable update replaced r and z = D^dag r: A = |r|^2, B = |z|^2
+    F_BI_OMEGA_RHO = 10, // merged BiCGStab: A = |s|^2, B = RED_BICG of t = D s with v = rh:
+                         // omega, then rho' = <rh, s> - omega <rh, t> and beta before r is formed
+    F_BI_CONV = 11       // merged BiCGStab, end of an iteration: A = |r|^2 -> convergence / stop
 };
 struct FinParams {
     const double *A;

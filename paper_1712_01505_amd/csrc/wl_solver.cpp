@@ -45,7 +45,7 @@ size_t vec_bytes(int prec, uint32_t V, int nrhs) { return (size_t)nrhs * V * spi
 size_t max_nblk(uint32_t V, int Lt) { return (V + 63) / 64 + (size_t)Lt + 8; }
 size_t partial_bytes(uint32_t V, int Lt, int nrhs)
 {
-    return align_up(3 * (size_t)nrhs * max_nblk(V, Lt) * sizeof(double));
+    return align_up(RED_NVAL_MAX * (size_t)nrhs * max_nblk(V, Lt) * sizeof(double));
 }
 
 struct Arena {
@@ -246,12 +246,13 @@ struct Engine {
     }
 
     int blas(int bop, void *y0, void *y1, const void *a0, const void *a1, const void *a2, const void *a3, int slot,
-             bool loop = false)
+             bool loop = false, void *y2 = nullptr)
     {
         BlasParams p{};
         p.skip_frozen = loop ? 1 : 0;
         p.y0 = y0;
         p.y1 = y1;
+        p.y2 = y2;
         p.a0 = a0;
         p.a1 = a1;
         p.a2 = a2;
@@ -290,7 +291,7 @@ struct Engine {
         p.out = sums;
         // the host reads the status at iteration ends only: the mid-iteration
         // steps skip the (PCIe) mirror writes
-        const bool mid = fop == F_CG_ALPHA || fop == F_BI_ALPHA || fop == F_BI_OMEGA;
+        const bool mid = fop == F_CG_ALPHA || fop == F_BI_ALPHA || fop == F_BI_OMEGA || fop == F_BI_OMEGA_RHO;
         p.hflag = mid ? nullptr : hb->dflag;
         p.hrr = mid ? nullptr : hb->drr;
         p.nrhs = nrhs;
@@ -399,9 +400,15 @@ struct Engine {
             }
         } else {
             void *rh = v[1], *p = v[2], *vv = v[3], *s = v[4], *t = v[5];
+            // Merged iteration (no reliable-update hook, which replaces r
+            // between iterations): the second product also yields <rh, s>
+            // and <rh, t>, so rho' and beta are known before r' = s - omega t
+            // is formed and one pass updates x, r and the next p.
+            const bool merged = !on_iter && op->ns == 0;
             if ((rc = blas(B_COPY, rh, nullptr, r, nullptr, nullptr, nullptr, -1)))
                 return rc;
-            if ((rc = blas(B_ZERO, p, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+            if ((rc = merged ? blas(B_COPY, p, nullptr, r, nullptr, nullptr, nullptr, -1)
+                             : blas(B_ZERO, p, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return rc;
             if ((rc = blas(B_ZERO, vv, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return rc;
@@ -409,7 +416,26 @@ struct Engine {
                 return rc;
             WL_TRY(hipStreamSynchronize(st));
             bool stop = host_all_done();
-            while (!stop && it < maxiter) {
+            while (merged && !stop && it < maxiter) {
+                if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0, true)))
+                    return rc;
+                if ((rc = fin(F_BI_ALPHA, 0, -1, -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_BI_S, s, nullptr, r, vv, nullptr, nullptr, 0, true)))
+                    return rc;
+                if ((rc = stencil(t, s, 0, RED_BICG, rh, 1, true)))
+                    return rc;
+                if ((rc = fin(F_BI_OMEGA_RHO, 0, 1, -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_BI_XRP, x, r, nullptr, s, t, vv, 0, true, p)))
+                    return rc;
+                if ((rc = fin(F_BI_CONV, 0, -1, -1, it, tol2)))
+                    return rc;
+                if ((rc = mark(it, &stop)))
+                    return rc;
+                ++it;
+            }
+            while (!merged && !stop && it < maxiter) {
                 if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1, true)))
                     return rc;
                 if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0, true)))

@@ -356,7 +356,7 @@ template <int P, int DAG, int RED, int APPLY>
 __global__ __launch_bounds__(512) void twalk_kernel(StencilParams p, int T, uint32_t nxyz, uint32_t nbxyz)
 {
     using R_ = typename Traits<P>::real;
-    constexpr int NV = RED == RED_NORM ? 1 : RED == RED_DOTV ? 2 : RED == RED_DOTIN_NORM ? 3 : 0;
+    constexpr int NV = red_nval(RED);
     constexpr int SF = DAG ? 1 : -1;  // forward hops use (1 + SF g), backward (1 - SF g)
     constexpr int G = TwalkG<P>::G;
     constexpr bool CARRY = TwalkG<P>::CARRY_SELF;
@@ -507,6 +507,11 @@ __global__ __launch_bounds__(512) void twalk_kernel(StencilParams p, int T, uint
                     red[1] = fma((double)v[i].re, (double)o[i].im, fma(-(double)v[i].im, (double)o[i].re, red[1]));
                 }
             }
+            if constexpr (RED == RED_BICG) {
+                cx<R_> v[12];
+                load_site<P>(p.aux, p.V, p.nrhs, s, rhs, v);
+                bicg_values(self, o, v, red);  // accumulates over the t-walk
+            }
             if constexpr (CARRY) {  // the forward neighbour becomes the next site
                 if constexpr (Traits<P>::SCALED)
                     scale_site<P>(nxt, rf.sc);
@@ -587,7 +592,7 @@ template <int P, int DAG, int R, int RED, int APPLY, int VAR>
 __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 {
     using T = typename Traits<P>::real;
-    constexpr int NV = RED == RED_NORM ? 1 : RED == RED_DOTV ? 2 : RED == RED_DOTIN_NORM ? 3 : 0;
+    constexpr int NV = red_nval(RED);
     __shared__ double lds[(NV > 0 ? NV : 1) * (R > 1 ? R : 8) * 8];
     int grp;
     const uint32_t bt = tile_group(p, grp);
@@ -668,6 +673,12 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
                     n2 = fma((double)o[k].re, (double)o[k].re, fma((double)o[k].im, (double)o[k].im, n2));
                 red[NV * r + NV - 1] = n2;
             }
+            if constexpr (RED == RED_BICG) {
+                cx<T> in[12], v[12];
+                load_site<P>(p.in, p.V, p.nrhs, s, r0 + r, in);
+                load_site<P>(p.aux, p.V, p.nrhs, s, r0 + r, v);
+                bicg_values(in, o, v, &red[NV * r]);
+            }
             if constexpr (RED == RED_DOTV) {
                 cx<T> v[12];
                 load_site<P>(p.aux, p.V, p.nrhs, s, r0 + r, v);
@@ -711,7 +722,7 @@ bool slab_ok(const int *L, int block, int mode)
     return L[2] % 8 == 0 && L[1] % (1 << (mode - 2)) == 0 && slab % (uint64_t)block == 0;
 }
 
-int stencil_nval(int red) { return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : 0; }
+int stencil_nval(int red) { return red_nval(red); }
 
 // Tile count and right-hand-side groups of a launch (see tile_group).
 static void set_groups(StencilParams &p, uint32_t tiles, uint32_t ng)
@@ -749,6 +760,7 @@ static hipError_t launch_v(dim3 grid, dim3 block, const StencilParams &p, hipStr
     case RED_DOTIN_NORM:
         hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTIN_NORM, 1, VAR>), grid, block, 0, st, p);
         break;
+    case RED_BICG: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_BICG, 1, VAR>), grid, block, 0, st, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -780,6 +792,7 @@ static hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_
     case RED_DOTIN_NORM:
         hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_DOTIN_NORM, 1>), grid, block, 0, st, p, T, nxyz, nbxyz);
         break;
+    case RED_BICG: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_BICG, 1>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -34,7 +34,7 @@ EXPORTS = [
     "wl_field_bytes", "wl_pack_gauge", "wl_pack_spinor", "wl_unpack_spinor", "wl_convert_spinor",
     "wl_op_create", "wl_op_destroy", "wilson_dslash", "wilson_apply", "wl_solver_workspace_bytes",
     "solve_cgnr", "solve_bicgstab", "wilson_gauge_force", "wilson_multi_apply", "wl_autotune",
-    "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read",
+    "wl_get_launch", "wl_set_launch", "wl_prof_enable", "wl_prof_reset", "wl_prof_read", "wl_prof_read_aux",
     "wl_stream_copy", "wl_strerror", "wl_last_hip_error", "wl_multi_plan_create", "wl_multi_plan_run",
     "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
     "wl_dw_op_create", "dwf_apply", "wl_halo_bytes", "wilson_apply_halo", "wl_eo_split", "wl_eo_merge",
@@ -122,6 +122,7 @@ def lib():
         "wl_prof_enable": [I],
         "wl_prof_reset": [],
         "wl_prof_read": [I, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D), ctypes.POINTER(D)],
+        "wl_prof_read_aux": [I, ctypes.POINTER(D)],
         "wl_stream_copy": [P, P, SZ, P],
         "wl_strerror": [I],
         "wl_last_hip_error": [],
@@ -315,6 +316,12 @@ def wl_prof_read(prec):
     n, ms, sites = ctypes.c_long(), ctypes.c_double(), ctypes.c_double()
     _check(lib().wl_prof_read(prec, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(sites)), "wl_prof_read")
     return n.value, ms.value, sites.value
+
+
+def wl_prof_read_aux(prec):
+    aux = ctypes.c_double()
+    _check(lib().wl_prof_read_aux(prec, ctypes.byref(aux)), "wl_prof_read_aux")
+    return aux.value
 
 
 # ---------------------------------------------------------------- torch conveniences
