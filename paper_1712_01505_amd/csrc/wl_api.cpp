@@ -246,28 +246,39 @@ LaunchCfg launch_for(const wl_op *op, int nrhs, int red)
         auto it = o->launch.find(launch_key(nrhs, red));
         if (it != o->launch.end())
             return it->second;
-        if (red != RED_NONE) {
-            auto it0 = o->launch.find(launch_key(nrhs, RED_NONE));
-            if (it0 != o->launch.end())
-                return it0->second;
-        }
     }
+    // first use of this (nrhs, reduction): the tune cache's entry for the
+    // reduction, else this op's plain-apply choice, else the cache's
+    // plain-apply entry, else the default
     LaunchCfg c = default_launch(op, nrhs);
-    bool found = false;
+    bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_cache_locked();
-        for (int r : {red, (int)RED_NONE}) {
-            auto it = g_tune.find(tune_key_red(op, nrhs, r));
-            if (it != g_tune.end() && launch_ok(op, nrhs, it->second)) {
-                c = it->second;
-                found = r == red;
-                break;
+        auto it = g_tune.find(tune_key_red(op, nrhs, red));
+        if (it != g_tune.end() && launch_ok(op, nrhs, it->second)) {
+            c = it->second;
+            have = true;
+        }
+    }
+    if (!have && red != RED_NONE) {
+        {
+            std::lock_guard<std::mutex> lk(o->mu);
+            auto it0 = o->launch.find(launch_key(nrhs, RED_NONE));
+            if (it0 != o->launch.end()) {
+                c = it0->second;
+                have = true;
             }
+        }
+        if (!have) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(tune_key_red(op, nrhs, RED_NONE));
+            if (it != g_tune.end() && launch_ok(op, nrhs, it->second))
+                c = it->second;
         }
     }
     std::lock_guard<std::mutex> lk(o->mu);
-    o->launch[launch_key(nrhs, found ? red : (int)RED_NONE)] = c;
+    o->launch[launch_key(nrhs, red)] = c;
     return c;
 }
 
