@@ -226,11 +226,12 @@ int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int 
  * precision (Sec. II-C: the inner low-precision solver sets the speed).
  * With domain-wall ops (wl_dw_op_create; hi and lo with equal Ns, m0, m)
  * only solve_cgnr is offered and nrhs counts 5-d vectors.
- * Without reliable updates BiCGStab runs a merged iteration: the second
+ * BiCGStab runs a merged iteration: the second
  * product also returns <rh, s> and <rh, t>, so rho' = <rh, s> - omega <rh, t>
  * and beta are known before r' = s - omega t is formed, and one pass updates
  * x, r and the next p (the same recurrences; two vector passes and one
- * kernel fewer per iteration).
+ * kernel fewer per iteration; an iteration followed by a reliable update
+ * updates x and r only, and the next forms p from the replaced r).
  * stats: array of nrhs entries (may be NULL).  Synchronises `stream`.
  * Returns the worst status over right-hand sides. */
 int solve_cgnr(const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *p,

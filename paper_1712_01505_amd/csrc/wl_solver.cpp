@@ -160,6 +160,11 @@ struct Engine {
     // Called after each queued BiCGStab iteration that did not stop the run
     // (the reliable-update check of the mixed solver).
     std::function<int(int)> on_iter;
+    // The same check split in two for the merged BiCGStab iteration: whether
+    // iteration it ends with a reliable update (asked before its last BLAS
+    // pass, which then leaves p alone), and the update itself.
+    std::function<bool(int)> rel_decide;
+    std::function<int(int)> rel_act;
 
     int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, HostBufs *h, bool even_odd = false)
     {
@@ -404,7 +409,8 @@ struct Engine {
             // between iterations): the second product also yields <rh, s>
             // and <rh, t>, so rho' and beta are known before r' = s - omega t
             // is formed and one pass updates x, r and the next p.
-            const bool merged = !on_iter && op->ns == 0;
+            const bool merged = op->ns == 0 && (!on_iter || (rel_decide && rel_act));
+            bool pending_p = false;  // merged: a reliable update replaced r, p is formed from it next
             if ((rc = blas(B_COPY, rh, nullptr, r, nullptr, nullptr, nullptr, -1)))
                 return rc;
             if ((rc = merged ? blas(B_COPY, p, nullptr, r, nullptr, nullptr, nullptr, -1)
@@ -417,6 +423,11 @@ struct Engine {
             WL_TRY(hipStreamSynchronize(st));
             bool stop = host_all_done();
             while (merged && !stop && it < maxiter) {
+                if (pending_p) {  // p = r + beta (p - omega v) with the replaced r and its beta
+                    if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1, true)))
+                        return rc;
+                    pending_p = false;
+                }
                 if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0, true)))
                     return rc;
                 if ((rc = fin(F_BI_ALPHA, 0, -1, -1, it, tol2)))
@@ -427,12 +438,24 @@ struct Engine {
                     return rc;
                 if ((rc = fin(F_BI_OMEGA_RHO, 0, 1, -1, it, tol2)))
                     return rc;
-                if ((rc = blas(B_BI_XRP, x, r, nullptr, s, t, vv, 0, true, p)))
+                // the host has the status through iteration it - 1 at most, so
+                // the check runs as it would have after that iteration
+                const bool upd = rel_decide && rel_decide(it - 1);
+                if (upd) {  // x and r only: p follows the replaced r
+                    if ((rc = blas(B_BI_XR, x, r, p, s, t, rh, 0, true)))
+                        return rc;
+                } else if ((rc = blas(B_BI_XRP, x, r, nullptr, s, t, vv, 0, true, p))) {
                     return rc;
-                if ((rc = fin(F_BI_CONV, 0, -1, -1, it, tol2)))
+                }
+                if ((rc = fin(F_BI_CONV, 0, -1, -1, it, tol2)))  // |r|^2 is the first value of either
                     return rc;
                 if ((rc = mark(it, &stop)))
                     return rc;
+                if (upd && !stop) {
+                    if ((rc = rel_act(it)))
+                        return rc;
+                    pending_p = true;
+                }
                 ++it;
             }
             while (!merged && !stop && it < maxiter) {
@@ -667,9 +690,9 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         // room for the rounding of the iterated residual
         L.tol2v = tol2_dev;
         const double d2 = delta * delta;
-        L.on_iter = [&](int it) -> int {
+        auto decide = [&](int it) -> bool {
             if (it < next_read)
-                return WL_OK;
+                return false;
             const volatile int *hf = lease.b->hflag;
             const volatile double *hr = lease.b->hrr;
             // update when the iterated residual has dropped by delta, and also
@@ -687,8 +710,9 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
                 else if (v < d2 * rmax[r])
                     need = true;
             }
-            if (!need)
-                return WL_OK;
+            return need;
+        };
+        auto act = [&](int it) -> int {
             last_gap = it - last_update;
             last_update = it;
             int e;
@@ -726,6 +750,11 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
                 rmax[r] = 0.0;
             return WL_OK;
         };
+        L.on_iter = [decide, act](int it) -> int { return decide(it) ? act(it) : WL_OK; };
+        if (solver == WL_SOLVER_BICGSTAB) {
+            L.rel_decide = decide;
+            L.rel_act = act;
+        }
     }
     for (;;) {
         if ((rc = H.true_res2(x, b, rr)))
