@@ -528,61 +528,9 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         sc.alpha = zero;
         break;
     }
-    case F_BI_OMEGA: {
-        const double ss = sA[r];
-        const double st_re = sB[r], st_im = sB[nr + r], tt = sB[2 * nr + r];
-        sc.ss = ss;
-        if (sc.flag == 0) {
-            if (!finite2(ss) || !finite2(tt) || !finite2(st_re) || !finite2(st_im))
-                sc.flag = 3;
-            else if (ss <= sc.tol2 * sc.bb) {  // x += alpha p ; r = s  (omega = 0)
-                sc.flag = 1;
-                sc.conv_iter = p.iter + 1;
-            } else if (tt > 0.0) {  // omega = <t, s> / <t, t> = conj(<s, t>) / |t|^2
-                sc.omega = make_double2(st_re / tt, -st_im / tt);
-                break;
-            } else
-                sc.flag = 2;
-        } else
-            sc.alpha = zero;
-        sc.omega = zero;
-        break;
-    }
-    case F_BI_RHO: {
-        const double rr = sA[r];
-        const double2 rho_new = make_double2(sA[nr + r], sA[2 * nr + r]);
-        if (sc.flag == 0) {
-            sc.rr = rr;
-            const double om2 = sc.omega.x * sc.omega.x + sc.omega.y * sc.omega.y;
-            const double rho2 = sc.rho.x * sc.rho.x + sc.rho.y * sc.rho.y;
-            if (!finite2(rr) || !finite2(rho_new.x) || !finite2(rho_new.y))
-                sc.flag = 3;
-            else if (rr <= sc.tol2 * sc.bb) {
-                sc.flag = 1;
-                sc.conv_iter = p.iter + 1;
-            } else if (om2 > 0.0 && rho2 > 0.0 && (rho_new.x != 0.0 || rho_new.y != 0.0)) {
-                // beta = (rho_new / rho) (alpha / omega)
-                const double2 q1 = make_double2((rho_new.x * sc.rho.x + rho_new.y * sc.rho.y) / rho2,
-                                                (rho_new.y * sc.rho.x - rho_new.x * sc.rho.y) / rho2);
-                const double2 q2 = make_double2((sc.alpha.x * sc.omega.x + sc.alpha.y * sc.omega.y) / om2,
-                                                (sc.alpha.y * sc.omega.x - sc.alpha.x * sc.omega.y) / om2);
-                sc.beta = make_double2(q1.x * q2.x - q1.y * q2.y, q1.x * q2.y + q1.y * q2.x);
-                sc.rho_prev = sc.rho;
-                sc.rho = rho_new;
-                break;
-            } else
-                sc.flag = 2;
-        } else if (sc.flag == 1 && sc.conv_iter == p.iter + 1) {
-            sc.rr = rr;  // converged on |s| this iteration: r = s
-        }
-        sc.beta = zero;
-        sc.alpha = zero;
-        sc.omega = zero;
-        sc.frozen = 1;  // end of the iteration with flag != 0
-        break;
-    }
     case F_BI_OMEGA_RHO: {
-        // as F_BI_OMEGA; then, with r' = s - omega t still to be formed,
+        // omega = <t, s> / <t, t> (or stop: converged on |s|, t = 0, NaN);
+        // then, with r' = s - omega t still to be formed,
         // rho' = <rh, r'> = <rh, s> - omega <rh, t> and beta = (rho'/rho)(alpha/omega)
         const double ss = sA[r];
         const double st_re = sB[r], st_im = sB[nr + r], tt = sB[2 * nr + r];

@@ -167,7 +167,7 @@ struct Scalars {
     double zz;            // CGNR |z|^2
     double ss;            // BiCGStab |s|^2
     double2 alpha, beta, omega, rho;
-    double2 rho_prev;     // BiCGStab: rho before the last F_BI_RHO (for reliable updates)
+    double2 rho_prev;     // BiCGStab: rho before the last F_BI_OMEGA_RHO (for reliable updates)
     double tol2;          // converge when rr <= tol2 * bb
     double rr_upd;        // reliable updates: |r|^2 after the previous update (or at the start)
     int flag;             // 0 running, 1 converged, 2 breakdown, 3 NaN/Inf
@@ -218,8 +218,6 @@ enum FinOp {
     F_CG_BETA = 2,    // vals: |r|^2 (A), |z|^2 (B)
     F_INIT_BI = 3,    // vals: |r|^2 (A), bb (C)
     F_BI_ALPHA = 4,   // vals: <rh, v>
-    F_BI_OMEGA = 5,   // vals: |s|^2 (A), <s,t>, |t|^2 (B)
-    F_BI_RHO = 6,     // vals: |r|^2, <rh, r> (A)
     F_SUM = 7,        // just reduce set A into out[] (nval x nrhs)
     F_BI_RELIABLE = 8, // after a reliable update replaced r: A = (<rh, r>, |r|^2) -> rr,
                        // convergence, rho and beta = (rho'/rho_prev)(alpha/omega)

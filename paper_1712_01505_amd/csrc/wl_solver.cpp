@@ -157,12 +157,12 @@ struct Engine {
     bool eo = false;       // even-odd: vectors are even half fields, the operator is the Schur complement
     void *eo_tmp = nullptr;  // odd half field for H_oe in
     const double *tol2v = nullptr;  // optional per-column tolerance^2 (device)
-    // Called after each queued BiCGStab iteration that did not stop the run
+    // Called after each queued CGNR iteration that did not stop the run
     // (the reliable-update check of the mixed solver).
     std::function<int(int)> on_iter;
-    // The same check split in two for the merged BiCGStab iteration: whether
-    // iteration it ends with a reliable update (asked before its last BLAS
-    // pass, which then leaves p alone), and the update itself.
+    // The same check for BiCGStab, split in two: whether iteration it ends
+    // with a reliable update (asked before its last BLAS pass, which then
+    // leaves p alone), and the update itself.
     std::function<bool(int)> rel_decide;
     std::function<int(int)> rel_act;
 
@@ -296,7 +296,7 @@ struct Engine {
         p.out = sums;
         // the host reads the status at iteration ends only: the mid-iteration
         // steps skip the (PCIe) mirror writes
-        const bool mid = fop == F_CG_ALPHA || fop == F_BI_ALPHA || fop == F_BI_OMEGA || fop == F_BI_OMEGA_RHO;
+        const bool mid = fop == F_CG_ALPHA || fop == F_BI_ALPHA || fop == F_BI_OMEGA_RHO;
         p.hflag = mid ? nullptr : hb->dflag;
         p.hrr = mid ? nullptr : hb->drr;
         p.nrhs = nrhs;
@@ -405,16 +405,17 @@ struct Engine {
             }
         } else {
             void *rh = v[1], *p = v[2], *vv = v[3], *s = v[4], *t = v[5];
-            // Merged iteration (no reliable-update hook, which replaces r
-            // between iterations): the second product also yields <rh, s>
-            // and <rh, t>, so rho' and beta are known before r' = s - omega t
-            // is formed and one pass updates x, r and the next p.
-            const bool merged = op->ns == 0 && (!on_iter || (rel_decide && rel_act));
-            bool pending_p = false;  // merged: a reliable update replaced r, p is formed from it next
+            // Merged iteration: the second product also yields <rh, s> and
+            // <rh, t>, so rho' and beta are known before r' = s - omega t is
+            // formed and one pass updates x, r and the next p.  An iteration
+            // followed by a reliable update updates x and r only; the next
+            // one forms p from the replaced r.
+            if (op->ns > 0)
+                return WL_EINVAL;  // BiCGStab is offered for the Wilson operator only
+            bool pending_p = false;  // a reliable update replaced r: p is formed from it next
             if ((rc = blas(B_COPY, rh, nullptr, r, nullptr, nullptr, nullptr, -1)))
                 return rc;
-            if ((rc = merged ? blas(B_COPY, p, nullptr, r, nullptr, nullptr, nullptr, -1)
-                             : blas(B_ZERO, p, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+            if ((rc = blas(B_COPY, p, nullptr, r, nullptr, nullptr, nullptr, -1)))
                 return rc;
             if ((rc = blas(B_ZERO, vv, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return rc;
@@ -422,7 +423,7 @@ struct Engine {
                 return rc;
             WL_TRY(hipStreamSynchronize(st));
             bool stop = host_all_done();
-            while (merged && !stop && it < maxiter) {
+            while (!stop && it < maxiter) {
                 if (pending_p) {  // p = r + beta (p - omega v) with the replaced r and its beta
                     if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1, true)))
                         return rc;
@@ -456,29 +457,6 @@ struct Engine {
                         return rc;
                     pending_p = true;
                 }
-                ++it;
-            }
-            while (!merged && !stop && it < maxiter) {
-                if ((rc = blas(B_BI_P, p, nullptr, r, vv, nullptr, nullptr, -1, true)))
-                    return rc;
-                if ((rc = stencil(vv, p, 0, RED_DOTV, rh, 0, true)))
-                    return rc;
-                if ((rc = fin(F_BI_ALPHA, 0, -1, -1, it, tol2)))
-                    return rc;
-                if ((rc = blas(B_BI_S, s, nullptr, r, vv, nullptr, nullptr, 0, true)))
-                    return rc;
-                if ((rc = stencil(t, s, 0, RED_DOTIN_NORM, nullptr, 1, true)))
-                    return rc;
-                if ((rc = fin(F_BI_OMEGA, 0, 1, -1, it, tol2)))
-                    return rc;
-                if ((rc = blas(B_BI_XR, x, r, p, s, t, rh, 0, true)))
-                    return rc;
-                if ((rc = fin(F_BI_RHO, 0, -1, -1, it, tol2)))
-                    return rc;
-                if ((rc = mark(it, &stop)))
-                    return rc;
-                if (!stop && on_iter && (rc = on_iter(it)))
-                    return rc;
                 ++it;
             }
         }
@@ -750,10 +728,11 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
                 rmax[r] = 0.0;
             return WL_OK;
         };
-        L.on_iter = [decide, act](int it) -> int { return decide(it) ? act(it) : WL_OK; };
         if (solver == WL_SOLVER_BICGSTAB) {
             L.rel_decide = decide;
             L.rel_act = act;
+        } else {
+            L.on_iter = [decide, act](int it) -> int { return decide(it) ? act(it) : WL_OK; };
         }
     }
     for (;;) {
