@@ -317,7 +317,8 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
  * variant         0 straight-line hops; with rhs_per_thread = 1 a
  *                 software-pipelined hop loop 1 (all precisions), 2 (not
  *                 WL_F64), 3 (16-bit formats only), or a t-walk 4, 5, 6
- *                 (columns of 4, 8, 16 sites along t; Lt divisible by that).
+ *                 (columns of 4, 8, 16 sites along t; Lt divisible by that;
+ *                 block <= 256).
  * Results do not depend on the configuration (16-bit t-walk: to rounding). */
 typedef struct {
     int block;

@@ -225,7 +225,7 @@ static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
            nrhs % c.rpt == 0 && lanes_ok && c.xcd >= 0 && c.xcd <= 5 &&
            (c.xcd < 2 || slab_ok(op->g.dims, c.block / c.lanes, c.xcd)) && c.var >= 0 && c.var <= max_var(prec) &&
            var_ok(prec, c.var) && (c.var == 0 || c.rpt == 1) &&
-           (c.var < 4 || op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0);
+           (c.var < 4 || (c.block <= 256 && op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0));
 }
 
 // Launch configurations are kept per (nrhs, fused reduction): the solver's

@@ -353,7 +353,11 @@ struct TwalkG {
 };
 
 template <int P, int DAG, int RED, int APPLY>
-__global__ __launch_bounds__(512) void twalk_kernel(StencilParams p, int T, uint32_t nxyz, uint32_t nbxyz)
+// At most 256 threads per workgroup: the walk's live state (carried spinor,
+// t-term, pipelined hops) needs more than the 256 registers a 512-thread
+// bound leaves (FP64 and FP32 spilled to scratch there); with this bound the
+// compiler can spill into accumulation registers instead.
+__global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint32_t nxyz, uint32_t nbxyz)
 {
     using R_ = typename Traits<P>::real;
     constexpr int NV = red_nval(RED);
@@ -770,7 +774,7 @@ template <int P, int DAG>
 static hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
 {
     const int T = twalk_T(cfg.var);
-    if (p.L[3] % T != 0)
+    if (p.L[3] % T != 0 || cfg.block > 256)
         return hipErrorInvalidValue;
     const uint32_t nxyz = (uint32_t)p.L[0] * p.L[1] * p.L[2];
     const uint32_t nbxyz = (nxyz + cfg.block - 1) / cfg.block;
