@@ -10,9 +10,11 @@
  *       (H psi)(x) = sum_mu [ s+ (1 - g_mu) U_mu(x) psi(x+mu)
  *                           + s- (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ],
  *   where s+/s- are the boundary signs of hops that wrap around the lattice.
- *   Sec. II-C: linear solves D x = b by BiCGStab and by CG on the normal
- *   equations (CGNR); a mixed-precision solve whose inner solver runs in a
- *   lower precision.
+ *   Sec. II-C: linear solves D x = b by BiCGStab (the paper's solver for the
+ *   Wilson matrix) and a mixed-precision solve whose inner solver runs in a
+ *   lower precision.  The paper applies CG to the normal equations D^dag D
+ *   of the domain-wall matrix (Sec. II-C, Sec. VI-B); the library offers the
+ *   same CG on the normal equations (CGNR) for the Wilson matrix as well.
  *   Sec. IV-A: the solver is offloaded from the host code to a separately
  *   tuned library whose fields may take any data layout and type; here that
  *   library is this C ABI, with caller-owned device buffers.
@@ -169,7 +171,7 @@ int wilson_schur_apply(const wl_op *op, void *out_e, const void *in_e, void *tmp
  * D_DW^dag (adjoint hop, P_+ and P_- exchanged).  11520 flop per 4-d site
  * at Ns = 8, i.e. 1440 per 5-d site (Table I).
  * The op borrows U_packed like wl_op_create; Ns in [1, 64].  Such an op
- * takes dwf_apply, solve_cgnr (CG on D_DW^dag D_DW, Sec. V-C; nrhs there
+ * takes dwf_apply, solve_cgnr (CG on D_DW^dag D_DW, Sec. II-C and VI-B; nrhs there
  * counts 5-d vectors, nrhs * Ns <= 64), wl_autotune / wl_get_launch /
  * wl_set_launch (nrhs = 5-d vectors; one slice per thread, variants 0..2)
  * and wl_op_destroy; the Wilson entry points, solve_bicgstab (its spectrum
@@ -181,7 +183,10 @@ int wl_dw_op_create(const wl_geom *g, double m0, double m, int Ns, int prec, con
 int dwf_apply(const wl_op *op, void *out, const void *in, int dagger, int nvec, void *stream);
 
 typedef struct {
-    double tol;           /* stop when ||b - D x|| <= tol ||b|| (true residual, FP64) */
+    double tol;           /* stop when ||b - D x|| <= tol ||b|| (true residual, FP64; the
+                             library accepts at tol (1 - 1e-4), so that an independent FP64
+                             evaluation of the residual, rounded in another order, also
+                             finds <= tol) */
     int maxiter;          /* Krylov iterations (summed over inner solves when mixed) */
     double inner_tol;     /* mixed: defect correction: relative tolerance of each inner solve;
                              reliable updates: residual drop that triggers an FP64 update
@@ -192,11 +197,15 @@ typedef struct {
                              refreshed in place; BiCGStab re-derives rho and beta, CGNR
                              recomputes z = D^dag r and keeps its search direction unless
                              |r| has grown since the previous update).  CGNR with a
-                             16-bit inner op keeps defect correction. */
+                             16-bit inner op takes defect correction only: reliable = 1
+                             returns WL_EPREC for that pairing. */
     int check_every;      /* host convergence check period in iterations (0 = default) */
     int use_x0;           /* 1 = x holds the initial guess on entry, 0 = start from x = 0 */
     int dagger;           /* 1 = solve D^dag x = b (the adjoint system; D^dag = gamma5 D gamma5) */
-    void *workspace;      /* device scratch, NULL = library allocates for the call */
+    void *workspace;      /* device scratch of at least wl_solver_workspace_bytes, owned by
+                             the caller and not used by two concurrent solves; a solve
+                             allocates no device memory itself (NULL or too small:
+                             WL_EWORKSPACE) */
     size_t workspace_bytes;
     int eo;               /* 1 = even-odd preconditioned: solve the Schur system
                              (1 - kappa^2 H_eo H_oe) x_e = b_e + kappa H_eo b_o on the even
@@ -220,8 +229,9 @@ int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int 
 
 /* Solve D x = b for nrhs right-hand sides at once (per-right-hand-side
  * scalars; converged columns are frozen).  x, b: packed spinors of hi's
- * precision.  lo == NULL: plain solve in hi's precision (CGNR: Sec. II-C,
- * CG on D^dag D; BiCGStab: Sec. II-C / V-C).  lo != NULL: mixed precision --
+ * precision.  lo == NULL: plain solve in hi's precision (BiCGStab: Sec. II-C,
+ * Sec. V-C; CGNR: the CG on the normal equations that Sec. II-C and VI-B apply
+ * to the domain-wall matrix, offered for the Wilson matrix too).  lo != NULL: mixed precision --
  * FP64 outer true-residual refinement around an inner solve in lo's
  * precision (Sec. II-C: the inner low-precision solver sets the speed).
  * With domain-wall ops (wl_dw_op_create; hi and lo with equal Ns, m0, m)

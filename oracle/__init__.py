@@ -11,7 +11,7 @@ Paper: Kanamori & Matsufuru, arXiv:1712.01505.
   Sec. II-B   eq. (1), the Wilson fermion matrix
   Sec. II-B   eq. (2), the domain-wall fermion matrix (5-d fields, shape (Ns, Lt, Lz, Ly, Lx, 4, 3))
   Sec. II-C   BiCGStab for the Wilson matrix, CG on the normal equations
-  Sec. V-C    CG on D^dag D for the domain-wall matrix
+  Sec. II-C, Sec. VI-B   CG on D^dag D for the domain-wall matrix
 
 Array conventions (numpy, complex128, canonical):
   spinor  shape (Lt, Lz, Ly, Lx, 4, 3)

@@ -442,7 +442,7 @@ void oracle_dw_apply(const int *L, const int *bc, int Ns, double m0, double m, c
 }
 
 /* CG on the normal equations of the domain-wall matrix, D^dag D x = D^dag b
- * (Sec. V-C: the paper applies CG to D^dag D for this operator), following
+ * (Sec. II-C and Sec. VI-B: the paper applies CG to D^dag D for this operator), following
  * the same textbook steps as oracle_cgnr (Saad, Alg. 8.4).  x holds the
  * initial guess.  Returns 0 if the true relative residual ||b - D x|| / ||b||
  * is <= tol, 1 otherwise. */

@@ -681,11 +681,17 @@ static int solve_entry(int solver, const wl_op *hi, const wl_op *lo, void *x, co
         p->maxiter < 1 || (p->dagger != 0 && p->dagger != 1))
         return WL_EINVAL;
     if (hi->ns > 0 && solver != WL_SOLVER_CGNR)
-        return WL_EINVAL;  // domain wall: CG on the normal equations only (Sec. V-C)
+        return WL_EINVAL;  // domain wall: CG on the normal equations only (Sec. II-C, Sec. VI-B)
     if (!al16(x) || !al16(b))
         return WL_EALIGN;
     if (lo) {
         if (hi->prec != WL_F64 || lo->prec == WL_F64)
+            return WL_EPREC;
+        // CG on the normal equations cannot carry its recurrence between
+        // reliable updates with 16-bit storage (measured: BF16 stalls, FP16
+        // drifts into thousands of iterations or overflows); those pairs take
+        // defect correction (reliable = 0) only
+        if (p->reliable && solver == WL_SOLVER_CGNR && lo->prec != WL_F32)
             return WL_EPREC;
         for (int i = 0; i < 4; ++i)
             if (lo->g.dims[i] != hi->g.dims[i] || lo->g.bc[i] != hi->g.bc[i])

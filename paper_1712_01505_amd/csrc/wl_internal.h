@@ -119,6 +119,12 @@ EoParams eo_params(const wl_op *op, int parity, int nrhs);  // links, extents, p
 
 // ---- stencil (wl_stencil.hip)
 hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilParams p, hipStream_t st);
+// the stencil and multi-lattice kernels of one storage precision P, each
+// instantiated in its own translation unit (wl_stencil_<prec>.hip)
+template <int P>
+hipError_t launch_stencil_p(int dagger, const LaunchCfg &cfg, const StencilParams &p, hipStream_t st);
+template <int P>
+const void *multi_kernel_p(int dagger, int rpt, int var, bool persistent);
 // enforced halo: pack the two t faces' projected half-spinors, and add the
 // received faces' hops to the boundary slices
 hipError_t launch_halo_pack(int prec, int dagger, const StencilParams &p, hipStream_t st);

@@ -551,7 +551,7 @@ def dw_apply(U, psi, m0, m, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None)
 
 def dw_solve(U, b, m0, m, precision="f64", tol=1e-10, maxiter=20000, bc=(1, 1, 1, -1), inner_tol=0.0,
              check_every=0, x0=None, ops=None, return_stats=False, reliable=False):
-    """x = D_DW^{-1} b by CG on D_DW^dag D_DW (Sec. V-C) for a canonical 5-d
+    """x = D_DW^{-1} b by CG on D_DW^dag D_DW (Sec. II-C, Sec. VI-B) for a canonical 5-d
     complex128 CUDA tensor b (Ns, ...) or (nvec, Ns, ...).
 
     precision: "f64", "f32", or "mixed-f32" / "mixed-bf16" / "mixed-f16" (FP64
