@@ -328,14 +328,25 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
  *                 software-pipelined hop loop 1 (all precisions), 2 (not
  *                 WL_F64), 3 (16-bit formats only), or a t-walk 4, 5, 6
  *                 (columns of 4, 8, 16 sites along t; Lt divisible by that;
- *                 block <= 256).
- * Results do not depend on the configuration (16-bit t-walk: to rounding). */
+ *                 block <= 256), or 7, the LDS-staged brick walk: a
+ *                 workgroup of brick[0] x brick[1] x brick[2] = block
+ *                 threads (64..256) owns that brick of (x, y, z) sites and
+ *                 walks t_steps t-slices; each slice's spinors of the brick
+ *                 and of its face halos are staged in LDS (the halo by
+ *                 direct-to-LDS copies) and the spatial neighbours are read
+ *                 from there (brick extents dividing Lx, Ly, Lz; t_steps
+ *                 dividing Lt; rhs_per_thread = rhs_lanes = 1; Wilson ops).
+ * brick, t_steps  variant 7 only (ignored otherwise).
+ * Results do not depend on the configuration (16-bit t-walk and brick walk:
+ * to rounding). */
 typedef struct {
     int block;
     int rhs_per_thread;
     int rhs_lanes;
     int xcd_remap;
     int variant;
+    int brick[3];
+    int t_steps;
 } wl_launch;
 int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg);
 /* Force a configuration (WL_EINVAL if it breaks a rule above).  Used by

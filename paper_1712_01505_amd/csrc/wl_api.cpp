@@ -168,8 +168,11 @@ static void load_tune_cache_locked()
         std::istringstream is(line);
         std::string key;
         LaunchCfg c;
-        if (is >> key >> c.block >> c.rpt >> c.xcd >> c.var >> c.lanes)
+        if (is >> key >> c.block >> c.rpt >> c.xcd >> c.var >> c.lanes) {
+            if (!(is >> c.bx >> c.by >> c.bz >> c.tsteps))
+                c.bx = c.by = c.bz = c.tsteps = 0;
             g_tune[key] = c;
+        }
     }
 }
 
@@ -181,7 +184,8 @@ static void save_tune_cache_locked()
     std::ofstream f(path, std::ios::trunc);
     for (auto &kv : g_tune)
         f << kv.first << " " << kv.second.block << " " << kv.second.rpt << " " << kv.second.xcd << " "
-          << kv.second.var << " " << kv.second.lanes << "\n";
+          << kv.second.var << " " << kv.second.lanes << " " << kv.second.bx << " " << kv.second.by << " "
+          << kv.second.bz << " " << kv.second.tsteps << "\n";
 }
 
 // Untuned defaults (measured on MI355X at 32^3 x 64): one right-hand side
@@ -225,7 +229,44 @@ static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
            nrhs % c.rpt == 0 && lanes_ok && c.xcd >= 0 && c.xcd <= 5 &&
            (c.xcd < 2 || slab_ok(op->g.dims, c.block / c.lanes, c.xcd)) && c.var >= 0 && c.var <= max_var(prec) &&
            var_ok(prec, c.var) && (c.var == 0 || c.rpt == 1) &&
-           (c.var < 4 || (c.block <= 256 && op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0));
+           (c.var < 4 || c.var == VAR_BRICK ||
+            (c.block <= 256 && op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0)) &&
+           (c.var != VAR_BRICK || (op->ns == 0 && c.lanes == 1 && c.bx * c.by * c.bz == c.block &&
+                                   brick_ok(op->g.dims, prec, c.bx, c.by, c.bz, c.tsteps)));
+}
+
+// Brick shapes (variant 7) for extents L: x extent 8, 16 or 32, the rest
+// as close to cubic as the divisors allow, 128 or 256 sites; walks of 4, 8
+// or 16 t-slices.
+static void brick_candidates(const wl_op *op, std::vector<LaunchCfg> &out)
+{
+    const int *L = op->g.dims;
+    if (op->ns > 0)
+        return;
+    const int blocks[] = {128, 256};
+    const int bxs[] = {8, 16, 32};
+    const int ts[] = {4, 8, 16};
+    for (int block : blocks)
+        for (int bx : bxs) {
+            if (block % bx != 0)
+                continue;
+            const int rest = block / bx;
+            for (int by = 1; by <= rest; by *= 2) {
+                const int bz = rest / by;
+                if (by * bz != rest || by > 4 * bz || bz > 4 * by)
+                    continue;
+                for (int T : ts)
+                    for (int xcd = 0; xcd <= 1; ++xcd) {
+                        LaunchCfg c{block, 1, xcd, VAR_BRICK, 1};
+                        c.bx = bx;
+                        c.by = by;
+                        c.bz = bz;
+                        c.tsteps = T;
+                        if (brick_ok(L, op->prec, bx, by, bz, T))
+                            out.push_back(c);
+                    }
+            }
+        }
 }
 
 // Launch configurations are kept per (nrhs, fused reduction): the solver's
@@ -902,6 +943,10 @@ int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg)
     cfg->rhs_lanes = c.lanes;
     cfg->xcd_remap = c.xcd;
     cfg->variant = c.var;
+    cfg->brick[0] = c.bx;
+    cfg->brick[1] = c.by;
+    cfg->brick[2] = c.bz;
+    cfg->t_steps = c.tsteps;
     return WL_OK;
 }
 
@@ -916,6 +961,12 @@ int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg)
     c.lanes = cfg->rhs_lanes;
     c.xcd = cfg->xcd_remap;
     c.var = cfg->variant;
+    if (c.var == VAR_BRICK) {
+        c.bx = cfg->brick[0];
+        c.by = cfg->brick[1];
+        c.bz = cfg->brick[2];
+        c.tsteps = cfg->t_steps;
+    }
     if (!launch_ok(op, nrhs, c))
         return WL_EINVAL;
     std::lock_guard<std::mutex> lk(op->mu);
@@ -953,9 +1004,18 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
                         const LaunchCfg c{blocks[bi], rpt, xcd, var, lanes};
                         if (var >= 4 && xcd >= 2)
                             continue;  // the t-walk orders only distinguish 0 and 1
+                        if (var == VAR_BRICK)
+                            continue;  // brick shapes below
                         if (launch_ok(op, nrhs, c))
                             cands.push_back(c);
                     }
+    {
+        std::vector<LaunchCfg> bc;
+        brick_candidates(op, bc);
+        for (const LaunchCfg &c : bc)
+            if (launch_ok(op, nrhs, c))
+                cands.push_back(c);
+    }
     // the plain apply, then each fused reduction of the solvers (partials
     // and the <v, out> operand in scratch)
     LaunchCfg bests[RED_BICG + 1];

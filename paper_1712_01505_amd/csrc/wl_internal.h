@@ -23,6 +23,8 @@ struct LaunchCfg {
                       // t-major in y-chunks of Ly >> (xcd - 2) rows
     int var = 0;      // stencil code variant (0 = straight-line hops; 1..3 = pipelined, R = 1 only)
     int lanes = 1;    // right-hand sides interleaved across the lanes of a wavefront (1, 2, 4, 8; rpt = 1)
+    // variant 7 (LDS-staged brick walk): brick extents in x, y, z (bx by bz = block) and t-slices per unit
+    int bx = 0, by = 0, bz = 0, tsteps = 0;
 };
 
 }  // namespace wl
@@ -136,6 +138,9 @@ int max_var(int prec);  // largest stencil code variant for R = 1
 bool var_ok(int prec, int var);  // variant exists for this precision
 int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V, int nrhs);  // partials per RHS of one launch
 bool slab_ok(const int *L, int block, int mode);  // slab order `mode` usable for these extents and block size
+// variant 7: the brick (bx, by, bz) and walk length T tile extents L and fit the kernel's LDS and halo limits
+bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T);
+constexpr int VAR_BRICK = 7;
 
 struct MultiEntry {
     StencilParams p;      // per lattice; ng / f_ng = RHS groups per tile

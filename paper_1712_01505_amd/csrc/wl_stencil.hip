@@ -21,14 +21,20 @@
 //   * XCD-aware tile order and fused reductions for the solvers.
 #include <type_traits>
 
-#include "wl_stencil_dev.h"
+#include "wl_brick.h"
 
 namespace wl {
 
 // FP64 with G = 2 and FP32 with G = 4 exceed the register file and spill;
-// variants 4-6 (t-walk) exist for every precision.
-int max_var(int prec) { return 6; }
+// variants 4-6 (t-walk) and 7 (LDS-staged brick walk) exist for every precision.
+int max_var(int prec) { return VAR_BRICK; }
 bool var_ok(int prec, int var) { return var <= 1 || var >= 4 || (var == 2 && prec != F64) || (var == 3 && prec >= BF16S); }
+
+bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T)
+{
+    BrickGeom g{};
+    return brick_setup(L, prec, bx, by, bz, T, g);
+}
 
 bool slab_ok(const int *L, int block, int mode)
 {
@@ -48,7 +54,9 @@ int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V, int nrhs)
 {
     const uint32_t tile = (uint32_t)(cfg.block / cfg.lanes);
     uint32_t n = (V + tile - 1) / tile;
-    if (cfg.rpt == 1 && cfg.var >= 4) {
+    if (cfg.rpt == 1 && cfg.var == VAR_BRICK && cfg.bx > 0 && cfg.by > 0 && cfg.bz > 0 && cfg.tsteps > 0) {
+        n = (uint32_t)((L[0] / cfg.bx) * (L[1] / cfg.by) * (L[2] / cfg.bz)) * (uint32_t)(L[3] / cfg.tsteps);
+    } else if (cfg.rpt == 1 && cfg.var >= 4) {
         const uint32_t nxyz = (uint32_t)L[0] * L[1] * L[2];
         n = ((nxyz + cfg.block - 1) / cfg.block) * (uint32_t)(L[3] / twalk_T(cfg.var));
     }

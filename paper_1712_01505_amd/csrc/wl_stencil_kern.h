@@ -3,6 +3,7 @@
 // them for one precision (paper Sec. II-B, eq. (1); Table I cost).
 #pragma once
 
+#include "wl_brick.h"
 #include "wl_stencil_dev.h"
 
 namespace wl {
@@ -411,6 +412,7 @@ inline hipError_t launch_t(const LaunchCfg &cfg, StencilParams p, hipStream_t st
         case 4:
         case 5:
         case 6: return launch_twalk<P, DAG>(cfg, p, st);
+        case VAR_BRICK: return launch_brick<P, DAG>(cfg, p, st);
         default: return hipErrorInvalidValue;
         }
     } else {

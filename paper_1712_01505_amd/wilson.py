@@ -64,7 +64,8 @@ class wl_solve_stats(ctypes.Structure):
 
 class wl_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("rhs_per_thread", ctypes.c_int), ("rhs_lanes", ctypes.c_int),
-                ("xcd_remap", ctypes.c_int), ("variant", ctypes.c_int)]
+                ("xcd_remap", ctypes.c_int), ("variant", ctypes.c_int), ("brick", ctypes.c_int * 3),
+                ("t_steps", ctypes.c_int)]
 
 
 class wl_multi_desc(ctypes.Structure):
@@ -274,28 +275,40 @@ def wl_autotune(op, nrhs, dagger, stream):
 
 
 def wl_get_launch(op, nrhs):
-    """(block, rhs_per_thread, xcd_remap, variant, rhs_lanes) used for nrhs right-hand sides."""
+    """(block, rhs_per_thread, xcd_remap, variant, rhs_lanes, brick_x, brick_y, brick_z, t_steps)
+    used for nrhs right-hand sides (the brick fields are 0 unless variant is 7)."""
     c = wl_launch()
     _check(lib().wl_get_launch(op, nrhs, ctypes.byref(c)), "wl_get_launch")
-    return c.block, c.rhs_per_thread, c.xcd_remap, c.variant, c.rhs_lanes
+    return (c.block, c.rhs_per_thread, c.xcd_remap, c.variant, c.rhs_lanes, c.brick[0], c.brick[1], c.brick[2],
+            c.t_steps)
 
 
-def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1):
+def _launch(block, rpt, xcd, variant, lanes, brick, t_steps):
     c = wl_launch(block=block, rhs_per_thread=rpt, rhs_lanes=lanes, xcd_remap=xcd, variant=variant)
+    if brick is not None:
+        c.brick[0], c.brick[1], c.brick[2] = (int(b) for b in brick)
+        c.t_steps = int(t_steps)
+    return c
+
+
+def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0):
+    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps)
     return _check(lib().wl_set_launch(op, nrhs, ctypes.byref(c)), "wl_set_launch")
 
 
 # Stencil code variants per precision (see wl_set_launch in the header):
-# 0 straight-line, 1-3 pipelined hops, 4-6 t-walk with columns of 4, 8, 16.
+# 0 straight-line, 1-3 pipelined hops, 4-6 t-walk with columns of 4, 8, 16,
+# 7 LDS-staged brick walk (needs a brick shape and a walk length).
 VARIANTS = {WL_F64: (0, 1, 4, 5, 6), WL_F32: (0, 1, 2, 4, 5, 6), WL_BF16S: (0, 1, 2, 3, 4, 5, 6),
             WL_F16S: (0, 1, 2, 3, 4, 5, 6)}
-MAX_VARIANT = {k: max(v) for k, v in VARIANTS.items()}
+VAR_BRICK = 7
+MAX_VARIANT = {k: VAR_BRICK for k in VARIANTS}
 
 
-def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1):
+def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0):
     """wl_set_launch that returns False (instead of raising) for a configuration
     the library rejects."""
-    c = wl_launch(block=block, rhs_per_thread=rpt, rhs_lanes=lanes, xcd_remap=xcd, variant=variant)
+    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps)
     return lib().wl_set_launch(op, nrhs, ctypes.byref(c)) == WL_OK
 MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
 
