@@ -234,11 +234,11 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
 #pragma unroll
                     for (int q = 0; q < NCH; ++q) {
                         const Ch *src = reinterpret_cast<const Ch *>(p.in) + ((size_t)rhs * NCH + q) * p.V + hs;
-                        __builtin_amdgcn_global_load_lds(src, (lds_void_t *)(lsp + q * g.NSP + g.NB + grp * 64), 16, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(lsp + q * g.NSP + g.NB + grp * 64), 16, 0, 0);
                     }
                     if constexpr (Traits<P>::SCALED) {
                         const float *src = scale_ptr<P>(p.in, p.V, p.nrhs) + (size_t)rhs * p.V + hs;
-                        __builtin_amdgcn_global_load_lds(src, (lds_void_t *)(lsc + g.NB + grp * 64), 4, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(lsc + g.NB + grp * 64), 4, 0, 0);
                     }
                 }
             }
@@ -419,15 +419,14 @@ template <int P, int DAG, int RED, int APPLY>
 inline hipError_t brick_go(dim3 grid, dim3 block, size_t smem, const StencilParams &p, const BrickGeom &g,
                            hipStream_t st)
 {
-    auto fn = brick_kernel<P, DAG, RED, APPLY>;
     static bool big = false;  // LDS beyond the default 64 KB limit, set once per instantiation
     if (smem > 65536 && !big) {
         // a failure here shows up as the launch's own error
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&brick_kernel<P, DAG, RED, APPLY>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         big = true;
     }
-    hipLaunchKernelGGL(fn, grid, block, smem, st, p, g);
+    hipLaunchKernelGGL((brick_kernel<P, DAG, RED, APPLY>), grid, block, smem, st, p, g);
     return hipGetLastError();
 }
 
