@@ -366,6 +366,30 @@ int wl_prof_read(int prec, long *launches, double *total_ms, double *site_rhs);
  * compulsory traffic per site.  WL_EINVAL for a bad precision or null. */
 int wl_prof_read_aux(int prec, double *aux_site_rhs);
 
+/* ---- Fused apply with the solvers' inner products ----
+ * out = D in (dagger: D^dag in) and, from the same pass over the sites, the
+ * inner products the Krylov solvers fuse into their operator products
+ * (paper Sec. V-C: the solver's linear algebra and reductions, not the
+ * stencil, dominate its time):
+ *   kind WL_DOT_BICG: 7 values per right-hand side r, <in, out>, |out|^2,
+ *        <v, in>, <v, out> (BiCGStab's second product: omega and the next rho);
+ *   kind WL_DOT_V:    2 values, <v, out> (BiCGStab's <rh, D p>);
+ *   kind WL_DOT_NORM: 1 value, |out|^2 (CG on the normal equations).
+ * Complex values take two entries (re, im); <a, b> = sum conj(a_i) b_i,
+ * accumulated in FP64 in a fixed order.  dots: DEVICE array of nval x nrhs
+ * doubles, value-major (entry k of column r at dots[k nrhs + r]), 8-byte
+ * aligned; for WL_DOT_BICG the order is Re<in,out>, Im<in,out>, |out|^2,
+ * Re<v,in>, Im<v,in>, Re<v,out>, Im<v,out>.  v: packed spinor of the op's
+ * precision (nrhs columns; may equal in; NULL only for WL_DOT_NORM).  The
+ * stencil runs in the launch shape tuned for that reduction.  workspace:
+ * caller-owned device scratch of wl_apply_dot_workspace_bytes (256-byte
+ * aligned), not shared by concurrent calls.  Wilson ops, nrhs <= 64.  Async
+ * (nothing is copied to the host). */
+enum { WL_DOT_BICG = 0, WL_DOT_V = 1, WL_DOT_NORM = 2 };
+int wl_apply_dot_workspace_bytes(const wl_op *op, int nrhs, size_t *out_bytes);
+int wilson_apply_dot(const wl_op *op, void *out, const void *in, const void *v, int dagger, int nrhs, int kind,
+                     double *dots, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Plain device-to-device streaming copy of `bytes` (a multiple of 16, no
  * overlap): the reference point for achievable HBM bandwidth and for
  * calibrating hardware byte counters against a kernel of known traffic.

@@ -1100,6 +1100,76 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     return WL_OK;
 }
 
+// ---------------------------------------------------------------- fused apply + inner products
+static int dot_red(int kind)
+{
+    return kind == WL_DOT_BICG ? RED_BICG : kind == WL_DOT_V ? RED_DOTV : kind == WL_DOT_NORM ? RED_NORM : -1;
+}
+
+// Per-workgroup partials of any launch shape (the smallest tile has 64
+// sites; t-walk and brick units are no more numerous) plus the sums.
+static size_t apply_dot_bytes(const wl_op *op, int nrhs)
+{
+    const size_t nblk = (size_t)(op->V + 63) / 64 + (size_t)op->g.dims[3] + 8;
+    return ((size_t)RED_NVAL_MAX * nrhs * nblk * sizeof(double) + 255) / 256 * 256;
+}
+
+int wl_apply_dot_workspace_bytes(const wl_op *op, int nrhs, size_t *out_bytes)
+{
+    if (!op || op->ns > 0 || nrhs < 1 || nrhs > 64 || !out_bytes)
+        return WL_EINVAL;
+    *out_bytes = apply_dot_bytes(op, nrhs);
+    return WL_OK;
+}
+
+// The fused apply on `work` (partials, apply_dot_bytes of them); shared by
+// wilson_apply_dot and its allocation-free variant.
+int apply_dot_run(const wl_op *op, void *out, const void *in, const void *v, int dagger, int nrhs, int kind,
+                  double *dots, double *work, hipStream_t st)
+{
+    const int red = dot_red(kind);
+    StencilParams p = base_params(op, out, in, nrhs, 1);
+    p.red = red;
+    p.aux = v;
+    p.partials = work;
+    LaunchCfg cfg = launch_for(op, nrhs, red);
+    FinParams fp{};
+    fp.A = work;
+    fp.nblkA = stencil_partials(cfg, p.L, op->V, nrhs);
+    fp.nvalA = stencil_nval(red);
+    fp.out = dots;
+    fp.nrhs = nrhs;
+    fp.group = 1;
+    CHECK_HIP(prof_stencil(op->prec, op, dagger, cfg, p, st));
+    CHECK_HIP(launch_finalize(F_SUM, fp, st));
+    return WL_OK;
+}
+
+static int apply_dot_args(const wl_op *op, void *out, const void *in, const void *v, int dagger, int nrhs, int kind,
+                          double *dots)
+{
+    if (!op || op->ns > 0 || !out || !in || !dots || out == in || nrhs < 1 || nrhs > 64 ||
+        (dagger != 0 && dagger != 1) || dot_red(kind) < 0 || ((kind == WL_DOT_BICG || kind == WL_DOT_V) && !v) ||
+        v == out)
+        return WL_EINVAL;
+    if (!al16(out) || !al16(in) || (v && !al16(v)) || ((uintptr_t)dots & 7u) != 0)
+        return WL_EALIGN;
+    return WL_OK;
+}
+
+int wilson_apply_dot(const wl_op *op, void *out, const void *in, const void *v, int dagger, int nrhs, int kind,
+                     double *dots, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int rc = apply_dot_args(op, out, in, v, dagger, nrhs, kind, dots);
+    if (rc != WL_OK)
+        return rc;
+    if (!workspace || workspace_bytes < apply_dot_bytes(op, nrhs))
+        return WL_EWORKSPACE;
+    if (((uintptr_t)workspace & 255u) != 0)
+        return WL_EALIGN;
+    return apply_dot_run(op, out, in, v, dagger, nrhs, kind, dots, (double *)workspace, (hipStream_t)stream);
+}
+
 int wl_stream_copy(void *dst, const void *src, size_t bytes, void *stream)
 {
     if (!dst || !src || bytes % 16 != 0)

@@ -38,7 +38,7 @@ EXPORTS = [
     "wl_stream_copy", "wl_strerror", "wl_last_hip_error", "wl_multi_plan_create", "wl_multi_plan_run",
     "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
     "wl_dw_op_create", "dwf_apply", "wl_halo_bytes", "wilson_apply_halo", "wl_eo_split", "wl_eo_merge",
-    "wilson_schur_apply",
+    "wilson_schur_apply", "wl_apply_dot_workspace_bytes", "wilson_apply_dot",
 ]
 
 
@@ -134,6 +134,8 @@ def lib():
                                      ctypes.POINTER(I)],
         "wl_multi_plan_set_launch": [P, I, I, I, I],
         "wl_multi_plan_destroy": [P],
+        "wl_apply_dot_workspace_bytes": [P, I, ctypes.POINTER(SZ)],
+        "wilson_apply_dot": [P, P, P, P, I, I, I, P, P, SZ, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -311,6 +313,34 @@ def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_
     c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps)
     return lib().wl_set_launch(op, nrhs, ctypes.byref(c)) == WL_OK
 MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
+
+
+WL_DOT_BICG, WL_DOT_V, WL_DOT_NORM = 0, 1, 2
+DOT_NVAL = {WL_DOT_BICG: 7, WL_DOT_V: 2, WL_DOT_NORM: 1}
+
+
+def wl_apply_dot_workspace_bytes(op, nrhs) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().wl_apply_dot_workspace_bytes(op, nrhs, ctypes.byref(out)), "wl_apply_dot_workspace_bytes")
+    return out.value
+
+
+def wilson_apply_dot(op, out, inp, v, dagger, nrhs, kind, dots, workspace, workspace_bytes, stream):
+    return _check(lib().wilson_apply_dot(op, out, inp, v, int(dagger), nrhs, kind, dots, workspace,
+                                         workspace_bytes, stream), "wilson_apply_dot")
+
+
+def apply_dot(op, out_packed, in_packed, v_packed=None, dagger=False, nrhs=1, kind=WL_DOT_BICG):
+    """out = D in (packed, op precision) with the fused inner products of
+    `kind`; returns a float64 CUDA tensor of shape (nval, nrhs)."""
+    torch = _torch()
+    dev = in_packed.device
+    nb = wl_apply_dot_workspace_bytes(op.handle, nrhs)
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    dots = torch.empty((DOT_NVAL[kind], nrhs), dtype=torch.float64, device=dev)
+    wilson_apply_dot(op.handle, _ptr(out_packed), _ptr(in_packed), _ptr(v_packed) if v_packed is not None else None,
+                     dagger, nrhs, kind, _ptr(dots), _ptr(work), nb, _stream())
+    return dots
 
 
 def wl_stream_copy(dst, src, nbytes, stream):
