@@ -15,6 +15,17 @@ each stencil precision on its own (GFLOP/s and GB/s on compulsory bytes), the
 plain FP64 BiCGStab and CGNR solves, the other inner precisions, checks the
 step's solution with the FP64 CPU oracle, and times the oracle on the host.
 
+Every solve reports, beside the library's own FP64 residual, the true
+residual recomputed by the FP64 CPU oracle and the forward error against the
+oracle's solution x* (BiCGStab to 1e-12 from x = 0).  Further sections: the
+paper's single-node lattice 16^3 x 32 (apply with one and with four rotated
+buffer sets, FP64 BiCGStab and CGNR, the oracle's solvers timed on the host),
+24^3 x 48 with 12 point sources (multi-RHS stencil, batched solve with every
+column's oracle residual), multi-lattice plans, the differentiable solve, the
+domain-wall operator and the enforced halo.  The CPU baseline is the oracle's
+D on the benchmark lattice with all host threads and with one, with the CPU
+model.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Prints one JSON line on stdout (progress goes to stderr).
 """
@@ -63,7 +74,7 @@ def measured_traffic(prec, dims):
         # autotune, so these are the timed solve's launches)
         if k.startswith("wl::stencil_kernel<"):
             red_at = 3
-        elif k.startswith("wl::twalk_kernel<"):
+        elif k.startswith("wl::twalk_kernel<") or k.startswith("wl::brick_kernel<"):
             red_at = 2
         else:
             continue
@@ -72,6 +83,45 @@ def measured_traffic(prec, dims):
             tot += v["hbm_bytes"] * v["dispatches"]
             n += v["dispatches"]
     return round(tot / n) if n else None
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo; lscpu reads the same)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads the oracle's OpenMP runtime uses: OMP_NUM_THREADS, else the
+    cores this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def omp_set_threads(n):
+    """Set the thread count of the OpenMP runtime the oracle is linked with."""
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def oracle_errors(oracle, U, x, b, kappa, x_star=None, dagger=False):
+    """The true relative residual ||b - D x|| / ||b|| with the FP64 oracle D
+    and, given the oracle solution x*, the forward error ||x - x*|| / ||x*||."""
+    import numpy as np
+    r = oracle.apply(U, x, kappa, dagger=dagger) - b
+    out = {"oracle_true_rel_res": float(np.linalg.norm(r) / np.linalg.norm(b))}
+    if x_star is not None:
+        out["forward_error_vs_oracle"] = float(np.linalg.norm(x - x_star) / np.linalg.norm(x_star))
+    return out
 
 
 def _time_ms(torch, fn, reps):
@@ -86,7 +136,7 @@ def _time_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def bench_batching(W, inputs, torch, log):
+def bench_batching(W, inputs, torch, log, oracle=None):
     """24^3 x 48 with the 12 point sources (one per spin-colour at the origin):
     multi-RHS FP32 stencil vs one right-hand side at a time, and the batched
     mixed-precision solve vs 12 sequential solves; plus one persistent launch
@@ -97,8 +147,10 @@ def bench_batching(W, inputs, torch, log):
     V = inputs.volume(dims)
     kappa = 0.12
     log(f"[bench] batching: generating {dims}")
-    Ud = torch.from_numpy(inputs.near_unity_gauge(dims, 0.3, seed=inputs.GAUGE_SEED)).cuda()
-    src = torch.from_numpy(inputs.point_sources_all_spin_colour(dims)).cuda()
+    U24 = inputs.near_unity_gauge(dims, 0.3, seed=inputs.GAUGE_SEED)
+    src24 = inputs.point_sources_all_spin_colour(dims)
+    Ud = torch.from_numpy(U24).cuda()
+    src = torch.from_numpy(src24).cuda()
     hi = W.Operator.create(Ud, kappa, W.WL_F64)
     lo = W.Operator.create(Ud, kappa, W.WL_F32)
     del Ud
@@ -121,9 +173,10 @@ def bench_batching(W, inputs, torch, log):
     log(f"[bench] multi-RHS stencil: {out['multi_rhs_stencil_f32']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, sts = W.solve(None, src, kappa, method="bicgstab", precision="mixed-f32", tol=1e-10, ops=(hi, lo),
-                     return_stats=True)
+    xb, sts = W.solve(None, src, kappa, method="bicgstab", precision="mixed-f32", tol=1e-10, ops=(hi, lo),
+                      return_stats=True)
     t_batch = time.perf_counter() - t0
+    xb = xb.cpu().numpy()
     t0 = time.perf_counter()
     iters = []
     for k in range(12):
@@ -135,6 +188,22 @@ def bench_batching(W, inputs, torch, log):
                             "sequential_seconds": round(t_seq, 4), "speedup": round(t_seq / t_batch, 3),
                             "max_true_rel_res": max(x["true_rel_res"] for x in sts),
                             "iters": [x["iters"] for x in sts], "sequential_iters": iters}
+    if oracle is not None:
+        # every column's true residual by the FP64 oracle; the forward error
+        # against oracle solutions (BiCGStab to 1e-12) for two columns, a
+        # bounded sample of the CPU work
+        cols = {}
+        for k in range(12):
+            star = None
+            if k in (0, 11):
+                t1 = time.perf_counter()
+                star, code, it, rr = oracle.bicgstab(U24, src24[k], kappa, tol=1e-12)
+                log(f"[bench] oracle solution of column {k}: {it} iterations, rel. res. {rr:.2e}, "
+                    f"{time.perf_counter() - t1:.1f} s")
+            cols[k] = oracle_errors(oracle, U24, xb[k], src24[k], kappa, star)
+        out["batched_solve"]["oracle_per_column"] = cols
+        out["batched_solve"]["max_oracle_true_rel_res"] = max(c["oracle_true_rel_res"] for c in cols.values())
+    del xb
     log(f"[bench] batched solve: {out['batched_solve']}")
     del hi, lo, src, s12, d12, s1, d1
     torch.cuda.empty_cache()
@@ -190,6 +259,97 @@ def bench_batching(W, inputs, torch, log):
                                     "speedup": round(ms_sep / ms_multi, 3),
                                     "GFLOP/s": round(1368 * Vt * 4 / (ms_multi * 1e-3) / 1e9, 1)}
     log(f"[bench] ensemble of small lattices: {out['ensemble_64_small_f32']}")
+    return out
+
+
+def _copy_launch(W, src_op, dst_op, nrhs=1):
+    c = W.wl_get_launch(src_op.handle, nrhs)
+    W.wl_set_launch(dst_op.handle, nrhs, c[0], c[1], c[2], c[3], c[4],
+                    brick=c[5:8] if c[3] == W.VAR_BRICK else None, t_steps=c[8])
+
+
+def bench_c2(W, inputs, torch, log, oracle=None):
+    """The paper's single-node lattice 16^3 x 32 (eps = 0.3, kappa = 0.125):
+    FP64 and FP32 apply on one buffer set (it fits the 256 MB Infinity Cache)
+    and rotated over four sets (links, source and output each; > 256 MB), the
+    FP64 BiCGStab and CGNR solves to 1e-10 with their errors against the
+    oracle, and the oracle's own BiCGStab and CGNR timed on the host."""
+    import numpy as np
+    dims = (16, 16, 16, 32)
+    kappa = 0.125
+    V = inputs.volume(dims)
+    st = W._stream()
+    log(f"[bench] single lattice {dims}: generating")
+    U = inputs.near_unity_gauge(dims, 0.3, seed=inputs.GAUGE_SEED)
+    b = inputs.gaussian_spinor(dims, seed=inputs.SOURCE_SEED)
+    Ud = torch.from_numpy(U).cuda()
+    bd = torch.from_numpy(b).cuda()
+    out = {"dims": list(dims), "kappa": kappa, "eps": 0.3}
+    app = {}
+    nsets = 4
+    for p in (0, 1):
+        ops = [W.Operator.create(Ud, kappa, p) for _ in range(nsets)]  # four packed copies of the links
+        W.wl_autotune(ops[0].handle, 1, 0, st)
+        for o in ops[1:]:
+            _copy_launch(W, ops[0], o)
+        srcs = [o.pack(bd) for o in ops]
+        dsts = [o.new_field() for o in ops]
+        ms1 = _time_ms(torch, lambda: ops[0].apply_packed(dsts[0], srcs[0]), 200)
+
+        def rotated():
+            for k in range(nsets):
+                ops[k].apply_packed(dsts[k], srcs[k])
+        ms4 = _time_ms(torch, rotated, 50) / nsets
+        gbs1 = BYTES[p] * V / (ms1 * 1e-3) / 1e9
+        gbs4 = BYTES[p] * V / (ms4 * 1e-3) / 1e9
+        app[PNAME[p]] = {"us": round(ms1 * 1e3, 2), "GFLOP/s": round(FLOP_APPLY * V / (ms1 * 1e-3) / 1e9, 1),
+                         "GB/s": round(gbs1, 1), "hbm_frac": round(gbs1 / HBM_PEAK_GBS, 4),
+                         "rotated_us": round(ms4 * 1e3, 2),
+                         "rotated_GFLOP/s": round(FLOP_APPLY * V / (ms4 * 1e-3) / 1e9, 1),
+                         "rotated_GB/s": round(gbs4, 1), "rotated_hbm_frac": round(gbs4 / HBM_PEAK_GBS, 4),
+                         "rotated_sets": nsets, "set_MB": round(BYTES[p] * V / 1e6, 1),
+                         "launch": W.wl_get_launch(ops[0].handle, 1)}
+        log(f"[bench] {dims} apply {PNAME[p]}: {app[PNAME[p]]}")
+        del ops, srcs, dsts
+    out["apply"] = app
+    hi = W.Operator.create(Ud, kappa, W.WL_F64)
+    W.wl_autotune(hi.handle, 1, 0, st)
+    x_star = None
+    if oracle is not None:
+        t1 = time.perf_counter()
+        x_star, code_s, it_s, rr_s = oracle.bicgstab(U, b, kappa, tol=1e-12)
+        out["oracle_reference_solution"] = {"tol": 1e-12, "iters": it_s, "true_rel_res": rr_s,
+                                            "seconds": round(time.perf_counter() - t1, 2)}
+    solves = {}
+    for method in ("bicgstab", "cgnr"):
+        W.solve(None, bd, kappa, method=method, precision="f64", tol=1e-10, ops=(hi, None))  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, sst = W.solve(None, bd, kappa, method=method, precision="f64", tol=1e-10, ops=(hi, None),
+                         return_stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        r = {"seconds": round(dt, 4), "status": sst["status"], "iters": sst["iters"],
+             "stencil_calls": sst["stencil_calls"], "true_rel_res": sst["true_rel_res"]}
+        if oracle is not None:
+            r.update(oracle_errors(oracle, U, x.cpu().numpy(), b, kappa, x_star))
+        solves[method + "_f64"] = r
+        log(f"[bench] {dims} solve {method} f64: {r}")
+    out["solves"] = solves
+    if oracle is not None:
+        # the oracle's solvers on the same system, timed on the host
+        osol = {"threads": host_threads(), "cpu_model": cpu_model()}
+        for method in ("bicgstab", "cgnr"):
+            fn = oracle.bicgstab if method == "bicgstab" else oracle.cgnr
+            t1 = time.perf_counter()
+            _, code_o, it_o, rr_o = fn(U, b, kappa, tol=1e-10)
+            dt = time.perf_counter() - t1
+            osol[method] = {"seconds": round(dt, 2), "status": code_o, "iters": it_o, "true_rel_res": rr_o,
+                            "gpu_speedup": round(dt / solves[method + "_f64"]["seconds"], 1)}
+        out["oracle_solvers"] = osol
+        log(f"[bench] {dims} oracle solvers: {osol}")
+    del hi, Ud, bd
+    torch.cuda.empty_cache()
     return out
 
 
@@ -382,6 +542,9 @@ def main():
         code = fn(hi.handle, lo, x64.data_ptr(), b64.data_ptr(), 1, prm, st, stream)
         return code, st[0].as_dict()
 
+    oracle = None
+    if not args.no_cpu:
+        import oracle  # the FP64 CPU checker (test infrastructure), never the product path
     inner = {"f32": W.WL_F32, "bf16": W.WL_BF16S, "f16": W.WL_F16S}[args.inner]
     tuned = {}
     for p, op in ops.items():
@@ -427,7 +590,7 @@ def main():
     bytes_per_launch = (BYTES[dom] * sites_l + SPINOR[dom] * prof_aux[dom]) / max(n_l, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm",
-                "kernel": f"wilson stencil <{PNAME[dom]}> in the solve (stencil_kernel/twalk_kernel, fused reductions)",
+                "kernel": f"wilson stencil <{PNAME[dom]}> in the solve (stencil/t-walk/brick kernels, fused reductions)",
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, dims),
@@ -474,6 +637,19 @@ def main():
             del src, dst
             log(f"[bench] apply {PNAME[p]}: {dsl[PNAME[p]]}")
         result["dslash"] = dsl
+        # the FP64 oracle's solution x* of the same system (BiCGStab to 1e-12,
+        # zero start), against which every solve below states its error
+        x_star, ref_info = None, None
+        if oracle is not None:
+            log("[bench] oracle reference solution x* (CPU, BiCGStab to 1e-12)")
+            t1 = time.perf_counter()
+            x_star, code_s, it_s, rr_s = oracle.bicgstab(U, b, kappa, tol=1e-12)
+            ref_info = {"method": "oracle BiCGStab, FP64, zero start", "tol": 1e-12, "status": code_s,
+                        "iters": it_s, "true_rel_res": rr_s, "seconds": round(time.perf_counter() - t1, 2),
+                        "threads": host_threads()}
+            result["oracle_reference_solution"] = ref_info
+            log(f"[bench] x*: {ref_info}")
+            result["solve_step"].update(oracle_errors(oracle, U, step_x, b, kappa, x_star))
         solves = {}
         for method, lo, rel, eo in (("bicgstab", None, 0, 0), ("cgnr", None, 0, 0), ("bicgstab", W.WL_F32, 0, 0),
                                     ("bicgstab", W.WL_BF16S, 0, 0), ("bicgstab", W.WL_F16S, 0, 0),
@@ -490,37 +666,56 @@ def main():
                    f"{'_evenodd' if eo else ''}")
             solves[key] = {"seconds": round(dt, 4), "status": code, "iters": st["iters"], "outer": st["outer"],
                            "true_rel_res": st["true_rel_res"]}
+            if oracle is not None:
+                solves[key].update(oracle_errors(oracle, U, hi.unpack(x64).cpu().numpy(), b, kappa, x_star))
             log(f"[bench] solve {key}: {solves[key]}")
         base = solves["bicgstab_f64"]["seconds"]
         for k, v in solves.items():
             v["speedup_vs_bicgstab_f64"] = round(base / v["seconds"], 3)
         result["solves"] = solves
 
+    c2 = None
     if not args.no_extra and not args.no_batch:
         del ops, hi, b64, x64, work
         torch.cuda.empty_cache()
-        result["batching"] = bench_batching(W, inputs, torch, log)
+        c2 = bench_c2(W, inputs, torch, log, oracle)
+        result["single_lattice_16x16x16x32"] = c2
+        result["batching"] = bench_batching(W, inputs, torch, log, oracle)
         result["differentiable"] = bench_autograd(W, inputs, torch, log)
         result["domain_wall"] = bench_dwf(W, inputs, torch, log)
         result["enforced_halo"] = bench_halo(W, inputs, torch, log)
 
-    if not args.no_cpu:
-        import oracle
-        log("[bench] oracle check of the step solution (CPU)")
+    if oracle is not None:
+        if "oracle_true_rel_res" not in result["solve_step"]:
+            result["solve_step"].update(oracle_errors(oracle, U, step_x, b, kappa))
+        # the oracle's D on the same lattice: all host threads, then one
+        threads = host_threads()
+        log(f"[bench] CPU baseline: oracle D on {dims}, {threads} threads then 1 ({cpu_model()})")
         t1 = time.perf_counter()
-        r = oracle.apply(U, step_x, kappa) - b
-        result["solve_step"]["oracle_true_rel_res"] = float(np.linalg.norm(r) / np.linalg.norm(b))
+        oracle.apply(U, b, kappa)
         t_apply = time.perf_counter() - t1
-        reps = max(1, min(10, int(15.0 / max(t_apply, 1e-3))))
+        reps = max(1, min(10, int(12.0 / max(t_apply, 1e-3))))
         t1 = time.perf_counter()
         for _ in range(reps):
             oracle.apply(U, b, kappa)
         t_cpu = (time.perf_counter() - t1) / reps
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        result["cpu_baseline"] = {"value": round(FLOP_APPLY * V / t_cpu / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
-                                  "kind": "oracle",
-                                  "sample": f"{reps} FP64 oracle applications of D on the same {dims} lattice "
-                                            f"({t_cpu:.2f} s each, OpenMP)"}
+        omp_set_threads(1)
+        t1 = time.perf_counter()
+        oracle.apply(U, b, kappa)
+        t_one = time.perf_counter() - t1
+        omp_set_threads(threads)
+        result["cpu_baseline"] = {
+            "value": round(FLOP_APPLY * V / t_cpu / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} FP64 oracle applications of D on the same {dims} lattice ({t_cpu:.3f} s each, "
+                      f"OpenMP, {threads} threads); one more with 1 thread ({t_one:.2f} s)",
+            "single_thread_value": round(FLOP_APPLY * V / t_one / 1e9, 3),
+            "cpu_model": cpu_model(),
+            "gpu_fp64_apply_vs_cpu": (round(result["dslash"]["f64"]["GFLOP/s"] / (FLOP_APPLY * V / t_cpu / 1e9), 1)
+                                      if "dslash" in result else None)}
+        if c2 is not None and "oracle_solvers" in c2:
+            result["cpu_baseline"]["solvers_16x16x16x32"] = c2["oracle_solvers"]
+        if "oracle_reference_solution" in result:
+            result["cpu_baseline"]["reference_solve_32x32x32x64"] = result["oracle_reference_solution"]
     print(json.dumps(result), flush=True)
 
 

@@ -630,6 +630,8 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
     if (p.hflag) {  // mirror the status into host-visible memory for polling
         p.hrr[r] = sc.rr;
         p.hflag[r] = sc.flag;
+        if (p.hsc)
+            p.hsc[r] = sc;
     }
 }
 

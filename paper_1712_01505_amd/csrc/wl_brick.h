@@ -419,12 +419,16 @@ template <int P, int DAG, int RED, int APPLY>
 inline hipError_t brick_go(dim3 grid, dim3 block, size_t smem, const StencilParams &p, const BrickGeom &g,
                            hipStream_t st)
 {
-    static bool big = false;  // LDS beyond the default 64 KB limit, set once per instantiation
-    if (smem > 65536 && !big) {
-        // a failure here shows up as the launch's own error
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&brick_kernel<P, DAG, RED, APPLY>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        big = true;
+    // dynamic LDS beyond the default 64 KB: raise this kernel's limit to what
+    // the launch needs (the kernel's static LDS counts against the same
+    // 160 KB, so the limit is set to the size asked for, not to the maximum)
+    static size_t granted = 65536;
+    if (smem > granted) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brick_kernel<P, DAG, RED, APPLY>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess)
+            return e;
+        granted = smem;
     }
     hipLaunchKernelGGL((brick_kernel<P, DAG, RED, APPLY>), grid, block, smem, st, p, g);
     return hipGetLastError();

@@ -247,6 +247,7 @@ struct FinParams {
     double *out;      // F_SUM destination [nval][nrhs]
     int *hflag;       // optional host-visible copy of flag[nrhs] ...
     double *hrr;      // ... and rr[nrhs] (device pointers to mapped host memory)
+    Scalars *hsc;     // optional host-visible copy of every column's scalars (mapped host memory)
     int nrhs;
     int iter;
     double tol2;

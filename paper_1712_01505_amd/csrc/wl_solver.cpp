@@ -79,33 +79,41 @@ size_t engine_bytes(int solver, int prec, uint32_t V, int Lt, int nrhs)
         }                                                                                                      \
     } while (0)
 
-// Host-side buffers of one solve, kept in a pool: pinned copies of the
-// per-RHS scalars, host-visible (coherent, mapped) status written by the
-// finalize kernels, and lookahead events.
+// Host-side buffers of one solve, kept in a pool and allocated once: coherent
+// mapped host memory that the kernels read and write directly (no copy
+// kernels): the per-RHS scalars mirrored by the finalize kernels, the status
+// they mirror every iteration, scalar inputs and sums (d), and lookahead
+// events.
 constexpr int MAX_RHS = 64;
 constexpr int MAX_LOOK = 8;
 struct HostBufs {
-    Scalars *sc = nullptr;   // pinned, filled by copies
-    double *d = nullptr;     // pinned scratch [4 * MAX_RHS]
-    int *hflag = nullptr;    // coherent mapped status
+    Scalars *sc = nullptr;   // mirror of the device scalars (written by the finalize kernels)
+    double *d = nullptr;     // scratch [4 * MAX_RHS]: sums written by kernels, scalars read by kernels
+    int *hflag = nullptr;    // status mirror
     double *hrr = nullptr;
-    int *dflag = nullptr;    // device views of hflag / hrr
+    Scalars *dsc = nullptr;  // device views of sc, d, hflag, hrr
+    double *dd = nullptr;
+    int *dflag = nullptr;
     double *drr = nullptr;
     hipEvent_t ev[MAX_LOOK + 1] = {};
     bool ok = false;
     void create()
     {
-        ok = hipHostMalloc((void **)&sc, sizeof(Scalars) * MAX_RHS) == hipSuccess &&
-             hipHostMalloc((void **)&d, sizeof(double) * 4 * MAX_RHS) == hipSuccess &&
-             hipHostMalloc((void **)&hflag, sizeof(int) * MAX_RHS, hipHostMallocMapped | hipHostMallocCoherent) ==
-                 hipSuccess &&
-             hipHostMalloc((void **)&hrr, sizeof(double) * MAX_RHS, hipHostMallocMapped | hipHostMallocCoherent) ==
-                 hipSuccess &&
+        const unsigned f = hipHostMallocMapped | hipHostMallocCoherent;
+        ok = hipHostMalloc((void **)&sc, sizeof(Scalars) * MAX_RHS, f) == hipSuccess &&
+             hipHostMalloc((void **)&d, sizeof(double) * 4 * MAX_RHS, f) == hipSuccess &&
+             hipHostMalloc((void **)&hflag, sizeof(int) * MAX_RHS, f) == hipSuccess &&
+             hipHostMalloc((void **)&hrr, sizeof(double) * MAX_RHS, f) == hipSuccess &&
+             hipHostGetDevicePointer((void **)&dsc, sc, 0) == hipSuccess &&
+             hipHostGetDevicePointer((void **)&dd, d, 0) == hipSuccess &&
              hipHostGetDevicePointer((void **)&dflag, hflag, 0) == hipSuccess &&
              hipHostGetDevicePointer((void **)&drr, hrr, 0) == hipSuccess;
         for (int i = 0; ok && i <= MAX_LOOK; ++i)
             ok = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
     }
+    // device view of a location in d (the host writes it only while the
+    // stream is idle; kernels read or write it in stream order)
+    double *dev(double *h) const { return dd + (h - d); }
 };
 std::mutex g_pool_mu;
 std::vector<HostBufs *> g_pool;
@@ -274,7 +282,8 @@ struct Engine {
         return WL_OK;
     }
 
-    int fin(int fop, int a, int b, int c, int iter, double tol2)
+    // out: F_SUM destination (default: the engine's device sums)
+    int fin(int fop, int a, int b, int c, int iter, double tol2, double *out = nullptr)
     {
         FinParams p{};
         if (a >= 0) {
@@ -293,12 +302,13 @@ struct Engine {
             p.nvalC = nval[c];
         }
         p.sc = sc;
-        p.out = sums;
+        p.out = out ? out : sums;
         // the host reads the status at iteration ends only: the mid-iteration
         // steps skip the (PCIe) mirror writes
         const bool mid = fop == F_CG_ALPHA || fop == F_BI_ALPHA || fop == F_BI_OMEGA_RHO;
         p.hflag = mid ? nullptr : hb->dflag;
         p.hrr = mid ? nullptr : hb->drr;
+        p.hsc = mid ? nullptr : hb->dsc;
         p.nrhs = nrhs;
         p.iter = iter;
         p.tol2 = tol2;
@@ -333,10 +343,10 @@ struct Engine {
         return WL_OK;
     }
 
-    // Copy the per-RHS scalars to the host (synchronises the stream).
+    // The per-RHS scalars as the last end-of-iteration finalize mirrored them
+    // into host memory (synchronises the stream).
     int poll()
     {
-        WL_TRY(hipMemcpyAsync(sc_host, sc, sizeof(Scalars) * nrhs, hipMemcpyDeviceToHost, st));
         WL_TRY(hipStreamSynchronize(st));
         return WL_OK;
     }
@@ -475,9 +485,8 @@ struct Engine {
             return rc;
         if ((rc = blas(B_RES, r, nullptr, b, w, nullptr, nullptr, 0)))
             return rc;
-        if ((rc = fin(F_SUM, 0, -1, -1, 0, 0.0)))
+        if ((rc = fin(F_SUM, 0, -1, -1, 0, 0.0, hb->dev(out_host))))
             return rc;
-        WL_TRY(hipMemcpyAsync(out_host, sums, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
         WL_TRY(hipStreamSynchronize(st));
         return WL_OK;
     }
@@ -487,9 +496,8 @@ struct Engine {
         int rc;
         if ((rc = blas(B_NORM, nullptr, nullptr, b, nullptr, nullptr, nullptr, 2)))
             return rc;
-        if ((rc = fin(F_SUM, 2, -1, -1, 0, 0.0)))
+        if ((rc = fin(F_SUM, 2, -1, -1, 0, 0.0, hb->dev(out_host))))
             return rc;
-        WL_TRY(hipMemcpyAsync(out_host, sums, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
         WL_TRY(hipStreamSynchronize(st));
         return WL_OK;
     }
@@ -526,16 +534,13 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
     // per-column tolerance (even-odd: scaled to the Schur right-hand side)
     std::vector<double> tol(nrhs, prm->tol);
     if (tolc) {
-        double *t2d = (double *)arena.take(sizeof(double) * nrhs);
-        if (!t2d)
-            return WL_EWORKSPACE;
-        double *t2h = lease.b->d + 3 * nrhs;
+        double *t2h = lease.b->d + 3 * nrhs;  // read by the kernels through its device view
+        WL_TRY(hipStreamSynchronize(st));     // no earlier kernel still reads this location
         for (int r = 0; r < nrhs; ++r) {
             tol[r] = tolc[r];
             t2h[r] = tolc[r] * tolc[r];
         }
-        WL_TRY(hipMemcpyAsync(t2d, t2h, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-        E.tol2v = t2d;
+        E.tol2v = lease.b->dev(t2h);
     }
     E.adj = prm->dagger;
     E.lookahead = lookahead_of(prm);
@@ -623,12 +628,14 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     H.adj = L.adj = prm->dagger;
     void *r_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
     void *e_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
-    double *sig_dev = (double *)arena.take(sizeof(double) * nrhs);
-    double *tol2_dev = (double *)arena.take(sizeof(double) * nrhs);
-    if (!r_lo || !e_lo || !sig_dev || !tol2_dev)
+    if (!r_lo || !e_lo)
         return WL_EWORKSPACE;
     H.lookahead = L.lookahead = lookahead_of(prm);
     double *bb = lease.b->d, *rr = lease.b->d + nrhs, *sig = lease.b->d + 2 * nrhs, *t2 = lease.b->d + 3 * nrhs;
+    // sigma and the inner tolerances are written by the host between cycles
+    // (the stream idle after each true-residual check) and read by the kernels
+    // through the device view of that host memory
+    double *sig_dev = lease.b->dev(sig), *tol2_dev = lease.b->dev(t2);
     if ((rc = H.norm2(b, bb)))
         return rc;
     if (!prm->use_x0)
@@ -750,9 +757,6 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         }
         if (all_ok || stagnated || outer >= max_outer || total >= prm->maxiter)
             break;
-        WL_TRY(hipMemcpyAsync(sig_dev, sig, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-        if (reliable)
-            WL_TRY(hipMemcpyAsync(tol2_dev, t2, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
         // r_lo = r64 / sigma (0 for converged columns)
         WL_TRY(launch_convert(WL_F64, lo->prec, H.V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
         int done = 0;

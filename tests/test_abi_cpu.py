@@ -99,6 +99,35 @@ def test_bad_arguments_rejected_before_launch():
         got = wilson.wl_launch()
         assert L.wl_get_launch(op, 4, ctypes.byref(got)) == wilson.WL_OK
         assert (got.block, got.rhs_per_thread, got.rhs_lanes, got.xcd_remap, got.variant) == (256, 1, 4, 1, 1)
+        # brick walk (variant 7): the brick tiles (x, y, z), has block sites and a walk dividing Lt
+        def setb(block, brick, T, nrhs=1, lanes=1):
+            c = wilson.wl_launch(block=block, rhs_per_thread=1, rhs_lanes=lanes, xcd_remap=1, variant=7)
+            c.brick[0], c.brick[1], c.brick[2] = brick
+            c.t_steps = T
+            return L.wl_set_launch(op, nrhs, ctypes.byref(c))
+        assert setb(64, (4, 4, 4), 4) == wilson.WL_OK
+        assert setb(64, (4, 4, 4), 3) == wilson.WL_EINVAL  # 3 does not divide Lt = 4
+        assert setb(128, (4, 4, 4), 4) == wilson.WL_EINVAL  # block != brick sites
+        assert setb(64, (8, 4, 2), 4) == wilson.WL_EINVAL  # 8 does not divide Lx = 4
+        assert setb(64, (4, 4, 4), 4, nrhs=2, lanes=2) == wilson.WL_EINVAL  # one right-hand side per lane
+        assert L.wl_get_launch(op, 1, ctypes.byref(got)) == wilson.WL_OK
+        assert (got.variant, tuple(got.brick), got.t_steps) == (7, (4, 4, 4), 4)
+        # fused apply + inner products: argument checks happen before any launch
+        wb = ctypes.c_size_t(0)
+        assert L.wl_apply_dot_workspace_bytes(op, 1, ctypes.byref(wb)) == wilson.WL_OK and wb.value % 256 == 0
+        assert L.wl_apply_dot_workspace_bytes(op, 65, ctypes.byref(wb)) == wilson.WL_EINVAL
+        assert L.wilson_apply_dot(op, 512, 1024, None, 0, 1, wilson.WL_DOT_BICG, 2048, 4096, wb.value,
+                                  None) == wilson.WL_EINVAL  # BiCG kind needs v
+        assert L.wilson_apply_dot(op, 512, 1024, 1536, 0, 1, 9, 2048, 4096, wb.value, None) == wilson.WL_EINVAL
+        assert L.wilson_apply_dot(op, 512, 1024, 1536, 0, 1, wilson.WL_DOT_V, 2048, None, wb.value,
+                                  None) == wilson.WL_EWORKSPACE
+        assert L.wilson_apply_dot(op, 512, 1024, 1536, 0, 1, wilson.WL_DOT_V, 2048, 4096, wb.value - 8,
+                                  None) == wilson.WL_EWORKSPACE
+        assert L.wilson_apply_dot(op, 512, 1024, 1536, 0, 1, wilson.WL_DOT_V, 2052, 4096, wb.value,
+                                  None) == wilson.WL_EALIGN  # dots not 8-byte aligned
+        # a solve allocates nothing: no workspace is an error
+        prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
+        assert L.solve_bicgstab(op, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EWORKSPACE
         prm = wilson.wl_solve_params(tol=0.0, maxiter=10)
         assert L.solve_cgnr(op, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
         prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
