@@ -390,6 +390,23 @@ int wl_apply_dot_workspace_bytes(const wl_op *op, int nrhs, size_t *out_bytes);
 int wilson_apply_dot(const wl_op *op, void *out, const void *in, const void *v, int dagger, int nrhs, int kind,
                      double *dots, void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- The same fused apply for callers that cannot allocate ----
+ * For code under HIP graph capture, tight serving loops and harnesses that
+ * forbid device allocation: wilson_apply_dot without a workspace argument.
+ * Its partial sums live in a library-owned device array of
+ * WL_NOALLOC_SCRATCH_BYTES (one per GPU the library runs on, held until the
+ * process ends); the call itself allocates nothing.  A size needing more
+ * than that (wl_apply_dot_workspace_bytes > WL_NOALLOC_SCRATCH_BYTES, e.g.
+ * more than 9 right-hand sides at 32^3 x 64) returns WL_EWORKSPACE before
+ * any launch.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (two streams, two threads) race and must not
+ * be issued; calls in one stream are ordered and safe.  The array keeps the
+ * last call's partials; nothing in it needs to start at zero.  Arguments,
+ * results and errors as wilson_apply_dot.  Async. */
+#define WL_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int wilson_apply_dot_noalloc(const wl_op *op, void *out, const void *in, const void *v, int dagger, int nrhs,
+                             int kind, double *dots, void *stream);
+
 /* Plain device-to-device streaming copy of `bytes` (a multiple of 16, no
  * overlap): the reference point for achievable HBM bandwidth and for
  * calibrating hardware byte counters against a kernel of known traffic.

@@ -1176,6 +1176,48 @@ int wilson_apply_dot(const wl_op *op, void *out, const void *in, const void *v, 
     return apply_dot_run(op, out, in, v, dagger, nrhs, kind, dots, (double *)workspace, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------- allocation-free fused apply
+// The partial sums of wilson_apply_dot_noalloc live in this file-scope array
+// (one copy per GPU, held until the process ends).  Host code never uses
+// its name as an address: the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+static __device__ __align__(256) char scratch[WL_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+constexpr int SCRATCH_MAX_DEV = 64;
+static void *g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+
+static int scratch_on_current_device(void **out)
+{
+    int dev = 0;
+    CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV)
+        return WL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return WL_OK;
+}
+
+int wilson_apply_dot_noalloc(const wl_op *op, void *out, const void *in, const void *v, int dagger, int nrhs,
+                             int kind, double *dots, void *stream)
+{
+    int rc = apply_dot_args(op, out, in, v, dagger, nrhs, kind, dots);
+    if (rc != WL_OK)
+        return rc;
+    if (apply_dot_bytes(op, nrhs) > WL_NOALLOC_SCRATCH_BYTES)
+        return WL_EWORKSPACE;
+    void *work = nullptr;
+    if ((rc = scratch_on_current_device(&work)) != WL_OK)
+        return rc;
+    // every partial the finalize reads is written by the stencil first, so
+    // the array needs no clearing between calls
+    return apply_dot_run(op, out, in, v, dagger, nrhs, kind, dots, (double *)work, (hipStream_t)stream);
+}
+
 int wl_stream_copy(void *dst, const void *src, size_t bytes, void *stream)
 {
     if (!dst || !src || bytes % 16 != 0)

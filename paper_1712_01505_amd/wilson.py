@@ -38,7 +38,7 @@ EXPORTS = [
     "wl_stream_copy", "wl_strerror", "wl_last_hip_error", "wl_multi_plan_create", "wl_multi_plan_run",
     "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
     "wl_dw_op_create", "dwf_apply", "wl_halo_bytes", "wilson_apply_halo", "wl_eo_split", "wl_eo_merge",
-    "wilson_schur_apply", "wl_apply_dot_workspace_bytes", "wilson_apply_dot",
+    "wilson_schur_apply", "wl_apply_dot_workspace_bytes", "wilson_apply_dot", "wilson_apply_dot_noalloc",
 ]
 
 
@@ -136,6 +136,7 @@ def lib():
         "wl_multi_plan_destroy": [P],
         "wl_apply_dot_workspace_bytes": [P, I, ctypes.POINTER(SZ)],
         "wilson_apply_dot": [P, P, P, P, I, I, I, P, P, SZ, P],
+        "wilson_apply_dot_noalloc": [P, P, P, P, I, I, I, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -125,6 +125,18 @@ def test_bad_arguments_rejected_before_launch():
                                   None) == wilson.WL_EWORKSPACE
         assert L.wilson_apply_dot(op, 512, 1024, 1536, 0, 1, wilson.WL_DOT_V, 2052, 4096, wb.value,
                                   None) == wilson.WL_EALIGN  # dots not 8-byte aligned
+        # the allocation-free variant rejects sizes beyond its scratch array before any launch
+        big = ctypes.c_void_p()
+        gb = wilson.make_geom((32, 32, 32, 64))
+        assert L.wl_op_create(ctypes.byref(gb), 0.12, wilson.WL_F16S, 256, ctypes.byref(big)) == wilson.WL_OK
+        try:
+            assert L.wl_apply_dot_workspace_bytes(big, 16, ctypes.byref(wb)) == wilson.WL_OK
+            assert wb.value > 16 << 20
+            assert L.wilson_apply_dot_noalloc(big, 512, 1024, None, 0, 16, wilson.WL_DOT_NORM, 2048,
+                                              None) == wilson.WL_EWORKSPACE
+            assert L.wilson_apply_dot_noalloc(big, 512, 1024, None, 0, 1, 9, 2048, None) == wilson.WL_EINVAL
+        finally:
+            L.wl_op_destroy(big)
         # a solve allocates nothing: no workspace is an error
         prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
         assert L.solve_bicgstab(op, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EWORKSPACE
