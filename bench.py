@@ -138,6 +138,15 @@ def oracle_solve(oracle, U, b, kappa, tol=1e-12):
     return x, {"status": code, "iters": its, "restarts": restarts, "true_rel_res": rr}
 
 
+def per_iteration(st, seconds):
+    """Launch counts and time per Krylov iteration of a solve (whole call,
+    set-up and final residual included, divided by the iterations)."""
+    it = max(int(st["iters"]), 1)
+    return {"kernels": st["kernels"], "finalizes": st["finalizes"],
+            "kernels_per_iter": round(st["kernels"] / it, 2), "finalizes_per_iter": round(st["finalizes"] / it, 2),
+            "ms_per_iter": round(1e3 * seconds / it, 4)}
+
+
 def _time_ms(torch, fn, reps):
     fn()
     torch.cuda.synchronize()
@@ -282,7 +291,7 @@ def bench_batching(W, inputs, torch, log, oracle=None):
 def _copy_launch(W, src_op, dst_op, nrhs=1):
     c = W.wl_get_launch(src_op.handle, nrhs)
     W.wl_set_launch(dst_op.handle, nrhs, c[0], c[1], c[2], c[3], c[4],
-                    brick=c[5:8] if c[3] == W.VAR_BRICK else None, t_steps=c[8])
+                    brick=c[5:8] if c[3] == W.VAR_BRICK else None, t_steps=c[8], wg_per_cu=c[9])
 
 
 def bench_c2(W, inputs, torch, log, oracle=None):
@@ -339,19 +348,22 @@ def bench_c2(W, inputs, torch, log, oracle=None):
         out["oracle_reference_solution"] = info
     solves = {}
     for method in ("bicgstab", "cgnr"):
-        W.solve(None, bd, kappa, method=method, precision="f64", tol=1e-10, ops=(hi, None))  # warm-up
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        x, sst = W.solve(None, bd, kappa, method=method, precision="f64", tol=1e-10, ops=(hi, None),
-                         return_stats=True)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        r = {"seconds": round(dt, 4), "status": sst["status"], "iters": sst["iters"],
-             "stencil_calls": sst["stencil_calls"], "true_rel_res": sst["true_rel_res"]}
-        if oracle is not None:
-            r.update(oracle_errors(oracle, U, x.cpu().numpy(), b, kappa, x_star))
-        solves[method + "_f64"] = r
-        log(f"[bench] {dims} solve {method} f64: {r}")
+        for form in (0, 1):
+            W.solve(None, bd, kappa, method=method, precision="f64", tol=1e-10, ops=(hi, None), form=form)  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, sst = W.solve(None, bd, kappa, method=method, precision="f64", tol=1e-10, ops=(hi, None),
+                             return_stats=True, form=form)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            r = {"seconds": round(dt, 4), "status": sst["status"], "iters": sst["iters"],
+                 "stencil_calls": sst["stencil_calls"], "true_rel_res": sst["true_rel_res"]}
+            r.update(per_iteration(sst, dt))
+            if oracle is not None:
+                r.update(oracle_errors(oracle, U, x.cpu().numpy(), b, kappa, x_star))
+            key = method + "_f64" + ("_single_reduction" if form else "")
+            solves[key] = r
+            log(f"[bench] {dims} solve {key}: {r}")
     out["solves"] = solves
     if oracle is not None:
         # the oracle's solvers on the same system, timed on the host
@@ -549,9 +561,9 @@ def main():
                    for lo in [None] + [ops[p].handle for p in (1, 2, 3)] for s in (0, 1))
     work = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
-    def run_solve(method, lo_prec, reliable=args.reliable, eo=0):
+    def run_solve(method, lo_prec, reliable=args.reliable, eo=0, form=0):
         prm = W.wl_solve_params(tol=tol, maxiter=20000, inner_tol=0.0, max_outer=0, reliable=int(reliable),
-                                eo=int(eo), check_every=0,
+                                eo=int(eo), check_every=0, form=int(form),
                                 use_x0=0, workspace=work.data_ptr(), workspace_bytes=ws_bytes)
         st = (W.wl_solve_stats * 1)()
         fn = W.solve_cgnr if method == "cgnr" else W.solve_bicgstab
@@ -627,7 +639,8 @@ def main():
                    "inner": args.inner, "reliable_updates": bool(args.reliable), "value_counts": "1368 flop/site x stencil applications per step / step time"},
         "launch": tuned,
         "solve_step": {"iters": last["iters"], "outer": last["outer"], "stencil_calls": last["stencil_calls"],
-                       "true_rel_res": last["true_rel_res"], "seconds": round(ms_per_step / 1e3, 4)},
+                       "true_rel_res": last["true_rel_res"], "seconds": round(ms_per_step / 1e3, 4),
+                       **per_iteration(last, ms_per_step / 1e3)},
         "roofline": roofline,
     }
 
@@ -667,21 +680,26 @@ def main():
             log(f"[bench] x*: {ref_info}")
             result["solve_step"].update(oracle_errors(oracle, U, step_x, b, kappa, x_star))
         solves = {}
-        for method, lo, rel, eo in (("bicgstab", None, 0, 0), ("cgnr", None, 0, 0), ("bicgstab", W.WL_F32, 0, 0),
-                                    ("bicgstab", W.WL_BF16S, 0, 0), ("bicgstab", W.WL_F16S, 0, 0),
-                                    ("cgnr", W.WL_F16S, 0, 0), ("bicgstab", W.WL_F32, 1, 0),
-                                    ("bicgstab", W.WL_BF16S, 1, 0), ("bicgstab", W.WL_F16S, 1, 0),
-                                    ("cgnr", W.WL_F32, 0, 0), ("cgnr", W.WL_F32, 1, 0),
-                                    ("bicgstab", None, 0, 1), ("cgnr", None, 0, 1), ("bicgstab", W.WL_F32, 1, 1),
-                                    ("bicgstab", W.WL_F16S, 0, 1), ("bicgstab", W.WL_F16S, 1, 1)):
+        F16 = W.WL_F16S
+        for method, lo, rel, eo, form in (
+                ("bicgstab", None, 0, 0, 0), ("cgnr", None, 0, 0, 0), ("bicgstab", W.WL_F32, 0, 0, 0),
+                ("bicgstab", W.WL_BF16S, 0, 0, 0), ("bicgstab", F16, 0, 0, 0), ("cgnr", F16, 0, 0, 0),
+                ("bicgstab", W.WL_F32, 1, 0, 0), ("bicgstab", W.WL_BF16S, 1, 0, 0), ("bicgstab", F16, 1, 0, 0),
+                ("cgnr", W.WL_F32, 0, 0, 0), ("cgnr", W.WL_F32, 1, 0, 0),
+                ("bicgstab", None, 0, 1, 0), ("cgnr", None, 0, 1, 0), ("bicgstab", W.WL_F32, 1, 1, 0),
+                ("bicgstab", F16, 0, 1, 0), ("bicgstab", F16, 1, 1, 0),
+                # one reduction phase per iteration
+                ("bicgstab", None, 0, 0, 1), ("cgnr", None, 0, 0, 1), ("bicgstab", F16, 0, 0, 1),
+                ("cgnr", F16, 0, 0, 1)):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            code, st = run_solve(method, lo, rel, eo)
+            code, st = run_solve(method, lo, rel, eo, form)
             dt = time.perf_counter() - t1
             key = (f"{method}_{'f64' if lo is None else 'mixed_' + PNAME[lo]}{'_reliable' if rel else ''}"
-                   f"{'_evenodd' if eo else ''}")
+                   f"{'_evenodd' if eo else ''}{'_single_reduction' if form else ''}")
             solves[key] = {"seconds": round(dt, 4), "status": code, "iters": st["iters"], "outer": st["outer"],
                            "true_rel_res": st["true_rel_res"]}
+            solves[key].update(per_iteration(st, dt))
             if oracle is not None:
                 solves[key].update(oracle_errors(oracle, U, hi.unpack(x64).cpu().numpy(), b, kappa, x_star))
             log(f"[bench] solve {key}: {solves[key]}")

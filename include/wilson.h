@@ -212,6 +212,23 @@ typedef struct {
                              sites, then x_o = b_o + kappa H_oe x_e; Wilson ops with every
                              extent even.  x, b stay full packed fields; tol applies to
                              the full system, whose residual is recomputed at the end. */
+    int form;             /* iteration form (Sec. V-C: the vector updates and global
+                             reductions, not the stencil, bound the solver):
+                             0 = merged two-phase iterations (CGNR: 4 kernels and 2
+                             finalizes per iteration; BiCGStab: 4 kernels and 3
+                             finalizes, see below);
+                             1 = one reduction phase per iteration.  CGNR in
+                             Chronopoulos and Gear's form: z = D^dag r and q = D z
+                             with their norms, one finalize (alpha from
+                             |z|^2 / (|q|^2 - beta |z|^2 / alpha_prev)), one pass
+                             updating p, w = D p, x and r: 3 kernels + 1 finalize.
+                             BiCGStab rearranged around u = D r, v = D p and q = D v
+                             (s and t = D s are never formed before the scalars):
+                             4 kernels + 1 finalize, with more vector traffic.
+                             Both check |r| one iteration later (two extra stencils
+                             at the end); the same recurrences in exact
+                             arithmetic.  Form 1 with a mixed solve needs
+                             reliable = 0 (WL_EINVAL otherwise). */
 } wl_solve_params;
 
 typedef struct {
@@ -222,6 +239,8 @@ typedef struct {
     double iter_rel_res;  /* final iterated (recursive) relative residual */
     double true_rel_res;  /* final true relative residual ||b - D x|| / ||b|| (FP64) */
     double seconds;       /* wall time of the whole call */
+    int kernels;          /* kernel launches of the call (finalizes included) */
+    int finalizes;        /* single-workgroup finalize launches (the reduction phases) */
 } wl_solve_stats;
 
 /* Device workspace needed by a solve (hi op; lo op or NULL; solver id). */
@@ -236,8 +255,8 @@ int wl_solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int 
  * precision (Sec. II-C: the inner low-precision solver sets the speed).
  * With domain-wall ops (wl_dw_op_create; hi and lo with equal Ns, m0, m)
  * only solve_cgnr is offered and nrhs counts 5-d vectors.
- * BiCGStab runs a merged iteration: the second
- * product also returns <rh, s> and <rh, t>, so rho' = <rh, s> - omega <rh, t>
+ * BiCGStab (form 0) runs a merged iteration: the second product t = D s
+ * also returns <rh, s>, <rh, t> and |s|^2, so rho' = <rh, s> - omega <rh, t>
  * and beta are known before r' = s - omega t is formed, and one pass updates
  * x, r and the next p (the same recurrences; two vector passes and one
  * kernel fewer per iteration; an iteration followed by a reliable update
@@ -304,8 +323,14 @@ int wl_multi_plan_destroy(wl_multi_plan *plan);
 int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void *stream);
 
 /* Time the stencil launch candidates for (op geometry, precision, nrhs,
- * dagger) with HIP events and keep the fastest; the choice is cached in
- * memory and in the JSON file named by $WL_TUNE_CACHE (if set).  Synchronous. */
+ * dagger), for the plain apply and for each fused reduction the solvers use,
+ * with HIP events (a reduction with its finalize), and keep the fastest; the
+ * best brick walk is timed again with each occupancy cap (wg_per_cu).  The
+ * choices are kept in memory and, if $WL_TUNE_CACHE names a file, in that
+ * JSON file: {"entries": [...]}, one object per line with "key", the key's
+ * fields ("arch", "dims", "prec", "nrhs", "dagger", "reduction"), the launch
+ * shape (the wl_launch fields) and "us", the measured time per launch.  A
+ * later process reads the file on its first launch.  Synchronous. */
 int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
 
 /* Stencil launch configuration for (op, nrhs):
@@ -337,6 +362,10 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
  *                 from there (brick extents dividing Lx, Ly, Lz; t_steps
  *                 dividing Lt; rhs_per_thread = rhs_lanes = 1; Wilson ops).
  * brick, t_steps  variant 7 only (ignored otherwise).
+ * wg_per_cu       variant 7 only (else 0): 0 no cap, or 1, 2, 4, 8 -- each
+ *                 workgroup reserves 1/wg_per_cu of the CU's 160 KB of LDS,
+ *                 so at most that many workgroups (wg_per_cu x block / 256
+ *                 waves per SIMD) share a CU; the slices must fit the share.
  * Results do not depend on the configuration (16-bit t-walk and brick walk:
  * to rounding). */
 typedef struct {
@@ -347,6 +376,7 @@ typedef struct {
     int variant;
     int brick[3];
     int t_steps;
+    int wg_per_cu;
 } wl_launch;
 int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg);
 /* Force a configuration (WL_EINVAL if it breaks a rule above).  Used by
@@ -371,15 +401,16 @@ int wl_prof_read_aux(int prec, double *aux_site_rhs);
  * inner products the Krylov solvers fuse into their operator products
  * (paper Sec. V-C: the solver's linear algebra and reductions, not the
  * stencil, dominate its time):
- *   kind WL_DOT_BICG: 7 values per right-hand side r, <in, out>, |out|^2,
- *        <v, in>, <v, out> (BiCGStab's second product: omega and the next rho);
+ *   kind WL_DOT_BICG: 8 values per right-hand side r, <in, out>, |out|^2,
+ *        <v, in>, <v, out>, |in|^2 (BiCGStab's second product: omega, the
+ *        next rho and |s|^2);
  *   kind WL_DOT_V:    2 values, <v, out> (BiCGStab's <rh, D p>);
  *   kind WL_DOT_NORM: 1 value, |out|^2 (CG on the normal equations).
  * Complex values take two entries (re, im); <a, b> = sum conj(a_i) b_i,
  * accumulated in FP64 in a fixed order.  dots: DEVICE array of nval x nrhs
  * doubles, value-major (entry k of column r at dots[k nrhs + r]), 8-byte
  * aligned; for WL_DOT_BICG the order is Re<in,out>, Im<in,out>, |out|^2,
- * Re<v,in>, Im<v,in>, Re<v,out>, Im<v,out>.  v: packed spinor of the op's
+ * Re<v,in>, Im<v,in>, Re<v,out>, Im<v,out>, |in|^2.  v: packed spinor of the op's
  * precision (nrhs columns; may equal in; NULL only for WL_DOT_NORM).  The
  * stencil runs in the launch shape tuned for that reduction.  workspace:
  * caller-owned device scratch of wl_apply_dot_workspace_bytes (256-byte
@@ -397,7 +428,7 @@ int wilson_apply_dot(const wl_op *op, void *out, const void *in, const void *v, 
  * WL_NOALLOC_SCRATCH_BYTES (one per GPU the library runs on, held until the
  * process ends); the call itself allocates nothing.  A size needing more
  * than that (wl_apply_dot_workspace_bytes > WL_NOALLOC_SCRATCH_BYTES, e.g.
- * more than 9 right-hand sides at 32^3 x 64) returns WL_EWORKSPACE before
+ * more than 7 right-hand sides at 32^3 x 64) returns WL_EWORKSPACE before
  * any launch.  Every call on one GPU shares that GPU's array: calls that
  * overlap in time on one GPU (two streams, two threads) race and must not
  * be issued; calls in one stream are ordered and safe.  The array keeps the

@@ -122,16 +122,27 @@ hipError_t prof_stencil(int prec, const wl_op *op, int dagger, const LaunchCfg &
         e = launch_stencil(prec, dagger, cfg, p, st);
     if (e == hipSuccess)
         e = hipEventRecord(b, st);
-    const bool aux = p.aux && (p.red == RED_DOTV || p.red == RED_BICG);
+    // sites of extra vectors the fused reduction reads (RED_SR: three)
+    const int naux = p.red == RED_SR ? 3 : (p.aux && (p.red == RED_DOTV || p.red == RED_BICG)) ? 1 : 0;
     if (e == hipSuccess)
-        g_prof_pending.push_back(ProfRec{prec, a, b, (double)p.V * p.nrhs, aux ? (double)p.V * p.nrhs : 0.0});
+        g_prof_pending.push_back(ProfRec{prec, a, b, (double)p.V * p.nrhs, (double)naux * p.V * p.nrhs});
     (void)op;
     return e;
 }
 
 // ---------------------------------------------------------------- launch choice and autotune cache
+// Tuned launch shapes, keyed by (architecture, extents, precision, columns,
+// dagger, fused reduction) for single operators and by (architecture,
+// precision, columns, dagger, lattice list) for multi-lattice plans; kept in
+// memory and, if $WL_TUNE_CACHE names a file, in that JSON file (one entry
+// per line, each with its key, the key's fields and the launch shape).
+struct TuneEntry {
+    LaunchCfg c;
+    double us = 0.0;       // measured time of the choice (per launch; reductions with their finalize)
+    std::string fields;    // the key's fields as JSON members (written out as they came)
+};
 static std::mutex g_tune_mu;
-static std::map<std::string, LaunchCfg> g_tune;
+static std::map<std::string, TuneEntry> g_tune;
 static bool g_tune_loaded = false;
 
 static std::string arch_name()
@@ -145,15 +156,41 @@ static std::string arch_name()
     return c == std::string::npos ? n : n.substr(0, c);
 }
 
-static std::string tune_key(const wl_op *op, int nrhs, int dagger)
+static std::string tune_key(const wl_op *op, int nrhs, int dagger, int red)
 {
     char buf[160];
-    snprintf(buf, sizeof buf, "%s:%dx%dx%dx%d:p%d:n%d:d%d", arch_name().c_str(), op->g.dims[0], op->g.dims[1],
-             op->g.dims[2], op->g.dims[3], op->prec, nrhs, dagger);
+    snprintf(buf, sizeof buf, "%s:%dx%dx%dx%d:p%d:n%d:d%d:r%d", arch_name().c_str(), op->g.dims[0], op->g.dims[1],
+             op->g.dims[2], op->g.dims[3], op->prec, nrhs, dagger, red);
     return buf;
 }
 
-// Cache file: one line per entry, "key block rpt xcd variant lanes".
+static std::string tune_fields(const wl_op *op, int nrhs, int dagger, int red)
+{
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "\"arch\": \"%s\", \"dims\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, \"dagger\": %d, "
+             "\"reduction\": %d",
+             arch_name().c_str(), op->g.dims[0], op->g.dims[1], op->g.dims[2], op->g.dims[3], op->prec, nrhs, dagger,
+             red);
+    return buf;
+}
+
+// the number after "name": in a line of the cache file
+static bool json_num(const std::string &line, const char *name, double *v)
+{
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t at = line.find(pat);
+    return at != std::string::npos && sscanf(line.c_str() + at + pat.size(), " %lf", v) == 1;
+}
+static bool json_int(const std::string &line, const char *name, int *v)
+{
+    double d = 0.0;
+    if (!json_num(line, name, &d))
+        return false;
+    *v = (int)d;
+    return true;
+}
+
 static void load_tune_cache_locked()
 {
     if (g_tune_loaded)
@@ -165,14 +202,32 @@ static void load_tune_cache_locked()
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        std::istringstream is(line);
-        std::string key;
-        LaunchCfg c;
-        if (is >> key >> c.block >> c.rpt >> c.xcd >> c.var >> c.lanes) {
-            if (!(is >> c.bx >> c.by >> c.bz >> c.tsteps))
-                c.bx = c.by = c.bz = c.tsteps = 0;
-            g_tune[key] = c;
-        }
+        const size_t k0 = line.find("\"key\": \"");
+        if (k0 == std::string::npos)
+            continue;
+        const size_t ks = k0 + 8, ke = line.find('"', ks);
+        if (ke == std::string::npos)
+            continue;
+        TuneEntry t;
+        LaunchCfg &c = t.c;
+        bool ok = json_int(line, "block", &c.block) && json_int(line, "rhs_per_thread", &c.rpt) &&
+                  json_int(line, "rhs_lanes", &c.lanes) && json_int(line, "xcd_remap", &c.xcd) &&
+                  json_int(line, "variant", &c.var);
+        if (!ok)
+            continue;
+        const size_t br = line.find("\"brick\":");
+        if (br == std::string::npos || sscanf(line.c_str() + br + 8, " [%d , %d , %d ]", &c.bx, &c.by, &c.bz) != 3)
+            c.bx = c.by = c.bz = 0;
+        if (!json_int(line, "t_steps", &c.tsteps))
+            c.tsteps = 0;
+        if (!json_int(line, "wg_per_cu", &c.wpe))
+            c.wpe = 0;
+        (void)json_num(line, "us", &t.us);
+        // the key's fields: everything between the key and the launch shape
+        const size_t fs = line.find(',', ke), fe = line.find(", \"block\":");
+        if (fs != std::string::npos && fe != std::string::npos && fe > fs + 2)
+            t.fields = line.substr(fs + 2, fe - fs - 2);
+        g_tune[line.substr(ks, ke - ks)] = t;
     }
 }
 
@@ -182,10 +237,21 @@ static void save_tune_cache_locked()
     if (!path)
         return;
     std::ofstream f(path, std::ios::trunc);
-    for (auto &kv : g_tune)
-        f << kv.first << " " << kv.second.block << " " << kv.second.rpt << " " << kv.second.xcd << " "
-          << kv.second.var << " " << kv.second.lanes << " " << kv.second.bx << " " << kv.second.by << " "
-          << kv.second.bz << " " << kv.second.tsteps << "\n";
+    f << "{\"format\": \"wilson launch shapes\", \"entries\": [\n";
+    size_t i = 0;
+    for (auto &kv : g_tune) {
+        const LaunchCfg &c = kv.second.c;
+        char buf[512];
+        snprintf(buf, sizeof buf,
+                 "\"block\": %d, \"rhs_per_thread\": %d, \"rhs_lanes\": %d, \"xcd_remap\": %d, \"variant\": %d, "
+                 "\"brick\": [%d, %d, %d], \"t_steps\": %d, \"wg_per_cu\": %d, \"us\": %.3f",
+                 c.block, c.rpt, c.lanes, c.xcd, c.var, c.bx, c.by, c.bz, c.tsteps, c.wpe, kv.second.us);
+        f << "{\"key\": \"" << kv.first << "\", ";
+        if (!kv.second.fields.empty())
+            f << kv.second.fields << ", ";
+        f << buf << "}" << (++i < g_tune.size() ? "," : "") << "\n";
+    }
+    f << "]}\n";
 }
 
 // Untuned defaults (measured on MI355X at 32^3 x 64): one right-hand side
@@ -232,7 +298,8 @@ static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
            (c.var < 4 || c.var == VAR_BRICK ||
             (c.block <= 256 && op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0)) &&
            (c.var != VAR_BRICK || (op->ns == 0 && c.lanes == 1 && c.bx * c.by * c.bz == c.block &&
-                                   brick_ok(op->g.dims, prec, c.bx, c.by, c.bz, c.tsteps)));
+                                   brick_ok(op->g.dims, prec, c.bx, c.by, c.bz, c.tsteps, c.wpe))) &&
+           (c.wpe == 0 || c.var == VAR_BRICK);
 }
 
 // Brick shapes (variant 7) for extents L: x extent 8, 16 or 32, the rest
@@ -269,57 +336,46 @@ static void brick_candidates(const wl_op *op, std::vector<LaunchCfg> &out)
         }
 }
 
-// Launch configurations are kept per (nrhs, fused reduction): the solver's
-// stencils with a reduction epilogue are tuned separately from the plain
-// apply.  A reduction kind without its own entry uses the plain one.
-static int launch_key(int nrhs, int red) { return nrhs * 8 + red; }
+// Launch configurations are kept per (nrhs, fused reduction, dagger): the
+// solver's stencils with a reduction epilogue are tuned separately from the
+// plain apply.  A combination without its own entry takes the other dagger's,
+// then the plain apply's, then the default.
+static int launch_key(int nrhs, int red, int dagger) { return (nrhs * 8 + red) * 2 + dagger; }
 
-static std::string tune_key_red(const wl_op *op, int nrhs, int red)
-{
-    return red == RED_NONE ? tune_key(op, nrhs, 0) : tune_key(op, nrhs, 0) + ":r" + std::to_string(red);
-}
-
-LaunchCfg launch_for(const wl_op *op, int nrhs, int red)
+LaunchCfg launch_for(const wl_op *op, int nrhs, int red, int dagger)
 {
     wl_op *o = const_cast<wl_op *>(op);
     {
         std::lock_guard<std::mutex> lk(o->mu);
-        auto it = o->launch.find(launch_key(nrhs, red));
+        auto it = o->launch.find(launch_key(nrhs, red, dagger));
         if (it != o->launch.end())
             return it->second;
     }
-    // first use of this (nrhs, reduction): the tune cache's entry for the
-    // reduction, else this op's plain-apply choice, else the cache's
-    // plain-apply entry, else the default
+    // first use of this (nrhs, reduction, dagger): search the op's choices
+    // and the tune cache in the order above
     LaunchCfg c = default_launch(op, nrhs);
+    const int order[4][2] = {{red, dagger}, {red, 1 - dagger}, {RED_NONE, dagger}, {RED_NONE, 1 - dagger}};
     bool have = false;
-    {
+    for (int k = 0; k < 4 && !have; ++k) {
+        {
+            std::lock_guard<std::mutex> lk(o->mu);
+            auto it = o->launch.find(launch_key(nrhs, order[k][0], order[k][1]));
+            if (it != o->launch.end()) {
+                c = it->second;
+                have = true;
+                break;
+            }
+        }
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_cache_locked();
-        auto it = g_tune.find(tune_key_red(op, nrhs, red));
-        if (it != g_tune.end() && launch_ok(op, nrhs, it->second)) {
-            c = it->second;
+        auto it = g_tune.find(tune_key(op, nrhs, order[k][1], order[k][0]));
+        if (it != g_tune.end() && launch_ok(op, nrhs, it->second.c)) {
+            c = it->second.c;
             have = true;
         }
     }
-    if (!have && red != RED_NONE) {
-        {
-            std::lock_guard<std::mutex> lk(o->mu);
-            auto it0 = o->launch.find(launch_key(nrhs, RED_NONE));
-            if (it0 != o->launch.end()) {
-                c = it0->second;
-                have = true;
-            }
-        }
-        if (!have) {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            auto it = g_tune.find(tune_key_red(op, nrhs, RED_NONE));
-            if (it != g_tune.end() && launch_ok(op, nrhs, it->second))
-                c = it->second;
-        }
-    }
     std::lock_guard<std::mutex> lk(o->mu);
-    o->launch[launch_key(nrhs, red)] = c;
+    o->launch[launch_key(nrhs, red, dagger)] = c;
     return c;
 }
 
@@ -377,6 +433,19 @@ static std::string multi_key(const wl_multi_plan *pl)
         k += buf;
     }
     return k;
+}
+
+static std::string multi_fields(const wl_multi_plan *pl)
+{
+    std::string f = "\"arch\": \"" + arch_name() + "\", \"multi_lattice\": [";
+    for (size_t i = 0; i < pl->desc.size(); ++i) {
+        const int *L = pl->desc[i].op->g.dims;
+        char buf[64];
+        snprintf(buf, sizeof buf, "%s[%d, %d, %d, %d]", i ? ", " : "", L[0], L[1], L[2], L[3]);
+        f += buf;
+    }
+    return f + "], \"prec\": " + std::to_string(pl->prec) + ", \"nrhs\": " + std::to_string(pl->nrhs) +
+           ", \"dagger\": " + std::to_string(pl->dagger);
 }
 
 // (Re)build the descriptor table for launch shape c and upload it
@@ -562,7 +631,7 @@ static int stencil_call(const wl_op *op, void *out, const void *in, int dagger, 
         return WL_EINVAL;
     if (!al16(out) || !al16(in))
         return WL_EALIGN;
-    LaunchCfg cfg = launch_for(op, nrhs, RED_NONE);
+    LaunchCfg cfg = launch_for(op, nrhs, RED_NONE, dagger);
     if (nrhs % cfg.rpt != 0) {
         cfg.rpt = 1;
         cfg.var = 0;
@@ -598,7 +667,7 @@ int wilson_apply_halo(const wl_op *op, void *out, const void *in, int dagger, in
         return WL_EWORKSPACE;
     if (!al16(out) || !al16(in) || !al16(halo))
         return WL_EALIGN;
-    LaunchCfg cfg = launch_for(op, nrhs, RED_NONE);
+    LaunchCfg cfg = launch_for(op, nrhs, RED_NONE, dagger);
     if (cfg.rpt == 1 && cfg.var >= 4) {  // the t-walk keeps its t hops in registers: use the hop loop
         cfg.var = op->prec == WL_F64 ? 1 : 2;
         cfg.xcd = cfg.xcd ? 1 : 0;
@@ -719,7 +788,11 @@ static int solve_entry(int solver, const wl_op *hi, const wl_op *lo, void *x, co
                        const wl_solve_params *p, wl_solve_stats *stats, void *stream)
 {
     if (!hi || !x || !b || !p || nrhs < 1 || op_cols(hi, nrhs) > 64 || x == b || !(p->tol > 0) ||
-        p->maxiter < 1 || (p->dagger != 0 && p->dagger != 1))
+        p->maxiter < 1 || (p->dagger != 0 && p->dagger != 1) || (p->form != 0 && p->form != 1))
+        return WL_EINVAL;
+    // the single-reduction forms keep recurrences (w = D p; v = D p and
+    // q = D v) that a residual replacement would break: defect correction only
+    if (p->form == 1 && lo && p->reliable)
         return WL_EINVAL;
     if (hi->ns > 0 && solver != WL_SOLVER_CGNR)
         return WL_EINVAL;  // domain wall: CG on the normal equations only (Sec. II-C, Sec. VI-B)
@@ -808,9 +881,9 @@ int wl_multi_plan_create(const wl_multi_desc *d, int n, int dagger, int nrhs, wl
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_cache_locked();
         auto it = g_tune.find(multi_key(pl));
-        if (it != g_tune.end() && nrhs % it->second.rpt == 0 &&
-            multi_launch_ok(prec, it->second.rpt, it->second.block, it->second.var))
-            c = it->second;
+        if (it != g_tune.end() && nrhs % it->second.c.rpt == 0 &&
+            multi_launch_ok(prec, it->second.c.rpt, it->second.c.block, it->second.c.var))
+            c = it->second.c;
     }
     const int rc = plan_build(pl, c);
     if (rc != WL_OK) {
@@ -884,7 +957,11 @@ int wl_multi_plan_tune(wl_multi_plan *pl, void *stream)
         return rc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache_locked();
-    g_tune[multi_key(pl)] = best;
+    TuneEntry te;
+    te.c = best;
+    te.us = best_ms * 1e3 / 10;
+    te.fields = multi_fields(pl);
+    g_tune[multi_key(pl)] = te;
     save_tune_cache_locked();
     return WL_OK;
 }
@@ -937,7 +1014,7 @@ int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg)
 {
     if (!op || nrhs < 1 || !cfg)
         return WL_EINVAL;
-    const LaunchCfg c = launch_for(op, op_cols(op, nrhs), RED_NONE);
+    const LaunchCfg c = launch_for(op, op_cols(op, nrhs), RED_NONE, 0);
     cfg->block = c.block;
     cfg->rhs_per_thread = c.rpt;
     cfg->rhs_lanes = c.lanes;
@@ -947,6 +1024,7 @@ int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg)
     cfg->brick[1] = c.by;
     cfg->brick[2] = c.bz;
     cfg->t_steps = c.tsteps;
+    cfg->wg_per_cu = c.wpe;
     return WL_OK;
 }
 
@@ -966,12 +1044,16 @@ int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg)
         c.by = cfg->brick[1];
         c.bz = cfg->brick[2];
         c.tsteps = cfg->t_steps;
+        c.wpe = cfg->wg_per_cu;
+    } else if (cfg->wg_per_cu != 0) {
+        return WL_EINVAL;
     }
     if (!launch_ok(op, nrhs, c))
         return WL_EINVAL;
     std::lock_guard<std::mutex> lk(op->mu);
-    for (int red = RED_NONE; red <= RED_BICG; ++red)  // every stencil of this nrhs
-        op->launch[launch_key(nrhs, red)] = c;
+    for (int red = RED_NONE; red <= RED_LAST; ++red)  // every stencil of this nrhs
+        for (int d = 0; d <= 1; ++d)
+            op->launch[launch_key(nrhs, red, d)] = c;
     return WL_OK;
 }
 
@@ -1017,69 +1099,90 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
                 cands.push_back(c);
     }
     // the plain apply, then each fused reduction of the solvers (partials
-    // and the <v, out> operand in scratch)
-    LaunchCfg bests[RED_BICG + 1];
+    // and the <v, out> operands in scratch)
+    LaunchCfg bests[RED_LAST + 1];
+    double best_us[RED_LAST + 1] = {};
     double *parts = nullptr, *sums = nullptr;
     if (e == hipSuccess)
         e = hipMalloc(&parts, RED_NVAL_MAX * sizeof(double) * (size_t)nrhs * ((op->V + 63) / 64 + op->g.dims[3] + 8));
     if (e == hipSuccess)
         e = hipMalloc(&sums, RED_NVAL_MAX * sizeof(double) * (size_t)nrhs);
+    // time one shape for one reduction kind (ms per launch, or < 0 when the
+    // shape cannot be launched for lack of resources)
+    auto time_shape = [&](const LaunchCfg &c, int red) -> float {
+        StencilParams p = base_params(op, out, in, nrhs, 1);
+        p.red = red;
+        p.partials = parts;
+        p.aux = p.aux2 = p.aux3 = in;
+        // a fused reduction is timed with the finalize that sums its
+        // partials: fewer, larger workgroups leave it less to read
+        FinParams fp{};
+        fp.A = parts;
+        fp.nblkA = stencil_partials(c, p.L, op->V, nrhs);
+        fp.nvalA = stencil_nval(red);
+        fp.out = sums;
+        fp.nrhs = nrhs;
+        fp.group = 1;
+        auto step = [&]() {
+            hipError_t r = launch_stencil(op->prec, dagger, c, p, st);
+            if (r == hipSuccess && red != RED_NONE)
+                r = launch_finalize(F_SUM, fp, st);
+            return r;
+        };
+        for (int w = 0; w < 2 && e == hipSuccess; ++w)
+            e = step();
+        if (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration || e == hipErrorLaunchOutOfResources) {
+            (void)hipGetLastError();  // a shape this kernel cannot be launched with: skip it
+            e = hipSuccess;
+            return -1.f;
+        }
+        const int reps = 10;
+        if (e == hipSuccess)
+            e = hipEventRecord(a, st);
+        for (int k = 0; k < reps && e == hipSuccess; ++k)
+            e = step();
+        if (e == hipSuccess)
+            e = hipEventRecord(b, st);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, a, b);
+        return e == hipSuccess ? ms / reps : -1.f;
+    };
     // a domain-wall operator has only the reductions of CG on the normal equations
-    const int last_red = op->ns > 0 ? (int)RED_NORM : (int)RED_BICG;
-    for (int red = RED_NONE; red <= RED_BICG && e == hipSuccess; ++red) {
-        float best_ms = INFINITY;
-        LaunchCfg best = default_launch(op, nrhs);
+    const int last_red = op->ns > 0 ? (int)RED_NORM : (int)RED_LAST;
+    for (int red = RED_NONE; red <= RED_LAST && e == hipSuccess; ++red) {
         if (red > last_red) {
             bests[red] = bests[last_red];
+            best_us[red] = best_us[last_red];
             continue;
         }
+        float best_ms = INFINITY;
+        LaunchCfg best = default_launch(op, nrhs);
         for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
-            const LaunchCfg c = cands[ci];
-            StencilParams p = base_params(op, out, in, nrhs, 1);
-            p.red = red;
-            p.partials = parts;
-            p.aux = in;
-            // a fused reduction is timed with the finalize that sums its
-            // partials: fewer, larger workgroups leave it less to read
-            FinParams fp{};
-            fp.A = parts;
-            fp.nblkA = stencil_partials(c, p.L, op->V, nrhs);
-            fp.nvalA = stencil_nval(red);
-            fp.out = sums;
-            fp.nrhs = nrhs;
-            fp.group = 1;
-            auto step = [&]() {
-                hipError_t r = launch_stencil(op->prec, dagger, c, p, st);
-                if (r == hipSuccess && red != RED_NONE)
-                    r = launch_finalize(F_SUM, fp, st);
-                return r;
-            };
-            for (int w = 0; w < 2 && e == hipSuccess; ++w)
-                e = step();
-            if (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration || e == hipErrorLaunchOutOfResources) {
-                // a shape this kernel cannot be launched with (resources): skip it
-                (void)hipGetLastError();
-                e = hipSuccess;
-                continue;
-            }
-            const int reps = 10;
-            if (e == hipSuccess)
-                e = hipEventRecord(a, st);
-            for (int k = 0; k < reps && e == hipSuccess; ++k)
-                e = step();
-            if (e == hipSuccess)
-                e = hipEventRecord(b, st);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(b);
-            float ms = 0.f;
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, a, b);
-            if (e == hipSuccess && ms < best_ms) {
+            const float ms = time_shape(cands[ci], red);
+            if (ms >= 0.f && ms < best_ms) {
                 best_ms = ms;
-                best = c;
+                best = cands[ci];
             }
         }
+        // the best brick walk again with its occupancy capped (workgroups per
+        // CU, i.e. waves per SIMD), which trades latency hiding for L2 reuse
+        if (best.var == VAR_BRICK)
+            for (int wpe = 1; wpe <= 8 && e == hipSuccess; wpe *= 2) {
+                LaunchCfg c = best;
+                c.wpe = wpe;
+                if (!launch_ok(op, nrhs, c))
+                    continue;
+                const float ms = time_shape(c, red);
+                if (ms >= 0.f && ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
         bests[red] = best;
+        best_us[red] = std::isfinite(best_ms) ? 1e3 * best_ms : 0.0;
     }
     if (a)
         (void)hipEventDestroy(a);
@@ -1095,13 +1198,18 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
     {
         wl_op *o = const_cast<wl_op *>(op);
         std::lock_guard<std::mutex> lk(o->mu);
-        for (int red = RED_NONE; red <= RED_BICG; ++red)
-            o->launch[launch_key(nrhs, red)] = bests[red];
+        for (int red = RED_NONE; red <= RED_LAST; ++red)
+            o->launch[launch_key(nrhs, red, dagger)] = bests[red];
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache_locked();
-    for (int red = RED_NONE; red <= RED_BICG; ++red)
-        g_tune[tune_key_red(op, nrhs, red)] = bests[red];
+    for (int red = RED_NONE; red <= RED_LAST; ++red) {
+        TuneEntry t;
+        t.c = bests[red];
+        t.us = best_us[red];
+        t.fields = tune_fields(op, nrhs, dagger, red);
+        g_tune[tune_key(op, nrhs, dagger, red)] = t;
+    }
     save_tune_cache_locked();
     return WL_OK;
 }
@@ -1117,7 +1225,7 @@ static int dot_red(int kind)
 static size_t apply_dot_bytes(const wl_op *op, int nrhs)
 {
     const size_t nblk = (size_t)(op->V + 63) / 64 + (size_t)op->g.dims[3] + 8;
-    return ((size_t)RED_NVAL_MAX * nrhs * nblk * sizeof(double) + 255) / 256 * 256;
+    return ((size_t)red_nval(RED_BICG) * nrhs * nblk * sizeof(double) + 255) / 256 * 256;  // the largest kind
 }
 
 int wl_apply_dot_workspace_bytes(const wl_op *op, int nrhs, size_t *out_bytes)
@@ -1138,7 +1246,7 @@ int apply_dot_run(const wl_op *op, void *out, const void *in, const void *v, int
     p.red = red;
     p.aux = v;
     p.partials = work;
-    LaunchCfg cfg = launch_for(op, nrhs, red);
+    LaunchCfg cfg = launch_for(op, nrhs, red, dagger);
     FinParams fp{};
     fp.A = work;
     fp.nblkA = stencil_partials(cfg, p.L, op->V, nrhs);

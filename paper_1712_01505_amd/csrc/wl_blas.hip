@@ -51,11 +51,25 @@ __device__ __forceinline__ void round_if_scaled(cx<typename Traits<P>::real> (&v
     }
 }
 
+// values reduced by each op, and sites per thread (ops with many reduced
+// values cover more sites per workgroup, so that the finalize reads fewer
+// partial sums)
+__host__ __device__ constexpr int blas_nv(int op)
+{
+    return (op == B_RES || op == B_CG_XR || op == B_NORM || op == B_BI_XRP || op == B_CG1 || op == B_SR_XR) ? 1
+           : (op == B_BI_XR || op == B_DOT_NORM)                                                           ? 3
+           : op == B_SR_PV                                                                                 ? 9
+                                                                                                           : 0;
+}
+__host__ __device__ constexpr int blas_spt(int op) { return op == B_SR_PV ? 4 : 1; }
+
 template <int P, int OP>
 __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
 {
     using T = typename Traits<P>::real;
-    __shared__ double lds[3 * 4];
+    constexpr int NV = blas_nv(OP);
+    constexpr int NA = NV > 0 ? NV : 1;
+    __shared__ double lds[NA * 4];
     const int r = blockIdx.y;
     const uint32_t V = p.V;
     const int nr = p.nrhs;
@@ -63,8 +77,9 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
         return;
     if (OP == B_CG_RESTART && !p.sc[r].restart)
         return;
-    double red[3] = {0.0, 0.0, 0.0};
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    double red[NA] = {};
+    for (int j = 0; j < blas_spt(OP); ++j) {
+    const uint32_t s = (blockIdx.x * blas_spt(OP) + j) * blockDim.x + threadIdx.x;
     if (s < V) {
         const Scalars &sc = p.sc[r];
         if constexpr (OP == B_RES) {  // r = b - w
@@ -114,7 +129,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
                 pp[k] = cfma(b, d, rr[k]);
             }
             store_site<P>(p.y0, V, nr, s, r, pp);
-        } else if constexpr (OP == B_BI_S) {  // s = r - alpha v
+        } else if constexpr (OP == B_BI_S) {  // s = r - alpha v (|s|^2 comes with t = D s)
             const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y};
             cx<T> rr[12], v[12];
             load_site<P>(p.a0, V, nr, s, r, rr);
@@ -122,8 +137,86 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 rr[k] = cfma(cx<T>{-a.re, -a.im}, v[k], rr[k]);
-            round_if_scaled<P>(rr);
             store_site<P>(p.y0, V, nr, s, r, rr);
+        } else if constexpr (OP == B_CG1) {
+            // p = z + beta p ; w = q + beta w ; x += alpha p ; r -= alpha w
+            const T a = (T)sc.alpha.x, b = (T)sc.beta.x;
+            cx<T> x[12], rr[12], pp[12], w[12], z[12], q[12];
+            load_site<P>(p.y2, V, nr, s, r, pp);
+            load_site<P>(p.y3, V, nr, s, r, w);
+            load_site<P>(p.a0, V, nr, s, r, z);
+            load_site<P>(p.a1, V, nr, s, r, q);
+            load_site<P>(p.y0, V, nr, s, r, x);
+            load_site<P>(p.y1, V, nr, s, r, rr);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                pp[k] = rfma(b, pp[k], z[k]);
+                w[k] = rfma(b, w[k], q[k]);
+            }
+            // the stored p and w are what the next iteration reads
+            round_if_scaled<P>(pp);
+            round_if_scaled<P>(w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                x[k] = rfma(a, pp[k], x[k]);
+                rr[k] = rfma(-a, w[k], rr[k]);
+            }
+            round_if_scaled<P>(rr);
+            store_site<P>(p.y2, V, nr, s, r, pp);
+            store_site<P>(p.y3, V, nr, s, r, w);
+            store_site<P>(p.y0, V, nr, s, r, x);
+            store_site<P>(p.y1, V, nr, s, r, rr);
+            red[0] += n2(rr);
+        } else if constexpr (OP == B_SR_PV) {
+            // p = r + beta (p - omega v) ; v = u + beta (v - omega q) ; then
+            // <rh, v>, <rh, u>, <u, r>, <u, v>, |u|^2 of the stored values
+            const cx<T> b{(T)sc.beta.x, (T)sc.beta.y}, om{(T)sc.omega.x, (T)sc.omega.y};
+            const cx<T> mom{-om.re, -om.im};
+            cx<T> pp[12], v[12], rr[12], u[12], q[12];
+            load_site<P>(p.y0, V, nr, s, r, pp);
+            load_site<P>(p.y1, V, nr, s, r, v);
+            load_site<P>(p.a0, V, nr, s, r, rr);
+            load_site<P>(p.a1, V, nr, s, r, u);
+            load_site<P>(p.a2, V, nr, s, r, q);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                pp[k] = cfma(b, cfma(mom, v[k], pp[k]), rr[k]);
+                v[k] = cfma(b, cfma(mom, q[k], v[k]), u[k]);
+            }
+            round_if_scaled<P>(v);
+            store_site<P>(p.y0, V, nr, s, r, pp);
+            store_site<P>(p.y1, V, nr, s, r, v);
+            cx<T> rh[12];
+            load_site<P>(p.a3, V, nr, s, r, rh);
+            dot(rh, v, red[0], red[1]);
+            dot(rh, u, red[2], red[3]);
+            dot(u, rr, red[4], red[5]);
+            dot(u, v, red[6], red[7]);
+            red[8] += n2(u);
+        } else if constexpr (OP == B_SR_XR) {
+            // s = r - alpha v ; x += alpha p + omega s ; r = s - omega (u - alpha q)
+            const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
+            const cx<T> ma{-a.re, -a.im}, mom{-om.re, -om.im};
+            cx<T> x[12], rr[12], pp[12], v[12];
+            load_site<P>(p.y0, V, nr, s, r, x);
+            load_site<P>(p.y1, V, nr, s, r, rr);
+            load_site<P>(p.a0, V, nr, s, r, pp);
+            load_site<P>(p.a1, V, nr, s, r, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                rr[k] = cfma(ma, v[k], rr[k]);  // s
+                x[k] = cfma(a, pp[k], x[k]);
+                x[k] = cfma(om, rr[k], x[k]);
+            }
+            cx<T> u[12], q[12];
+            load_site<P>(p.a2, V, nr, s, r, u);
+            load_site<P>(p.a3, V, nr, s, r, q);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                rr[k] = cfma(mom, cfma(ma, q[k], u[k]), rr[k]);
+            round_if_scaled<P>(rr);
+            store_site<P>(p.y0, V, nr, s, r, x);
+            store_site<P>(p.y1, V, nr, s, r, rr);
             red[0] += n2(rr);
         } else if constexpr (OP == B_BI_XR) {  // x += alpha p + omega s ; r = s - omega t
             const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
@@ -200,11 +293,9 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             red[2] += n2(b);
         }
     }
-    constexpr int NV = (OP == B_RES || OP == B_CG_XR || OP == B_BI_S || OP == B_NORM || OP == B_BI_XRP) ? 1
-                       : (OP == B_BI_XR || OP == B_DOT_NORM)                          ? 3
-                                                                                       : 0;
+    }
     if constexpr (NV > 0) {
-        block_sum<3>(red, lds);
+        block_sum<NV>(red, lds);
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int k = 0; k < NV; ++k)
@@ -213,14 +304,7 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
     }
 }
 
-int blas_nval(int op)
-{
-    switch (op) {
-    case B_RES: case B_CG_XR: case B_BI_S: case B_NORM: case B_BI_XRP: return 1;
-    case B_BI_XR: case B_DOT_NORM: return 3;
-    default: return 0;
-    }
-}
+int blas_nval(int op) { return blas_nv(op); }
 
 template <int P>
 static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hipStream_t st)
@@ -238,6 +322,9 @@ static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hip
     case B_DOT_NORM: hipLaunchKernelGGL((blas_kernel<P, B_DOT_NORM>), g, b, 0, st, p); break;
     case B_CG_RESTART: hipLaunchKernelGGL((blas_kernel<P, B_CG_RESTART>), g, b, 0, st, p); break;
     case B_BI_XRP: hipLaunchKernelGGL((blas_kernel<P, B_BI_XRP>), g, b, 0, st, p); break;
+    case B_CG1: hipLaunchKernelGGL((blas_kernel<P, B_CG1>), g, b, 0, st, p); break;
+    case B_SR_PV: hipLaunchKernelGGL((blas_kernel<P, B_SR_PV>), g, b, 0, st, p); break;
+    case B_SR_XR: hipLaunchKernelGGL((blas_kernel<P, B_SR_XR>), g, b, 0, st, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -246,16 +333,16 @@ static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hip
 // One workgroup per `block` sites and column.  (A grid-stride variant capped
 // at 2048 workgroups, which shrinks the finalize's input, measured slower
 // overall: the streaming kernels lost more than the finalize gained.)
-int blas_partials(uint32_t V, int nrhs, int block)
+int blas_partials(uint32_t V, int op, int block)
 {
-    (void)nrhs;
-    return (int)((V + block - 1) / (uint32_t)block);
+    const uint32_t per = (uint32_t)block * (uint32_t)blas_spt(op);
+    return (int)((V + per - 1) / per);
 }
 
 hipError_t launch_blas(int prec, int op, const BlasParams &p0, int block, hipStream_t st)
 {
     BlasParams p = p0;
-    p.nblk = blas_partials(p.V, p.nrhs, block);
+    p.nblk = blas_partials(p.V, op, block);
     dim3 g(p.nblk, p.nrhs), b(block);
     switch (prec) {
     case F64: return launch_blas_p<F64>(op, p, g, b, st);
@@ -312,6 +399,15 @@ constexpr int FIN_G = 4;         // rows summed per pass (one pass for the usual
 constexpr int FIN_U = 4;         // loads per thread per row and pass
 
 __device__ __forceinline__ bool finite2(double a) { return isfinite(a); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b)  // b != 0
+{
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
 
 struct RowRef {
     const double *p;
@@ -420,7 +516,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
     switch (op) {
     case F_INIT_CG: {
         sc.rr = sA[r];
-        sc.zz = sB[r];
+        sc.zz = p.nvalB > 0 ? sB[r] : 0.0;  // the single-reduction form computes z in its loop
         sc.bb = sC[r];
         sc.rr_upd = sc.rr;
         sc.restart = 0;
@@ -532,10 +628,10 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         // omega = <t, s> / <t, t> (or stop: converged on |s|, t = 0, NaN);
         // then, with r' = s - omega t still to be formed,
         // rho' = <rh, r'> = <rh, s> - omega <rh, t> and beta = (rho'/rho)(alpha/omega)
-        const double ss = sA[r];
-        const double st_re = sB[r], st_im = sB[nr + r], tt = sB[2 * nr + r];
-        const double2 hs = make_double2(sB[3 * nr + r], sB[4 * nr + r]);
-        const double2 ht = make_double2(sB[5 * nr + r], sB[6 * nr + r]);
+        const double ss = sA[7 * nr + r];
+        const double st_re = sA[r], st_im = sA[nr + r], tt = sA[2 * nr + r];
+        const double2 hs = make_double2(sA[3 * nr + r], sA[4 * nr + r]);
+        const double2 ht = make_double2(sA[5 * nr + r], sA[6 * nr + r]);
         sc.ss = ss;
         sc.brk = 0;
         sc.beta = zero;
@@ -591,6 +687,100 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int 
         sc.alpha = zero;
         sc.omega = zero;
         sc.frozen = 1;  // end of the iteration with flag != 0
+        break;
+    }
+    case F_CG1: {
+        // CG on the normal equations with one reduction phase per iteration
+        // (Chronopoulos and Gear's form): gamma = |z|^2 with z = D^dag r,
+        // delta = |D z|^2; beta = gamma / gamma_prev and
+        // alpha = gamma / (delta - beta gamma / alpha_prev), where the
+        // denominator equals |D p|^2 for p = z + beta p_prev
+        const double rr = p.nvalC > 0 ? sC[r] : sc.rr, gam = sA[r], del = sB[r];
+        if (sc.flag == 0) {
+            sc.rr = rr;
+            if (!finite2(rr) || !finite2(gam) || !finite2(del))
+                sc.flag = 3;
+            else if (rr <= sc.tol2 * sc.bb) {
+                sc.flag = 1;
+                sc.conv_iter = p.iter;
+            } else {
+                const double beta = p.iter > 0 && sc.zz > 0.0 ? gam / sc.zz : 0.0;
+                const double den = beta != 0.0 ? del - beta * gam / sc.alpha.x : del;
+                if (gam > 0.0 && den > 0.0 && finite2(den)) {
+                    sc.alpha = make_double2(gam / den, 0.0);
+                    sc.beta = make_double2(beta, 0.0);
+                    sc.zz = gam;
+                    break;
+                }
+                sc.flag = 2;
+            }
+        }
+        sc.alpha = sc.beta = zero;
+        sc.frozen = 1;  // the update pass of this iteration is skipped
+        break;
+    }
+    case F_SR: {
+        // BiCGStab with one reduction phase per iteration.  With u = D r,
+        // v = D p and q = D v known, s = r - alpha v and t = D s = u - alpha q
+        // never need to be formed before the scalars:
+        //   <t, s> = <u, r> - alpha <u, v> - conj(alpha) <q, r> + |alpha|^2 <q, v>
+        //   <t, t> = |u|^2 - 2 Re(alpha <u, q>) + |alpha|^2 |q|^2
+        //   rho'   = <rh, s> - omega <rh, t>
+        //          = rho - alpha <rh, v> - omega (<rh, u> - alpha <rh, q>)
+        const double rr = p.nvalC > 0 ? sC[r] : sc.rr;
+        const double2 hv = make_double2(sA[r], sA[nr + r]), hu = make_double2(sA[2 * nr + r], sA[3 * nr + r]);
+        const double2 ur = make_double2(sA[4 * nr + r], sA[5 * nr + r]), uv = make_double2(sA[6 * nr + r], sA[7 * nr + r]);
+        const double uu = sA[8 * nr + r];
+        const double2 vq = make_double2(sB[r], sB[nr + r]);
+        const double qq = sB[2 * nr + r];
+        const double2 hq = make_double2(sB[3 * nr + r], sB[4 * nr + r]), rq = make_double2(sB[5 * nr + r], sB[6 * nr + r]);
+        const double2 uq = make_double2(sB[7 * nr + r], sB[8 * nr + r]);
+        if (sc.flag == 0) {
+            sc.rr = rr;
+            const double d = hv.x * hv.x + hv.y * hv.y;
+            if (!finite2(rr) || !finite2(d) || !finite2(uu) || !finite2(qq) || sc.brk == 2)
+                sc.flag = 3;
+            else if (rr <= sc.tol2 * sc.bb) {
+                sc.flag = 1;
+                sc.conv_iter = p.iter;
+            } else if (sc.brk == 1 || !(d > 0.0))
+                sc.flag = 2;
+            if (sc.flag == 0) {
+                const double2 a = cdiv(sc.rho, hv);
+                const double a2 = a.x * a.x + a.y * a.y;
+                // <t, s>
+                const double2 auv = cmul(a, uv);
+                const double2 aqr = cmul(make_double2(a.x, -a.y), make_double2(rq.x, -rq.y));
+                const double2 ts = make_double2(ur.x - auv.x - aqr.x + a2 * vq.x, ur.y - auv.y - aqr.y - a2 * vq.y);
+                const double tt = uu - 2.0 * cmul(a, uq).x + a2 * qq;
+                sc.brk = 0;
+                if (!finite2(ts.x) || !finite2(ts.y) || !finite2(tt)) {
+                    sc.flag = 3;
+                } else if (!(tt > 0.0)) {
+                    sc.flag = 2;
+                } else {
+                    const double2 om = make_double2(ts.x / tt, ts.y / tt);
+                    const double2 ahq = cmul(a, hq);
+                    const double2 w1 = cmul(om, make_double2(hu.x - ahq.x, hu.y - ahq.y));
+                    const double2 ahv = cmul(a, hv);
+                    const double2 rho_new = make_double2(sc.rho.x - ahv.x - w1.x, sc.rho.y - ahv.y - w1.y);
+                    sc.alpha = a;
+                    sc.omega = om;
+                    sc.beta = zero;
+                    if (!finite2(rho_new.x) || !finite2(rho_new.y))
+                        sc.brk = 2;
+                    else if ((om.x != 0.0 || om.y != 0.0) && (rho_new.x != 0.0 || rho_new.y != 0.0))
+                        sc.beta = cmul(cdiv(rho_new, sc.rho), cdiv(a, om));
+                    else
+                        sc.brk = 1;  // this step is taken; the next check reports the breakdown
+                    sc.rho_prev = sc.rho;
+                    sc.rho = rho_new;
+                    break;
+                }
+            }
+        }
+        sc.alpha = sc.beta = sc.omega = zero;
+        sc.frozen = 1;
         break;
     }
     case F_BI_RELIABLE: {

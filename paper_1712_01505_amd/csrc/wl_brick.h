@@ -204,10 +204,7 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
             const uint32_t sb = sx + g.nxyz * (uint32_t)tb;
             RawHop<P> rb;
             raw_load<P>(p, sb, sb, 3, rhs, rb);
-            cx<R_> ps[12], u[9], h[6];
-            decode<P>(rb, ps, u);
-            project<3, -SF>(ps, h, one);
-            su3_adj_mv(u, h, Cg);
+            hop_g<P, 3, -SF, 1>(rb, Cg, one);
             Cs = (t0 == 0 && anti_t) ? R_(-1) : R_(1);
             if constexpr (Traits<P>::SCALED)
                 Cs *= rb.sc;
@@ -280,30 +277,27 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
                 default: compute_hop<P, DAG, 5>(r, sg[5], acc, one); break;
                 }
             }
-            // the site's own spinor (the stored values, scaled)
+            // the site's own spinor (the stored values, scaled), with U_t(x)
+            RawHop<P> rs;
+            lds_spinor<P>(smem, g.NSP, tid, rs);
+            for (int q = 0; q < (P == F64 ? 6 : 3); ++q)
+                rs.lk[q] = rf.lk[q];
             cx<R_> self[12];
             {
-                RawHop<P> r;
-                lds_spinor<P>(smem, g.NSP, tid, r);
                 cx<R_> u_unused[9];
-                for (int q = 0; q < (P == F64 ? 6 : 3); ++q)
-                    r.lk[q] = rf.lk[q];
-                decode<P>(r, self, u_unused);
+                decode<P>(rs, self, u_unused);
                 if constexpr (Traits<P>::SCALED)
-                    scale_site<P>(self, r.sc);
+                    scale_site<P>(self, rs.sc);
             }
             // forward t hop: U_t(x) (1 + SF g_t) psi(x + t)
-            cx<R_> u[9];
             {
                 RawHop<P> r;
                 for (int q = 0; q < NCH; ++q)
                     r.sp[q] = nxt.sp[q];
                 for (int q = 0; q < (P == F64 ? 6 : 3); ++q)
                     r.lk[q] = rf.lk[q];
-                cx<R_> ps[12], h[6], gg[6];
-                decode<P>(r, ps, u);
-                project<3, SF>(ps, h, one);
-                su3_mv(u, h, gg);
+                cx<R_> gg[6];
+                hop_g<P, 3, SF, 0>(r, gg, one);
                 R_ gf = (wf && anti_t) ? R_(-1) : R_(1);
                 if constexpr (Traits<P>::SCALED)
                     gf *= nxt.sc;
@@ -312,12 +306,11 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
             // the -t hop last, as in every variant
             accum<3, -SF>(acc, Cg, Cs);
             // backward-t contribution of the next site: U_t(x)^dag (1 - SF g_t) psi(x)
-            {
-                cx<R_> h[6];
-                project<3, -SF>(self, h, one);
-                su3_adj_mv(u, h, Cg);
+            hop_g<P, 3, -SF, 1>(rs, Cg, one);
+            if constexpr (Traits<P>::SCALED)
+                Cs = rs.sc;
+            else
                 Cs = R_(1);
-            }
             cx<R_> o[12];
             if constexpr (APPLY) {
 #pragma unroll
@@ -354,6 +347,13 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
                 cx<R_> v[12];
                 load_site<P>(p.aux, p.V, p.nrhs, s, rhs, v);
                 bicg_values(self, o, v, red);
+            }
+            if constexpr (RED == RED_SR) {
+                cx<R_> a[12], b[12], c[12];
+                load_site<P>(p.aux, p.V, p.nrhs, s, rhs, a);
+                load_site<P>(p.aux2, p.V, p.nrhs, s, rhs, b);
+                load_site<P>(p.aux3, p.V, p.nrhs, s, rhs, c);
+                sr_values(self, o, a, b, c, red);
             }
             cur = nxt;
         }
@@ -445,7 +445,10 @@ inline hipError_t launch_brick(const LaunchCfg &cfg, StencilParams p, hipStream_
     if ((uint64_t)p.ntile * p.ng > 0x7fffffffull)
         return hipErrorInvalidValue;
     const dim3 grid(p.ntile * p.ng), block(cfg.block);
-    const size_t smem = brick_lds_bytes(P, g.NSP);
+    const size_t need = brick_lds_bytes(P, g.NSP), cap = brick_reserve(cfg.wpe);
+    if (cap && need > cap)
+        return hipErrorInvalidValue;
+    const size_t smem = cap ? cap : need;  // a cap reserves more LDS than the slices need
     if (!p.apply) {
         if (p.red != RED_NONE)
             return hipErrorInvalidValue;
@@ -459,6 +462,7 @@ inline hipError_t launch_brick(const LaunchCfg &cfg, StencilParams p, hipStream_
     case RED_DOTV: return brick_go<P, DAG, RED_DOTV, 1>(grid, block, smem, p, g, st);
     case RED_DOTIN_NORM: return brick_go<P, DAG, RED_DOTIN_NORM, 1>(grid, block, smem, p, g, st);
     case RED_BICG: return brick_go<P, DAG, RED_BICG, 1>(grid, block, smem, p, g, st);
+    case RED_SR: return brick_go<P, DAG, RED_SR, 1>(grid, block, smem, p, g, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -416,8 +416,8 @@ __device__ __forceinline__ uint32_t slab_site(uint32_t b, uint32_t tid, uint32_t
 }
 
 // ---------------------------------------------------------------- reductions
-// RED_BICG values of one site, added to r[0..6]: <in, out> (re, im), |out|^2,
-// <v, in> (re, im), <v, out> (re, im); <a, b> = sum conj(a) b, in FP64.
+// RED_BICG values of one site, added to r[0..7]: <in, out> (re, im), |out|^2,
+// <v, in> (re, im), <v, out> (re, im), |in|^2; <a, b> = sum conj(a) b, in FP64.
 template <typename T>
 __device__ __forceinline__ void bicg_values(const cx<T> (&in)[12], const cx<T> (&out)[12], const cx<T> (&v)[12],
                                             double *r)
@@ -432,6 +432,26 @@ __device__ __forceinline__ void bicg_values(const cx<T> (&in)[12], const cx<T> (
         r[4] = fma(vr, ii, fma(-vi, ir, r[4]));
         r[5] = fma(vr, orr, fma(vi, oi, r[5]));
         r[6] = fma(vr, oi, fma(-vi, orr, r[6]));
+        r[7] = fma(ir, ir, fma(ii, ii, r[7]));
+    }
+}
+// RED_SR: <in, out>, |out|^2, <a, out>, <b, out>, <c, out> (9 values, accumulated)
+template <typename T>
+__device__ __forceinline__ void sr_values(const cx<T> (&in)[12], const cx<T> (&out)[12], const cx<T> (&a)[12],
+                                          const cx<T> (&b)[12], const cx<T> (&c)[12], double *r)
+{
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const double orr = out[k].re, oi = out[k].im;
+        r[0] = fma((double)in[k].re, orr, fma((double)in[k].im, oi, r[0]));
+        r[1] = fma((double)in[k].re, oi, fma(-(double)in[k].im, orr, r[1]));
+        r[2] = fma(orr, orr, fma(oi, oi, r[2]));
+        r[3] = fma((double)a[k].re, orr, fma((double)a[k].im, oi, r[3]));
+        r[4] = fma((double)a[k].re, oi, fma(-(double)a[k].im, orr, r[4]));
+        r[5] = fma((double)b[k].re, orr, fma((double)b[k].im, oi, r[5]));
+        r[6] = fma((double)b[k].re, oi, fma(-(double)b[k].im, orr, r[6]));
+        r[7] = fma((double)c[k].re, orr, fma((double)c[k].im, oi, r[7]));
+        r[8] = fma((double)c[k].re, oi, fma(-(double)c[k].im, orr, r[8]));
     }
 }
 __device__ __forceinline__ double wave_sum(double v)

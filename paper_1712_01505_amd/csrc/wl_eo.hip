@@ -130,7 +130,8 @@ __device__ __forceinline__ void eo_hop_dir(const EoParams &p, const int (&c)[4],
 
 // out(parity) = c_self * self + c_hop * H_{parity, other} in, with optional
 // fused reductions over out: |out|^2 (RED_NORM), <v, out> (RED_DOTV, v =
-// dotv) or <self, out> and |out|^2 (RED_DOTIN_NORM).
+// dotv) or <self, out> and |out|^2 (RED_DOTIN_NORM); with self the Schur
+// input, the BiCGStab sets RED_BICG and RED_SR.
 template <int P, int DAG, int RED>
 __global__ __launch_bounds__(256) void eo_hop_kernel(EoParams p)
 {
@@ -206,6 +207,13 @@ __global__ __launch_bounds__(256) void eo_hop_kernel(EoParams p)
             load_site<P>(p.dotv, p.Vh, p.nrhs, i, rhs, v);
             bicg_values(sf, o, v, red);
         }
+        if constexpr (RED == RED_SR) {  // self = the Schur input v; dotv, dotv2, dotv3 = rh, r, u
+            cx<T> a[12], b[12], c[12];
+            load_site<P>(p.dotv, p.Vh, p.nrhs, i, rhs, a);
+            load_site<P>(p.dotv2, p.Vh, p.nrhs, i, rhs, b);
+            load_site<P>(p.dotv3, p.Vh, p.nrhs, i, rhs, c);
+            sr_values(sf, o, a, b, c, red);
+        }
     }
     if constexpr (NV > 0) {
         block_sum<NV>(red, lds);
@@ -250,6 +258,7 @@ hipError_t launch_eo_hop(int prec, int dagger, int red, EoParams p, hipStream_t 
     case RED_DOTV: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_DOTV>), g, b, 0, st, p); break;              \
     case RED_DOTIN_NORM: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_DOTIN_NORM>), g, b, 0, st, p); break;  \
     case RED_BICG: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_BICG>), g, b, 0, st, p); break;              \
+    case RED_SR: hipLaunchKernelGGL((eo_hop_kernel<PP, DD, RED_SR>), g, b, 0, st, p); break;                  \
     default: return hipErrorInvalidValue;                                                                      \
     }
     switch (prec * 2 + (dagger ? 1 : 0)) {

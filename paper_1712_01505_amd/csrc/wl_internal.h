@@ -25,6 +25,9 @@ struct LaunchCfg {
     int lanes = 1;    // right-hand sides interleaved across the lanes of a wavefront (1, 2, 4, 8; rpt = 1)
     // variant 7 (LDS-staged brick walk): brick extents in x, y, z (bx by bz = block) and t-slices per unit
     int bx = 0, by = 0, bz = 0, tsteps = 0;
+    // variant 7: cap of workgroups per CU (0 = none): each workgroup reserves
+    // 1/wpe of the CU's LDS, which bounds the waves per SIMD
+    int wpe = 0;
 };
 
 }  // namespace wl
@@ -52,13 +55,17 @@ enum Red {
     RED_NORM = 1,      // |out|^2                           (1 value)
     RED_DOTV = 2,      // <v, out> with v = aux              (2 values: re, im)
     RED_DOTIN_NORM = 3,// <in, out> and |out|^2              (3 values)
-    RED_BICG = 4       // <in, out>, |out|^2, <v, in>, <v, out> with v = aux (7 values;
-                       // BiCGStab's second product: omega and the next rho together)
+    RED_BICG = 4,      // <in, out>, |out|^2, <v, in>, <v, out>, |in|^2 with v = aux (8 values;
+                       // BiCGStab's second product: omega, the next rho and |s|^2 together)
+    RED_SR = 5         // <in, out>, |out|^2, <aux, out>, <aux2, out>, <aux3, out> (9 values;
+                       // the single-reduction BiCGStab's q = D v with aux = rh, aux2 = r, aux3 = u)
 };
-constexpr int RED_NVAL_MAX = 7;  // values per right-hand side of the largest reduction
+constexpr int RED_NVAL_MAX = 9;  // values per right-hand side of the largest reduction
+constexpr int RED_LAST = RED_SR;
 __host__ __device__ constexpr int red_nval(int red)
 {
-    return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : red == RED_BICG ? 7 : 0;
+    return red == RED_NORM ? 1 : red == RED_DOTV ? 2 : red == RED_DOTIN_NORM ? 3 : red == RED_BICG ? 8
+           : red == RED_SR ? 9 : 0;
 }
 
 struct StencilParams {
@@ -66,6 +73,7 @@ struct StencilParams {
     const void *in;
     void *out;
     const void *aux;   // RED_DOTV: the v of <v, out>
+    const void *aux2, *aux3;  // RED_SR: the second and third vectors dotted with out
     double *partials;  // per-block partial sums
     FastDiv fx, fy, fz;
     int L[4];
@@ -102,6 +110,7 @@ struct EoParams {
     const void *in;      // half field of the other parity
     const void *self;    // half field of the output parity (c_self term, <self, out>), or null
     const void *dotv;    // RED_DOTV: the v of <v, out>
+    const void *dotv2, *dotv3;  // RED_SR: the second and third vectors dotted with out
     void *out;           // half field of the output parity
     double *partials;
     const struct Scalars *skip;
@@ -139,7 +148,10 @@ bool var_ok(int prec, int var);  // variant exists for this precision
 int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V, int nrhs);  // partials per RHS of one launch
 bool slab_ok(const int *L, int block, int mode);  // slab order `mode` usable for these extents and block size
 // variant 7: the brick (bx, by, bz) and walk length T tile extents L and fit the kernel's LDS and halo limits
-bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T);
+bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T, int wpe = 0);
+constexpr size_t LDS_PER_CU = 160 * 1024;
+// dynamic LDS a brick launch reserves for its occupancy cap (0: none)
+inline size_t brick_reserve(int wpe) { return wpe > 0 ? (LDS_PER_CU / (size_t)wpe - 512) / 256 * 256 : 0; }
 constexpr int VAR_BRICK = 7;
 
 struct MultiEntry {
@@ -200,13 +212,22 @@ enum BlasOp {
     B_NORM = 8,       // |x|^2
     B_DOT_NORM = 9,   // <a0, a1> and |a1|^2  (3 values)
     B_CG_RESTART = 10,// p = z for columns whose restart flag is set
-    B_BI_XRP = 11     // x += alpha p + omega s ; r = s - omega t ; p = r + beta (p - omega v) ; |r|^2
+    B_BI_XRP = 11,    // x += alpha p + omega s ; r = s - omega t ; p = r + beta (p - omega v) ; |r|^2
                       // (y0 = x, y1 = r, y2 = p, a1 = s, a2 = t, a3 = v)
+    // single-reduction forms (one finalize per iteration)
+    B_CG1 = 12,       // CGNR: p = z + beta p ; w = q + beta w ; x += alpha p ; r -= alpha w ; |r|^2
+                      // (y0 = x, y1 = r, y2 = p, y3 = w, a0 = z, a1 = q)
+    B_SR_PV = 13,     // BiCGStab: p = r + beta (p - omega v) ; v = u + beta (v - omega q) ;
+                      // <rh, v>, <rh, u>, <u, r>, <u, v>, |u|^2  (9 values;
+                      // y0 = p, y1 = v, a0 = r, a1 = u, a2 = q, a3 = rh)
+    B_SR_XR = 14      // BiCGStab: s = r - alpha v ; x += alpha p + omega s ; r = s - omega (u - alpha q) ;
+                      // |r|^2  (y0 = x, y1 = r, a0 = p, a1 = v, a2 = u, a3 = q)
 };
 struct BlasParams {
     void *y0;          // first output / in-out vector
     void *y1;          // second output / in-out vector
-    void *y2;          // third in-out vector (B_BI_XRP: p)
+    void *y2;          // third in-out vector (B_BI_XRP, B_CG1: p)
+    void *y3;          // fourth in-out vector (B_CG1: w)
     const void *a0, *a1, *a2, *a3;  // inputs
     const Scalars *sc;
     double *partials;
@@ -216,7 +237,7 @@ struct BlasParams {
     int skip_frozen;   // in a solver loop: skip frozen columns
 };
 hipError_t launch_blas(int prec, int op, const BlasParams &p, int block, hipStream_t st);
-int blas_partials(uint32_t V, int nrhs, int block);  // workgroups (= partial sums per RHS) of one launch
+int blas_partials(uint32_t V, int op, int block);  // workgroups (= partial sums per RHS) of one launch
 int blas_nval(int op);
 
 // x64 += s[rhs] * e (e in precision pin); s read from device with stride.
@@ -233,9 +254,13 @@ enum FinOp {
     F_BI_RELIABLE = 8, // after a reliable update replaced r: A = (<rh, r>, |r|^2) -> rr,
                        // convergence, rho and beta = (rho'/rho_prev)(alpha/omega)
     F_CG_RELIABLE = 9, // CGNR after a reliable update replaced r and z = D^dag r: A = |r|^2, B = |z|^2
-    F_BI_OMEGA_RHO = 10, // merged BiCGStab: A = |s|^2, B = RED_BICG of t = D s with v = rh:
+    F_BI_OMEGA_RHO = 10, // merged BiCGStab: A = RED_BICG of t = D s with v = rh (|s|^2 its last value):
                          // omega, then rho' = <rh, s> - omega <rh, t> and beta before r is formed
-    F_BI_CONV = 11       // merged BiCGStab, end of an iteration: A = |r|^2 -> convergence / stop
+    F_BI_CONV = 11,      // merged BiCGStab, end of an iteration: A = |r|^2 -> convergence / stop
+    // single-reduction forms: the iteration's only finalize.  C = |r|^2 of
+    // the previous update (absent in the first iteration: the value from the init)
+    F_CG1 = 12,          // CGNR: A = |z|^2 (z = D^dag r), B = |q|^2 (q = D z)
+    F_SR = 13            // BiCGStab: A = B_SR_PV's 9 values, B = RED_SR's 9 values
 };
 struct FinParams {
     const double *A;

@@ -26,7 +26,7 @@ namespace wl {
 
 hipError_t prof_stencil(int prec, const wl_op *op, int dagger, const LaunchCfg &cfg, StencilParams p,
                         hipStream_t st);  // wl_api.cpp
-LaunchCfg launch_for(const wl_op *op, int nrhs, int red);  // wl_api.cpp
+LaunchCfg launch_for(const wl_op *op, int nrhs, int red, int dagger);  // wl_api.cpp
 void set_last_hip_error(hipError_t e);           // wl_api.cpp
 
 namespace {
@@ -65,7 +65,7 @@ struct Arena {
 // Bytes of one Krylov engine for op precision `prec`.
 size_t engine_bytes(int solver, int prec, uint32_t V, int Lt, int nrhs)
 {
-    const int nvec = solver == WL_SOLVER_CGNR ? 4 : 6;
+    const int nvec = solver == WL_SOLVER_CGNR ? 5 : 6;
     return nvec * align_up(vec_bytes(prec, V, nrhs)) + 3 * partial_bytes(V, Lt, nrhs) +
            align_up(sizeof(Scalars) * nrhs) + align_up(sizeof(double) * 3 * nrhs);
 }
@@ -161,6 +161,8 @@ struct Engine {
     int lookahead = 2;
     int adj = 0;  // solving with D^dag: every stencil's dagger flag is flipped
     int stencil_calls = 0;
+    int kernels = 0, finalizes = 0;  // launches issued (kernels includes the finalizes)
+    int form = 0;   // 1: one reduction phase per iteration (single-reduction CGNR / BiCGStab)
     int group = 1;  // columns per linear system (domain wall: the fifth-dimension extent)
     bool eo = false;       // even-odd: vectors are even half fields, the operator is the Schur complement
     void *eo_tmp = nullptr;  // odd half field for H_oe in
@@ -188,7 +190,7 @@ struct Engine {
         st = s;
         hb = h;
         sc_host = h->sc;
-        const int nvec = solver == WL_SOLVER_CGNR ? 4 : 6;
+        const int nvec = solver == WL_SOLVER_CGNR ? 5 : 6;
         for (int i = 0; i < nvec; ++i)
             if (!(v[i] = a.take(vec_bytes(prec, V, nrhs))))
                 return WL_EWORKSPACE;
@@ -202,7 +204,8 @@ struct Engine {
         return WL_OK;
     }
 
-    int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot, bool loop = false)
+    int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot, bool loop = false,
+                const void *aux2 = nullptr, const void *aux3 = nullptr)
     {
         if (eo) {  // out = (1 - kappa^2 H_eo H_oe) in on even half fields
             EoParams a = eo_params(op, 1, nrhs);
@@ -215,6 +218,8 @@ struct Engine {
             b.in = eo_tmp;
             b.self = in;
             b.dotv = aux;
+            b.dotv2 = aux2;
+            b.dotv3 = aux3;
             b.out = out;
             b.c_self = 1.0;
             b.c_hop = -op->kappa * op->kappa;
@@ -225,6 +230,7 @@ struct Engine {
                 nval[slot] = stencil_nval(red);
             }
             ++stencil_calls;
+            kernels += 2;
             WL_TRY(launch_eo_hop(prec, dagger ^ adj, red, b, st));
             return WL_OK;
         }
@@ -234,6 +240,8 @@ struct Engine {
         p.in = in;
         p.out = out;
         p.aux = aux;
+        p.aux2 = aux2;
+        p.aux3 = aux3;
         p.partials = slot >= 0 ? part[slot] : nullptr;
         for (int i = 0; i < 4; ++i) {
             p.L[i] = op->g.dims[i];
@@ -248,24 +256,26 @@ struct Engine {
         p.apply = 1;
         p.red = red;
         op_apply_params(op, p);
-        LaunchCfg cfg = launch_for(op, nrhs, red);
+        LaunchCfg cfg = launch_for(op, nrhs, red, dagger ^ adj);
         if (slot >= 0) {
             nblk[slot] = stencil_partials(cfg, p.L, V, nrhs);
             nval[slot] = stencil_nval(red);
         }
         ++stencil_calls;
+        ++kernels;
         WL_TRY(prof_stencil(prec, op, dagger ^ adj, cfg, p, st));
         return WL_OK;
     }
 
     int blas(int bop, void *y0, void *y1, const void *a0, const void *a1, const void *a2, const void *a3, int slot,
-             bool loop = false, void *y2 = nullptr)
+             bool loop = false, void *y2 = nullptr, void *y3 = nullptr)
     {
         BlasParams p{};
         p.skip_frozen = loop ? 1 : 0;
         p.y0 = y0;
         p.y1 = y1;
         p.y2 = y2;
+        p.y3 = y3;
         p.a0 = a0;
         p.a1 = a1;
         p.a2 = a2;
@@ -275,9 +285,10 @@ struct Engine {
         p.V = V;
         p.nrhs = nrhs;
         if (slot >= 0) {
-            nblk[slot] = blas_partials(V, nrhs, BLAS_BLOCK);
+            nblk[slot] = blas_partials(V, bop, BLAS_BLOCK);
             nval[slot] = blas_nval(bop);
         }
+        ++kernels;
         WL_TRY(launch_blas(prec, bop, p, BLAS_BLOCK, st));
         return WL_OK;
     }
@@ -314,6 +325,8 @@ struct Engine {
         p.tol2 = tol2;
         p.tol2v = tol2v;
         p.group = group;
+        ++kernels;
+        ++finalizes;
         WL_TRY(launch_finalize(fop, p, st));
         return WL_OK;
     }
@@ -384,7 +397,66 @@ struct Engine {
         if ((rc = blas(B_NORM, nullptr, nullptr, b, nullptr, nullptr, nullptr, 2)))
             return rc;
         int it = 0;
-        if (solver == WL_SOLVER_CGNR) {
+        if (solver == WL_SOLVER_CGNR && form == 1) {
+            // one reduction phase per iteration: z = D^dag r (|z|^2), q = D z
+            // (|q|^2), one finalize, then one pass updates p, w = D p, x and r
+            // (|r|^2, checked by the next iteration's finalize)
+            void *z = v[1], *p = v[2], *w = v[3], *q = v[4];
+            if ((rc = blas(B_ZERO, p, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = blas(B_ZERO, w, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            if ((rc = fin(F_INIT_CG, 0, -1, 2, 0, tol2)))
+                return rc;
+            WL_TRY(hipStreamSynchronize(st));
+            bool stop = host_all_done();
+            while (!stop && it < maxiter) {
+                if ((rc = stencil(z, r, 1, RED_NORM, nullptr, 0, true)))
+                    return rc;
+                if ((rc = stencil(q, z, 0, RED_NORM, nullptr, 1, true)))
+                    return rc;
+                if ((rc = fin(F_CG1, 0, 1, it > 0 ? 2 : -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_CG1, x, r, z, q, nullptr, nullptr, 2, true, p, w)))
+                    return rc;
+                if ((rc = mark(it, &stop)))
+                    return rc;
+                ++it;
+            }
+        } else if (solver == WL_SOLVER_BICGSTAB && form == 1) {
+            // one reduction phase per iteration: u = D r; p and v = D p from
+            // their recurrences (with <rh, v>, <rh, u>, <u, r>, <u, v>, |u|^2);
+            // q = D v (with <v, q>, |q|^2, <rh, q>, <r, q>, <u, q>); one
+            // finalize forms alpha, omega, rho' and beta; one pass updates x
+            // and r (|r|^2, checked by the next iteration's finalize)
+            if (op->ns > 0)
+                return WL_EINVAL;
+            void *rh = v[1], *p = v[2], *vv = v[3], *u = v[4], *q = v[5];
+            if ((rc = blas(B_COPY, rh, nullptr, r, nullptr, nullptr, nullptr, -1)))
+                return rc;
+            for (void *z0 : {p, vv, q})
+                if ((rc = blas(B_ZERO, z0, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
+                    return rc;
+            if ((rc = fin(F_INIT_BI, 0, -1, 2, 0, tol2)))
+                return rc;
+            WL_TRY(hipStreamSynchronize(st));
+            bool stop = host_all_done();
+            while (!stop && it < maxiter) {
+                if ((rc = stencil(u, r, 0, RED_NONE, nullptr, -1, true)))
+                    return rc;
+                if ((rc = blas(B_SR_PV, p, vv, r, u, q, rh, 0, true)))
+                    return rc;
+                if ((rc = stencil(q, vv, 0, RED_SR, rh, 1, true, r, u)))
+                    return rc;
+                if ((rc = fin(F_SR, 0, 1, it > 0 ? 2 : -1, it, tol2)))
+                    return rc;
+                if ((rc = blas(B_SR_XR, x, r, p, vv, u, q, 2, true)))
+                    return rc;
+                if ((rc = mark(it, &stop)))
+                    return rc;
+                ++it;
+            }
+        } else if (solver == WL_SOLVER_CGNR) {
             void *z = v[1], *p = v[2], *w = v[3];
             if ((rc = stencil(z, r, 1, RED_NORM, nullptr, 1)))
                 return rc;
@@ -443,11 +515,11 @@ struct Engine {
                     return rc;
                 if ((rc = fin(F_BI_ALPHA, 0, -1, -1, it, tol2)))
                     return rc;
-                if ((rc = blas(B_BI_S, s, nullptr, r, vv, nullptr, nullptr, 0, true)))
+                if ((rc = blas(B_BI_S, s, nullptr, r, vv, nullptr, nullptr, -1, true)))
                     return rc;
-                if ((rc = stencil(t, s, 0, RED_BICG, rh, 1, true)))
+                if ((rc = stencil(t, s, 0, RED_BICG, rh, 1, true)))  // with |s|^2
                     return rc;
-                if ((rc = fin(F_BI_OMEGA_RHO, 0, 1, -1, it, tol2)))
+                if ((rc = fin(F_BI_OMEGA_RHO, 1, -1, -1, it, tol2)))
                     return rc;
                 // the host has the status through iteration it - 1 at most, so
                 // the check runs as it would have after that iteration
@@ -543,6 +615,7 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
         E.tol2v = lease.b->dev(t2h);
     }
     E.adj = prm->dagger;
+    E.form = prm->form;
     E.lookahead = lookahead_of(prm);
     double *bb = lease.b->d, *rr = lease.b->d + nrhs;
     if ((rc = E.norm2(b, bb)))
@@ -584,6 +657,8 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
         s.iters = iters[r];
         s.outer = 0;
         s.stencil_calls = E.stencil_calls;
+        s.kernels = E.kernels;
+        s.finalizes = E.finalizes;
         s.true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
         s.iter_rel_res = itres[r];
         s.converged = s.true_rel_res <= tol[r];
@@ -626,6 +701,8 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     if ((rc = L.init(arena, lo, solver, nrhs, st, lease.b, eo)))
         return rc;
     H.adj = L.adj = prm->dagger;
+    L.form = prm->form;
+    int direct = 0;  // accumulate / convert launches issued here
     void *r_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
     void *e_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
     if (!r_lo || !e_lo)
@@ -692,6 +769,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
             int e;
             // x64 += sigma e ; e = 0 ; r64 = b - D64 x ; r_lo = r64 / sigma
             WL_TRY(launch_accum(lo->prec, H.V, nrhs, x, e_lo, sig_dev, 1, st));
+            direct += 2;  // with the conversion below
             if ((e = L.blas(B_ZERO, e_lo, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return e;
             if ((e = H.stencil(H.v[1], x, 0, RED_NONE, nullptr, -1)))
@@ -759,6 +837,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
             break;
         // r_lo = r64 / sigma (0 for converged columns)
         WL_TRY(launch_convert(WL_F64, lo->prec, H.V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
+        ++direct;
         int done = 0;
         next_read = 0;
         last_update = 0;
@@ -779,6 +858,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         total += done;
         // x64 += sigma e
         WL_TRY(launch_accum(lo->prec, H.V, nrhs, x, e_lo, sig_dev, 1, st));
+        ++direct;
         ++outer;
     }
     int worst = WL_OK;
@@ -787,6 +867,8 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         s.iters = iters[r];
         s.outer = outer + updates;
         s.stencil_calls = H.stencil_calls + L.stencil_calls;
+        s.kernels = H.kernels + L.kernels + direct;
+        s.finalizes = H.finalizes + L.finalizes;
         s.true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
         s.iter_rel_res = s.true_rel_res;
         s.converged = s.true_rel_res <= tolv[r];
@@ -901,6 +983,8 @@ int solve_eo(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *
         if (!std::isfinite(rr[r]))
             return WL_ENAN;
         wl_solve_stats s = es[r];
+        s.kernels += F.kernels + Hh.kernels + 4 + (prm->use_x0 ? 1 : 0);  // the splits, two hops, the merge
+        s.finalizes += F.finalizes + Hh.finalizes;
         s.true_rel_res = nb[r] > 0 ? std::sqrt(rr[r] / nb[r]) : 0.0;
         s.iter_rel_res = nb[r] > 0 ? es[r].iter_rel_res * std::sqrt(nh[r] / nb[r]) : 0.0;
         s.converged = s.true_rel_res <= prm->tol;

@@ -30,10 +30,12 @@ namespace wl {
 int max_var(int prec) { return VAR_BRICK; }
 bool var_ok(int prec, int var) { return var <= 1 || var >= 4 || (var == 2 && prec != F64) || (var == 3 && prec >= BF16S); }
 
-bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T)
+bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T, int wpe)
 {
     BrickGeom g{};
-    return brick_setup(L, prec, bx, by, bz, T, g);
+    if (!brick_setup(L, prec, bx, by, bz, T, g))
+        return false;
+    return wpe == 0 || ((wpe == 1 || wpe == 2 || wpe == 4 || wpe == 8) && brick_lds_bytes(prec, g.NSP) <= brick_reserve(wpe));
 }
 
 bool slab_ok(const int *L, int block, int mode)

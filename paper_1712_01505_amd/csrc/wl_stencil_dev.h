@@ -6,9 +6,37 @@
 #pragma once
 
 #include "wl_hop.h"
+#include "wl_hop16.h"
 #include "wl_internal.h"
 
 namespace wl {
+
+// FP16 storage: a link's two stored rows as packed f16 complex with the
+// third row rebuilt, and a site's stored spinor (unscaled) with its scale.
+__device__ __forceinline__ void raw_link16(const StencilParams &p, int mu, uint32_t s, hf2 (&u)[9])
+{
+    const uint2 *b = reinterpret_cast<const uint2 *>(p.U) + (size_t)mu * 3 * p.V + s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint2 d = b[(size_t)k * p.V];
+        u[2 * k] = as_hf2(d.x);
+        u[2 * k + 1] = as_hf2(d.y);
+    }
+    rebuild_row16(u);
+}
+__device__ __forceinline__ void raw_spinor16(const StencilParams &p, uint32_t s, int rhs, hf2 (&ps)[12], float &sc)
+{
+    const uint4 *b = reinterpret_cast<const uint4 *>(p.in) + (size_t)rhs * 3 * p.V + s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint4 d = b[(size_t)k * p.V];
+        ps[4 * k] = as_hf2(d.x);
+        ps[4 * k + 1] = as_hf2(d.y);
+        ps[4 * k + 2] = as_hf2(d.z);
+        ps[4 * k + 3] = as_hf2(d.w);
+    }
+    sc = scale_ptr<F16S>(p.in, p.V, p.nrhs)[(size_t)rhs * p.V + s];
+}
 
 // Both hops in direction MU for R right-hand sides.
 template <int P, int DAG, int R, int MU>
@@ -27,6 +55,36 @@ __device__ __forceinline__ void hop_dir(const StencilParams &p, uint32_t s, int 
     const bool cut = MU == 3 && p.halo_t;
     const T gf = (wf && cut) ? T(0) : (wf && anti) ? T(-1) : T(1);
     const T gb = (wb && cut) ? T(0) : (wb && anti) ? T(-1) : T(1);
+    if constexpr (P == F16S) {  // packed f16 projection, dot2 products (wl_hop16.h)
+        hf2 u[9];
+        raw_link16(p, MU, s, u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            hf2 ps[12], h[6];
+            float sc;
+            raw_spinor16(p, sf, r0 + r, ps, sc);
+            project16<MU, SF>(ps, h);
+            cx<float> g[6];
+            su3_mv16<0>(u, h, g);
+            accum<MU, SF>(acc[r], g, gf * sc);
+        }
+        if constexpr (R > 1)
+            __builtin_amdgcn_sched_barrier(0);
+        raw_link16(p, MU, sb, u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            hf2 ps[12], h[6];
+            float sc;
+            raw_spinor16(p, sb, r0 + r, ps, sc);
+            project16<MU, -SF>(ps, h);
+            cx<float> g[6];
+            su3_mv16<1>(u, h, g);
+            accum<MU, -SF>(acc[r], g, gb * sc);
+        }
+        if constexpr (R > 1)
+            __builtin_amdgcn_sched_barrier(0);
+        return;
+    }
     cx<T> u[9];
     load_link<P>(p.U, p.V, MU, s, u);
 #pragma unroll
@@ -217,6 +275,39 @@ __device__ __forceinline__ void decode(const RawHop<P> &r, cx<typename Traits<P>
     u[8] = cconj(c2);
 }
 
+// The projected hop of raw (still packed) data: g = U (1 + SIG g_MU) psi
+// (ADJ = 0) or U^dag (1 + SIG g_MU) psi (ADJ = 1), the 16-bit site scale not
+// applied.  FP16 storage takes the packed f16 / dot2 path of wl_hop16.h.
+template <int P, int MU, int SIG, int ADJ>
+__device__ __forceinline__ void hop_g(const RawHop<P> &r, cx<typename Traits<P>::real> (&g)[6],
+                                      typename Traits<P>::real one)
+{
+    using T = typename Traits<P>::real;
+    if constexpr (P == F16S) {
+        hf2 ps[12], u[9], h[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ps[4 * k] = as_hf2(r.sp[k].x);
+            ps[4 * k + 1] = as_hf2(r.sp[k].y);
+            ps[4 * k + 2] = as_hf2(r.sp[k].z);
+            ps[4 * k + 3] = as_hf2(r.sp[k].w);
+            u[2 * k] = as_hf2(r.lk[k].x);
+            u[2 * k + 1] = as_hf2(r.lk[k].y);
+        }
+        rebuild_row16(u);
+        project16<MU, SIG>(ps, h);
+        su3_mv16<ADJ>(u, h, g);
+    } else {
+        cx<T> ps[12], u[9], h[6];
+        decode<P>(r, ps, u);
+        project<MU, SIG>(ps, h, one);
+        if constexpr (ADJ)
+            su3_adj_mv(u, h, g);
+        else
+            su3_mv(u, h, g);
+    }
+}
+
 template <int P, int DAG, int H>
 __device__ __forceinline__ void compute_hop(const RawHop<P> &r, float sg, cx<typename Traits<P>::real> (&acc)[12],
                                             typename Traits<P>::real one)
@@ -225,13 +316,8 @@ __device__ __forceinline__ void compute_hop(const RawHop<P> &r, float sg, cx<typ
     constexpr int MU = H / 2;
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SIG = (H % 2 == 0) ? SF : -SF;
-    cx<T> ps[12], u[9], h[6], g[6];
-    decode<P>(r, ps, u);
-    project<MU, SIG>(ps, h, one);
-    if constexpr (H % 2 == 0)
-        su3_mv(u, h, g);
-    else
-        su3_adj_mv(u, h, g);
+    cx<T> g[6];
+    hop_g<P, MU, SIG, H % 2>(r, g, one);
     // the hop is linear in the neighbour spinor, so a 16-bit site's scale
     // multiplies the accumulate coefficient instead of its 24 components
     if constexpr (Traits<P>::SCALED)

@@ -180,6 +180,13 @@ __global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint
                 load_site<P>(p.aux, p.V, p.nrhs, s, rhs, v);
                 bicg_values(self, o, v, red);  // accumulates over the t-walk
             }
+            if constexpr (RED == RED_SR) {
+                cx<R_> a[12], b[12], c[12];
+                load_site<P>(p.aux, p.V, p.nrhs, s, rhs, a);
+                load_site<P>(p.aux2, p.V, p.nrhs, s, rhs, b);
+                load_site<P>(p.aux3, p.V, p.nrhs, s, rhs, c);
+                sr_values(self, o, a, b, c, red);
+            }
             if constexpr (CARRY) {  // the forward neighbour becomes the next site
                 if constexpr (Traits<P>::SCALED)
                     scale_site<P>(nxt, rf.sc);
@@ -290,6 +297,14 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
                 load_site<P>(p.aux, p.V, p.nrhs, s, r0 + r, v);
                 bicg_values(in, o, v, &red[NV * r]);
             }
+            if constexpr (RED == RED_SR) {
+                cx<T> in[12], a[12], b[12], c[12];
+                load_site<P>(p.in, p.V, p.nrhs, s, r0 + r, in);
+                load_site<P>(p.aux, p.V, p.nrhs, s, r0 + r, a);
+                load_site<P>(p.aux2, p.V, p.nrhs, s, r0 + r, b);
+                load_site<P>(p.aux3, p.V, p.nrhs, s, r0 + r, c);
+                sr_values(in, o, a, b, c, &red[NV * r]);
+            }
             if constexpr (RED == RED_DOTV) {
                 cx<T> v[12];
                 load_site<P>(p.aux, p.V, p.nrhs, s, r0 + r, v);
@@ -353,6 +368,7 @@ inline hipError_t launch_v(dim3 grid, dim3 block, const StencilParams &p, hipStr
         hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_DOTIN_NORM, 1, VAR>), grid, block, 0, st, p);
         break;
     case RED_BICG: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_BICG, 1, VAR>), grid, block, 0, st, p); break;
+    case RED_SR: hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_SR, 1, VAR>), grid, block, 0, st, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -385,6 +401,7 @@ inline hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_
         hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_DOTIN_NORM, 1>), grid, block, 0, st, p, T, nxyz, nbxyz);
         break;
     case RED_BICG: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_BICG, 1>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
+    case RED_SR: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_SR, 1>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -22,7 +22,7 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/wl_stencil.hip", "csrc/wl_stencil_kern.h", "csrc/wl_stencil_dev.h", "csrc/wl_brick.h",
-                  "csrc/wl_hop.h", "csrc/wl_common.h", "csrc/wl_blas.hip"]
+                  "csrc/wl_hop.h", "csrc/wl_hop16.h", "csrc/wl_common.h", "csrc/wl_blas.hip"]
 
 
 def source_hash():

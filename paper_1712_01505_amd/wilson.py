@@ -50,13 +50,13 @@ class wl_solve_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("reliable", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("dagger", ctypes.c_int), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t), ("eo", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_size_t), ("eo", ctypes.c_int), ("form", ctypes.c_int)]
 
 
 class wl_solve_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("stencil_calls", ctypes.c_int),
                 ("converged", ctypes.c_int), ("iter_rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("kernels", ctypes.c_int), ("finalizes", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +65,7 @@ class wl_solve_stats(ctypes.Structure):
 class wl_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("rhs_per_thread", ctypes.c_int), ("rhs_lanes", ctypes.c_int),
                 ("xcd_remap", ctypes.c_int), ("variant", ctypes.c_int), ("brick", ctypes.c_int * 3),
-                ("t_steps", ctypes.c_int)]
+                ("t_steps", ctypes.c_int), ("wg_per_cu", ctypes.c_int)]
 
 
 class wl_multi_desc(ctypes.Structure):
@@ -278,24 +278,25 @@ def wl_autotune(op, nrhs, dagger, stream):
 
 
 def wl_get_launch(op, nrhs):
-    """(block, rhs_per_thread, xcd_remap, variant, rhs_lanes, brick_x, brick_y, brick_z, t_steps)
-    used for nrhs right-hand sides (the brick fields are 0 unless variant is 7)."""
+    """(block, rhs_per_thread, xcd_remap, variant, rhs_lanes, brick_x, brick_y, brick_z, t_steps,
+    wg_per_cu) used for nrhs right-hand sides (the brick fields are 0 unless variant is 7)."""
     c = wl_launch()
     _check(lib().wl_get_launch(op, nrhs, ctypes.byref(c)), "wl_get_launch")
     return (c.block, c.rhs_per_thread, c.xcd_remap, c.variant, c.rhs_lanes, c.brick[0], c.brick[1], c.brick[2],
-            c.t_steps)
+            c.t_steps, c.wg_per_cu)
 
 
-def _launch(block, rpt, xcd, variant, lanes, brick, t_steps):
+def _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu=0):
     c = wl_launch(block=block, rhs_per_thread=rpt, rhs_lanes=lanes, xcd_remap=xcd, variant=variant)
     if brick is not None:
         c.brick[0], c.brick[1], c.brick[2] = (int(b) for b in brick)
         c.t_steps = int(t_steps)
+    c.wg_per_cu = int(wg_per_cu)
     return c
 
 
-def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0):
-    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps)
+def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0, wg_per_cu=0):
+    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu)
     return _check(lib().wl_set_launch(op, nrhs, ctypes.byref(c)), "wl_set_launch")
 
 
@@ -308,16 +309,16 @@ VAR_BRICK = 7
 MAX_VARIANT = {k: VAR_BRICK for k in VARIANTS}
 
 
-def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0):
+def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0, wg_per_cu=0):
     """wl_set_launch that returns False (instead of raising) for a configuration
     the library rejects."""
-    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps)
+    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu)
     return lib().wl_set_launch(op, nrhs, ctypes.byref(c)) == WL_OK
 MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
 
 
 WL_DOT_BICG, WL_DOT_V, WL_DOT_NORM = 0, 1, 2
-DOT_NVAL = {WL_DOT_BICG: 7, WL_DOT_V: 2, WL_DOT_NORM: 1}
+DOT_NVAL = {WL_DOT_BICG: 8, WL_DOT_V: 2, WL_DOT_NORM: 1}
 
 
 def wl_apply_dot_workspace_bytes(op, nrhs) -> int:
@@ -594,7 +595,7 @@ def dw_apply(U, psi, m0, m, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None)
 
 
 def dw_solve(U, b, m0, m, precision="f64", tol=1e-10, maxiter=20000, bc=(1, 1, 1, -1), inner_tol=0.0,
-             check_every=0, x0=None, ops=None, return_stats=False, reliable=False):
+             check_every=0, x0=None, ops=None, return_stats=False, reliable=False, form=0):
     """x = D_DW^{-1} b by CG on D_DW^dag D_DW (Sec. II-C, Sec. VI-B) for a canonical 5-d
     complex128 CUDA tensor b (Ns, ...) or (nvec, Ns, ...).
 
@@ -617,7 +618,7 @@ def dw_solve(U, b, m0, m, precision="f64", tol=1e-10, maxiter=20000, bc=(1, 1, 1
     xp = hi.pack(x0) if x0 is not None else hi.new_field(n)
     prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=int(reliable),
                           check_every=check_every, use_x0=1 if x0 is not None else 0, dagger=0,
-                          workspace=None, workspace_bytes=0)
+                          workspace=None, workspace_bytes=0, form=int(form))
     ws = wl_solver_workspace_bytes(hi.handle, lo.handle if lo else None, WL_SOLVER_CGNR, n)
     work = torch.empty(ws, dtype=torch.uint8, device=b.device)
     prm.workspace = work.data_ptr()
@@ -657,13 +658,14 @@ def dslash(U, psi, dagger=False, prec="f64", bc=(1, 1, 1, -1), op=None):
 
 def solve(U, b, kappa, method="bicgstab", precision="f64", tol=1e-10, maxiter=10000, bc=(1, 1, 1, -1),
           inner_tol=0.0, check_every=0, x0=None, ops=None, return_stats=False, dagger=False, reliable=False,
-          eo=False):
+          eo=False, form=0):
     """x = D^{-1} b (dagger: x = D^{-dag} b) for canonical complex128 CUDA tensors.
 
     precision: "f64" (plain FP64), "f32" (plain FP32), or "mixed-f32", "mixed-bf16",
     "mixed-f16" (FP64 refinement around an inner solve with that storage).
     ops: optional (hi, lo) Operators to reuse (lo None for a plain solve).
-    eo: even-odd preconditioning (Schur complement on the even sites)."""
+    eo: even-odd preconditioning (Schur complement on the even sites).
+    form: 0 merged two-phase iterations, 1 one reduction phase per iteration."""
     torch = _torch()
     nrhs = None if b.dim() == 6 else int(b.shape[0])
     n = nrhs or 1
@@ -680,7 +682,7 @@ def solve(U, b, kappa, method="bicgstab", precision="f64", tol=1e-10, maxiter=10
     xp = hi.pack(x0) if x0 is not None else hi.new_field(n)
     prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=int(reliable),
                           check_every=check_every, use_x0=1 if x0 is not None else 0, dagger=int(dagger),
-                          workspace=None, workspace_bytes=0, eo=int(eo))
+                          workspace=None, workspace_bytes=0, eo=int(eo), form=int(form))
     ws = wl_solver_workspace_bytes(hi.handle, lo.handle if lo else None, SOLVER[method], n)
     work = torch.empty(ws, dtype=torch.uint8, device=b.device)
     prm.workspace = work.data_ptr()

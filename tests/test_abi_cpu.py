@@ -145,6 +145,11 @@ def test_bad_arguments_rejected_before_launch():
         prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
         assert L.solve_cgnr(op, op, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EPREC
         assert L.solve_cgnr(op, None, 512, 1024, 65, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
+        prm = wilson.wl_solve_params(tol=1e-10, maxiter=10, form=2)  # no such iteration form
+        assert L.solve_bicgstab(op, None, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
+        # the single-reduction forms take defect correction only
+        prm = wilson.wl_solve_params(tol=1e-10, maxiter=10, form=1, reliable=1)
+        assert L.solve_bicgstab(op, op, 512, 1024, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL
         assert L.wilson_gauge_force(op, 512, 1024, 2048, 3, None) == wilson.WL_EINVAL
         hb = ctypes.c_size_t(0)
         assert L.wl_halo_bytes(op, 2, ctypes.byref(hb)) == wilson.WL_OK
@@ -230,3 +235,34 @@ def _fastdiv_source():
     start = text.index("struct FastDiv {")
     end = text.index("// ---------------------------------------------------------------- tile order")
     return ["namespace wl {\n", text[start:end], "}\n"]
+
+
+def test_tune_cache_json_is_read(tmp_path):
+    """The launch-shape cache is JSON with one entry per line; a fresh process
+    that finds an entry for its (arch, extents, precision, nrhs, dagger,
+    reduction) key launches with it (no GPU: the architecture reads as
+    "unknown")."""
+    import json
+    import subprocess
+    import sys
+    path = tmp_path / "tune.json"
+    entry = {"key": "unknown:8x8x8x8:p1:n1:d0:r0", "arch": "unknown", "dims": [8, 8, 8, 8], "prec": 1, "nrhs": 1,
+             "dagger": 0, "reduction": 0, "block": 128, "rhs_per_thread": 1, "rhs_lanes": 1, "xcd_remap": 0,
+             "variant": 7, "brick": [8, 4, 4], "t_steps": 8, "wg_per_cu": 2, "us": 12.5}
+    path.write_text(json.dumps({"format": "wilson launch shapes", "entries": [entry]}, indent=None)
+                    .replace("[{", "[\n{").replace("}]", "}\n]") + "\n")
+    code = (
+        "import ctypes\n"
+        "from paper_1712_01505_amd import wilson\n"
+        "L = wilson.lib()\n"
+        "g = wilson.make_geom((8, 8, 8, 8))\n"
+        "op = ctypes.c_void_p()\n"
+        "assert L.wl_op_create(ctypes.byref(g), 0.12, wilson.WL_F32, 256, ctypes.byref(op)) == 0\n"
+        "c = wilson.wl_launch()\n"
+        "assert L.wl_get_launch(op, 1, ctypes.byref(c)) == 0\n"
+        "print(c.block, c.variant, tuple(c.brick), c.t_steps, c.wg_per_cu)\n")
+    env = dict(os.environ, WL_TUNE_CACHE=str(path))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["128", "7", "(8,", "4,", "4)", "8", "2"], out.stdout

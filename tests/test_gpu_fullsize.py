@@ -82,8 +82,8 @@ def test_tuned_launches_match_oracle_32x64(W, oracle_mod, fields, prec):
                 assert torch.equal(o2, out), (prec, dagger, kind)  # every shape adds in the same order
             oq = o2.cpu().numpy()
             if kind == W.WL_DOT_BICG:
-                want = [_cdot(inq, oq), _cdot(oq, oq), _cdot(vq, inq), _cdot(vq, oq)]
-                got_c = [dots[0] + 1j * dots[1], dots[2], dots[3] + 1j * dots[4], dots[5] + 1j * dots[6]]
+                want = [_cdot(inq, oq), _cdot(oq, oq), _cdot(vq, inq), _cdot(vq, oq), _cdot(inq, inq)]
+                got_c = [dots[0] + 1j * dots[1], dots[2], dots[3] + 1j * dots[4], dots[5] + 1j * dots[6], dots[7]]
             elif kind == W.WL_DOT_V:
                 want, got_c = [_cdot(vq, oq)], [dots[0] + 1j * dots[1]]
             else:
