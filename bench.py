@@ -261,6 +261,7 @@ def bench_batching(W, inputs, torch, log, oracle=None):
     log(f"[bench] multi-lattice: {out['multi_lattice_f32']}")
     del ops, srcs, dsts, plan
     torch.cuda.empty_cache()
+    out["multi_lattice_solve"] = bench_multi_solve(W, inputs, torch, log, oracle, lattices, kappa)
     # an ensemble of small lattices (64 of 4^4 .. 8^4), where separate
     # launches are bound by their fixed cost
     shapes = [(4, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8), (4, 4, 4, 8)]
@@ -292,6 +293,70 @@ def _copy_launch(W, src_op, dst_op, nrhs=1):
     c = W.wl_get_launch(src_op.handle, nrhs)
     W.wl_set_launch(dst_op.handle, nrhs, c[0], c[1], c[2], c[3], c[4],
                     brick=c[5:8] if c[3] == W.VAR_BRICK else None, t_steps=c[8], wg_per_cu=c[9])
+
+
+def bench_multi_solve(W, inputs, torch, log, oracle, lattices, kappa):
+    """The uneven lattices x 4 Gaussian sources solved together (mixed FP32
+    BiCGStab to 1e-10: every stencil one multi-lattice launch) against the
+    same four systems solved one after the other, each column checked with
+    the oracle's D."""
+    import numpy as np
+    st = W._stream()
+    nrhs = 4
+    systems, host = [], []
+    for j, dj in enumerate(lattices):
+        U = inputs.near_unity_gauge(dj, 0.3, seed=10 + j)
+        b = inputs.gaussian_spinor(dj, seed=100 * j, nrhs=nrhs)
+        Ud = torch.from_numpy(U).cuda()
+        hi = W.Operator.create(Ud, kappa, W.WL_F64)
+        lo = W.Operator.create(Ud, kappa, W.WL_F32)
+        systems.append((hi, lo, hi.pack(torch.from_numpy(b).cuda())))
+        host.append((U, b))
+    # the multi-lattice stencil shape: the plan tuner's choice for these lattices
+    plans = []
+    for prec_op in (0, 1):
+        fields = [(s_[prec_op], s_[prec_op].new_field(nrhs), s_[prec_op].new_field(nrhs)) for s_ in systems]
+        plan = W.MultiPlan([(o.handle, d.data_ptr(), i.data_ptr()) for o, d, i in fields], 0, nrhs)
+        plan.tune(st)
+        plans.append(plan.launch())
+        del plan, fields
+    W.solve_multi(systems, nrhs=nrhs, method="bicgstab", tol=1e-10)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, stm = W.solve_multi(systems, nrhs=nrhs, method="bicgstab", tol=1e-10, return_stats=True)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t0
+
+    def separate():
+        res = []
+        for hi, lo, b in systems:
+            res.append(W.solve(None, hi.unpack(b, nrhs), kappa, method="bicgstab", tol=1e-10, ops=(hi, lo),
+                               return_stats=True)[1])
+        return res
+    separate()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = separate()
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    r = {"lattices": [list(d) for d in lattices], "nrhs": nrhs, "precision": "mixed-f32", "method": "bicgstab",
+         "tol": 1e-10, "seconds": round(t_multi, 4), "separate_seconds": round(t_sep, 4),
+         "speedup": round(t_sep / t_multi, 3), "plan_launch_f64_f32": plans,
+         "iters": [s_["iters"] for s_ in stm], "separate_iters": [s_["iters"] for sj in sts for s_ in sj],
+         "kernels": stm[0]["kernels"], "separate_kernels": sum(sj[0]["kernels"] for sj in sts),
+         "status": stm[0]["status"], "max_true_rel_res": max(s_["true_rel_res"] for s_ in stm)}
+    if oracle is not None:
+        worst = 0.0
+        for (hi, _, _), (U, b), x in zip(systems, host, xs):
+            xc = hi.unpack(x, nrhs).cpu().numpy()
+            for k in range(nrhs):
+                res = b[k] - oracle.apply(U, xc[k], kappa)
+                worst = max(worst, float(np.linalg.norm(res) / np.linalg.norm(b[k])))
+        r["max_oracle_true_rel_res"] = worst
+    log(f"[bench] multi-lattice solve: {r}")
+    del systems, xs
+    torch.cuda.empty_cache()
+    return r
 
 
 def bench_c2(W, inputs, torch, log, oracle=None):

@@ -128,11 +128,12 @@ int wilson_apply(const wl_op *op, void *out, const void *in, int dagger, int nrh
  * out = D in (dagger: D^dag in) computed as one rank of a lattice decomposed
  * in t whose neighbours are itself: the projected half-spinors of the two t
  * faces are packed into buffers (12 reals per face site; the t = Lt-1 face
- * already multiplied by its link) and copied device to device on a library
- * stream while the caller's stream runs the interior stencil with the
- * wrapping t hops left out; a last kernel on the caller's stream adds the
- * received faces to the t = 0 and t = Lt-1 slices.  The result equals
- * wilson_apply's up to the order of the additions.  halo: device buffer of
+ * already multiplied by its link) and copied device to device (the
+ * exchange), the interior stencil runs in the tuned launch shape with the
+ * wrapping t hops left out, and a last kernel adds the received faces to
+ * the t = 0 and t = Lt-1 slices; all four in that order on `stream` (on one
+ * GPU the copy costs less than a synchronisation with a second stream).
+ * The result equals wilson_apply's up to the order of the additions.  halo: device buffer of
  * wl_halo_bytes (send and receive regions; FP64 ops use double, the others
  * float), owned by the caller and not used concurrently by two calls.
  * Wilson ops only.  Async with respect to the host. */
@@ -321,6 +322,36 @@ int wl_multi_plan_destroy(wl_multi_plan *plan);
 
 /* One-shot form: create a plan, run it, wait for `stream`, destroy it. */
 int wilson_multi_apply(const wl_multi_desc *d, int n, int dagger, int nrhs, void *stream);
+
+/* ---- Multi-lattice solve (Sec. II-C solvers over several lattices at once)
+ * n linear systems D_i x_i = b_i on lattices of any extents (each with its
+ * own links, kappa and boundary signs), nrhs right-hand sides each, solved
+ * together: every stencil application of the Krylov iteration is ONE
+ * multi-lattice launch over all lattices (the plan kernel with the solver's
+ * fused reduction, one descriptor table per call site, uploaded once per
+ * solve), every vector update one launch over all columns and every
+ * reduction one finalize; each (lattice, right-hand side) column keeps its
+ * own scalars and stops on its own tolerance.  Solver, params, precision
+ * pairing and stats as solve_cgnr / solve_bicgstab: hi ops all of one
+ * precision (plain: WL_F64 or WL_F32; mixed: WL_F64 with lo ops all of one
+ * lower precision, lo_i on the geometry and kappa of hi_i), Wilson ops only,
+ * n * nrhs <= 64, eo = 0.  x_i, b_i: packed fields of hi_i's precision with
+ * nrhs columns (x_i holds the start if use_x0).  The workspace
+ * (wl_multi_solver_workspace_bytes) holds the segmented vectors; the right-
+ * hand sides are gathered into it and the solutions scattered back (device
+ * copies).  The stencil shape is the multi-lattice plan tuner's choice for
+ * these lattices (one right-hand side per thread) if one is cached, else the
+ * default.  stats: n * nrhs entries, column i * nrhs + r.  Synchronises
+ * `stream`; returns the worst status. */
+typedef struct {
+    const wl_op *hi;
+    const wl_op *lo;  /* NULL for a plain solve (then NULL for every system) */
+    void *x;
+    const void *b;
+} wl_multi_system;
+int wl_multi_solver_workspace_bytes(const wl_multi_system *s, int n, int solver, int nrhs, size_t *out_bytes);
+int wilson_solve_multi(const wl_multi_system *s, int n, int solver, int nrhs, const wl_solve_params *p,
+                       wl_solve_stats *stats, void *stream);
 
 /* Time the stencil launch candidates for (op geometry, precision, nrhs,
  * dagger), for the plain apply and for each fused reduction the solvers use,

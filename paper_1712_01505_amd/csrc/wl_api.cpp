@@ -30,6 +30,11 @@ struct wl_multi_plan {
 
 namespace wl {
 size_t solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs);
+size_t multi_solver_workspace_bytes(const std::vector<const wl_op *> &hi, const std::vector<const wl_op *> &lo,
+                                    int solver, int nrhs);
+int solve_multi(int solver, const std::vector<const wl_op *> &hi, const std::vector<const wl_op *> &lo,
+                void *const *x, const void *const *b, int nrhs, const LaunchCfg &cfg, const LaunchCfg &cfg_lo,
+                const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st);
 int solve(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs, const wl_solve_params *prm,
           wl_solve_stats *stats, hipStream_t st);
 
@@ -423,16 +428,40 @@ static LaunchCfg multi_default(int prec, int nrhs)
     return LaunchCfg{256, 1, 1, prec == WL_F64 ? 1 : 2, 1};
 }
 
-static std::string multi_key(const wl_multi_plan *pl)
+static std::string multi_key_of(int prec, int nrhs, int dagger, const std::vector<const wl_op *> &ops)
 {
-    std::string k = arch_name() + ":multi:p" + std::to_string(pl->prec) + ":n" + std::to_string(pl->nrhs) + ":d" +
-                    std::to_string(pl->dagger);
-    for (const auto &d : pl->desc) {
+    std::string k = arch_name() + ":multi:p" + std::to_string(prec) + ":n" + std::to_string(nrhs) + ":d" +
+                    std::to_string(dagger);
+    for (const wl_op *op : ops) {
         char buf[64];
-        snprintf(buf, sizeof buf, ":%dx%dx%dx%d", d.op->g.dims[0], d.op->g.dims[1], d.op->g.dims[2], d.op->g.dims[3]);
+        snprintf(buf, sizeof buf, ":%dx%dx%dx%d", op->g.dims[0], op->g.dims[1], op->g.dims[2], op->g.dims[3]);
         k += buf;
     }
     return k;
+}
+
+static std::string multi_key(const wl_multi_plan *pl)
+{
+    std::vector<const wl_op *> ops;
+    for (const auto &d : pl->desc)
+        ops.push_back(d.op);
+    return multi_key_of(pl->prec, pl->nrhs, pl->dagger, ops);
+}
+
+// Launch shape of a multi-lattice solve's stencils (one site per thread, the
+// direct form): the plan tuner's choice for these lattices if it has one
+// with one right-hand side per thread, else the default.
+static LaunchCfg multi_solve_shape(int prec, int nrhs, const std::vector<const wl_op *> &ops)
+{
+    LaunchCfg c = multi_default(prec, nrhs);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    auto it = g_tune.find(multi_key_of(prec, nrhs, 0, ops));
+    if (it != g_tune.end() && it->second.c.rpt == 1 && multi_launch_ok(prec, 1, it->second.c.block, it->second.c.var))
+        c = it->second.c;
+    c.rpt = 1;
+    c.xcd = 0;
+    return c;
 }
 
 static std::string multi_fields(const wl_multi_plan *pl)
@@ -641,11 +670,11 @@ static int stencil_call(const wl_op *op, void *out, const void *in, int dagger, 
     return WL_OK;
 }
 
-// Enforced halo: a library stream (default priority) carries the face pack
-// and copy beside the caller's stream, which runs the interior.
-static std::mutex g_halo_mu;
-static hipStream_t g_halo_stream = nullptr;
-static hipEvent_t g_halo_ev[2] = {nullptr, nullptr};
+// Enforced halo: face pack, the face copy, the interior and the finish, in
+// that order on the caller's stream.  On one GPU the copy takes a few
+// microseconds, less than a synchronisation between two streams would; with
+// several GPUs the exchange goes to a communication stream and overlaps the
+// interior.
 
 int wl_halo_bytes(const wl_op *op, int nrhs, size_t *out_bytes)
 {
@@ -667,33 +696,20 @@ int wilson_apply_halo(const wl_op *op, void *out, const void *in, int dagger, in
         return WL_EWORKSPACE;
     if (!al16(out) || !al16(in) || !al16(halo))
         return WL_EALIGN;
-    LaunchCfg cfg = launch_for(op, nrhs, RED_NONE, dagger);
-    if (cfg.rpt == 1 && cfg.var >= 4) {  // the t-walk keeps its t hops in registers: use the hop loop
-        cfg.var = op->prec == WL_F64 ? 1 : 2;
-        cfg.xcd = cfg.xcd ? 1 : 0;
-    }
+    // the interior runs in the tuned shape (every variant leaves out the
+    // wrapping t hops when halo_t is set)
+    const LaunchCfg cfg = launch_for(op, nrhs, RED_NONE, dagger);
     StencilParams p = base_params(op, out, in, nrhs, 1);
     p.halo_t = 1;
     p.halo_send = halo;
     p.halo_recv = (char *)halo + need / 2;
     hipStream_t st = (hipStream_t)stream;
-    std::lock_guard<std::mutex> lk(g_halo_mu);
-    if (!g_halo_stream) {
-        CHECK_HIP(hipStreamCreateWithFlags(&g_halo_stream, hipStreamNonBlocking));
-        CHECK_HIP(hipEventCreateWithFlags(&g_halo_ev[0], hipEventDisableTiming));
-        CHECK_HIP(hipEventCreateWithFlags(&g_halo_ev[1], hipEventDisableTiming));
-    }
-    // faces: pack and copy on the side stream once the caller's prior work is done
-    CHECK_HIP(hipEventRecord(g_halo_ev[0], st));
-    CHECK_HIP(hipStreamWaitEvent(g_halo_stream, g_halo_ev[0], 0));
-    CHECK_HIP(launch_halo_pack(op->prec, dagger, p, g_halo_stream));
-    CHECK_HIP(hipMemcpyAsync(const_cast<void *>(p.halo_recv), p.halo_send, need / 2, hipMemcpyDeviceToDevice,
-                             g_halo_stream));
-    CHECK_HIP(hipEventRecord(g_halo_ev[1], g_halo_stream));
-    // interior (every site, wrapping t hops cut) on the caller's stream meanwhile
+    CHECK_HIP(launch_halo_pack(op->prec, dagger, p, st));
+    // the exchange (here with itself): a streaming copy kernel
+    CHECK_HIP(launch_stream_copy(const_cast<void *>(p.halo_recv), p.halo_send, need / 2, st));
+    // interior: every site, the wrapping t hops left out
     CHECK_HIP(prof_stencil(op->prec, op, dagger, cfg, p, st));
     // then the received faces into the boundary slices
-    CHECK_HIP(hipStreamWaitEvent(st, g_halo_ev[1], 0));
     CHECK_HIP(launch_halo_finish(op->prec, dagger, p, st));
     return WL_OK;
 }
@@ -828,6 +844,75 @@ int solve_bicgstab(const wl_op *hi, const wl_op *lo, void *x, const void *b, int
                    wl_solve_stats *stats, void *stream)
 {
     return solve_entry(WL_SOLVER_BICGSTAB, hi, lo, x, b, nrhs, p, stats, stream);
+}
+
+// Multi-lattice solves: validation shared by the workspace query and the solve.
+static int multi_systems(const wl_multi_system *s, int n, int solver, int nrhs, std::vector<const wl_op *> &hi,
+                         std::vector<const wl_op *> &lo)
+{
+    if (!s || n < 1 || nrhs < 1 || (long)n * nrhs > 64 || (solver != WL_SOLVER_CGNR && solver != WL_SOLVER_BICGSTAB))
+        return WL_EINVAL;
+    const bool mixed = s[0].lo != nullptr;
+    for (int i = 0; i < n; ++i) {
+        const wl_multi_system &q = s[i];
+        if (!q.hi || q.hi->ns > 0 || (q.lo != nullptr) != mixed || q.hi->prec != s[0].hi->prec)
+            return WL_EINVAL;
+        if (mixed) {
+            if (q.lo->ns > 0 || q.lo->prec != s[0].lo->prec)
+                return WL_EINVAL;
+            for (int k = 0; k < 4; ++k)
+                if (q.lo->g.dims[k] != q.hi->g.dims[k] || q.lo->g.bc[k] != q.hi->g.bc[k])
+                    return WL_EINVAL;
+            if (q.lo->kappa != q.hi->kappa)
+                return WL_EINVAL;
+        }
+        hi.push_back(q.hi);
+        if (mixed)
+            lo.push_back(q.lo);
+    }
+    if (mixed ? (s[0].hi->prec != WL_F64 || s[0].lo->prec == WL_F64)
+              : (s[0].hi->prec != WL_F64 && s[0].hi->prec != WL_F32))
+        return WL_EPREC;
+    return WL_OK;
+}
+
+int wl_multi_solver_workspace_bytes(const wl_multi_system *s, int n, int solver, int nrhs, size_t *out_bytes)
+{
+    std::vector<const wl_op *> hi, lo;
+    if (!out_bytes)
+        return WL_EINVAL;
+    const int rc = multi_systems(s, n, solver, nrhs, hi, lo);
+    if (rc != WL_OK)
+        return rc;
+    *out_bytes = multi_solver_workspace_bytes(hi, lo, solver, nrhs);
+    return WL_OK;
+}
+
+int wilson_solve_multi(const wl_multi_system *s, int n, int solver, int nrhs, const wl_solve_params *p,
+                       wl_solve_stats *stats, void *stream)
+{
+    std::vector<const wl_op *> hi, lo;
+    int rc = multi_systems(s, n, solver, nrhs, hi, lo);
+    if (rc != WL_OK)
+        return rc;
+    if (!p || !(p->tol > 0) || p->maxiter < 1 || (p->dagger != 0 && p->dagger != 1) || (p->form != 0 && p->form != 1) ||
+        p->eo != 0 || (p->form == 1 && !lo.empty() && p->reliable))
+        return WL_EINVAL;
+    if (p->reliable && solver == WL_SOLVER_CGNR && !lo.empty() && lo[0]->prec != WL_F32)
+        return WL_EPREC;
+    std::vector<void *> x(n);
+    std::vector<const void *> b(n);
+    for (int i = 0; i < n; ++i) {
+        if (!s[i].x || !s[i].b || s[i].x == s[i].b)
+            return WL_EINVAL;
+        if (!al16(s[i].x) || !al16(s[i].b))
+            return WL_EALIGN;
+        x[i] = s[i].x;
+        b[i] = s[i].b;
+    }
+    const LaunchCfg cfg = multi_solve_shape(hi[0]->prec, nrhs, hi);
+    const LaunchCfg cfg_lo = lo.empty() ? cfg : multi_solve_shape(lo[0]->prec, nrhs, lo);
+    return solve_multi(solver, hi, lo, x.data(), b.data(), nrhs, cfg, cfg_lo, p, stats, (hipStream_t)stream);
 }
 
 int wilson_gauge_force(const wl_op *op, void *out_canon, const void *x, const void *mu, int project, void *stream)

@@ -70,84 +70,100 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
     constexpr int NV = blas_nv(OP);
     constexpr int NA = NV > 0 ? NV : 1;
     __shared__ double lds[NA * 4];
-    const int r = blockIdx.y;
-    const uint32_t V = p.V;
-    const int nr = p.nrhs;
-    if (p.skip_frozen && p.sc[r].frozen)  // whole workgroup: one column per blockIdx.y
+    // one column per blockIdx.y; segmented vectors: that column's lattice
+    // segment (its sites, columns and offset into every buffer)
+    const int col = blockIdx.y;
+    uint32_t V = p.V;
+    int nr = p.nrhs, r = col;
+    size_t off = 0;
+    if (p.seg) {
+        const Seg g = p.seg[col];
+        V = g.V;
+        nr = g.nrhs;
+        r = g.r;
+        off = g.off;
+    }
+    void *const Y0 = p.y0 ? (char *)p.y0 + off : nullptr, *const Y1 = p.y1 ? (char *)p.y1 + off : nullptr;
+    void *const Y2 = p.y2 ? (char *)p.y2 + off : nullptr, *const Y3 = p.y3 ? (char *)p.y3 + off : nullptr;
+    const void *const A0 = p.a0 ? (const char *)p.a0 + off : nullptr;
+    const void *const A1 = p.a1 ? (const char *)p.a1 + off : nullptr;
+    const void *const A2 = p.a2 ? (const char *)p.a2 + off : nullptr;
+    const void *const A3 = p.a3 ? (const char *)p.a3 + off : nullptr;
+    if (p.skip_frozen && p.sc[col].frozen)  // whole workgroup
         return;
-    if (OP == B_CG_RESTART && !p.sc[r].restart)
+    if (OP == B_CG_RESTART && !p.sc[col].restart)
         return;
     double red[NA] = {};
     for (int j = 0; j < blas_spt(OP); ++j) {
     const uint32_t s = (blockIdx.x * blas_spt(OP) + j) * blockDim.x + threadIdx.x;
     if (s < V) {
-        const Scalars &sc = p.sc[r];
+        const Scalars &sc = p.sc[col];
         if constexpr (OP == B_RES) {  // r = b - w
             cx<T> b[12], w[12], o[12];
-            load_site<P>(p.a0, V, nr, s, r, b);
-            load_site<P>(p.a1, V, nr, s, r, w);
+            load_site<P>(A0, V, nr, s, r, b);
+            load_site<P>(A1, V, nr, s, r, w);
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 o[k] = cx<T>{b[k].re - w[k].re, b[k].im - w[k].im};
             round_if_scaled<P>(o);
-            store_site<P>(p.y0, V, nr, s, r, o);
+            store_site<P>(Y0, V, nr, s, r, o);
             red[0] += n2(o);
         } else if constexpr (OP == B_CG_XR) {  // x += a p ; r -= a w
             const T a = (T)sc.alpha.x;
             cx<T> x[12], rr[12], pp[12], w[12];
-            load_site<P>(p.y0, V, nr, s, r, x);
-            load_site<P>(p.y1, V, nr, s, r, rr);
-            load_site<P>(p.a0, V, nr, s, r, pp);
-            load_site<P>(p.a1, V, nr, s, r, w);
+            load_site<P>(Y0, V, nr, s, r, x);
+            load_site<P>(Y1, V, nr, s, r, rr);
+            load_site<P>(A0, V, nr, s, r, pp);
+            load_site<P>(A1, V, nr, s, r, w);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 x[k] = rfma(a, pp[k], x[k]);
                 rr[k] = rfma(-a, w[k], rr[k]);
             }
             round_if_scaled<P>(rr);
-            store_site<P>(p.y0, V, nr, s, r, x);
-            store_site<P>(p.y1, V, nr, s, r, rr);
+            store_site<P>(Y0, V, nr, s, r, x);
+            store_site<P>(Y1, V, nr, s, r, rr);
             red[0] += n2(rr);
         } else if constexpr (OP == B_CG_P) {  // p = z + beta p
             const T b = (T)sc.beta.x;
             cx<T> pp[12], z[12];
-            load_site<P>(p.y0, V, nr, s, r, pp);
-            load_site<P>(p.a0, V, nr, s, r, z);
+            load_site<P>(Y0, V, nr, s, r, pp);
+            load_site<P>(A0, V, nr, s, r, z);
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 pp[k] = rfma(b, pp[k], z[k]);
-            store_site<P>(p.y0, V, nr, s, r, pp);
+            store_site<P>(Y0, V, nr, s, r, pp);
         } else if constexpr (OP == B_BI_P) {  // p = r + beta (p - omega v)
             const cx<T> b{(T)sc.beta.x, (T)sc.beta.y}, om{(T)sc.omega.x, (T)sc.omega.y};
             cx<T> pp[12], rr[12], v[12];
-            load_site<P>(p.y0, V, nr, s, r, pp);
-            load_site<P>(p.a0, V, nr, s, r, rr);
-            load_site<P>(p.a1, V, nr, s, r, v);
+            load_site<P>(Y0, V, nr, s, r, pp);
+            load_site<P>(A0, V, nr, s, r, rr);
+            load_site<P>(A1, V, nr, s, r, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 cx<T> d = cfma(cx<T>{-om.re, -om.im}, v[k], pp[k]);
                 pp[k] = cfma(b, d, rr[k]);
             }
-            store_site<P>(p.y0, V, nr, s, r, pp);
+            store_site<P>(Y0, V, nr, s, r, pp);
         } else if constexpr (OP == B_BI_S) {  // s = r - alpha v (|s|^2 comes with t = D s)
             const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y};
             cx<T> rr[12], v[12];
-            load_site<P>(p.a0, V, nr, s, r, rr);
-            load_site<P>(p.a1, V, nr, s, r, v);
+            load_site<P>(A0, V, nr, s, r, rr);
+            load_site<P>(A1, V, nr, s, r, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 rr[k] = cfma(cx<T>{-a.re, -a.im}, v[k], rr[k]);
-            store_site<P>(p.y0, V, nr, s, r, rr);
+            store_site<P>(Y0, V, nr, s, r, rr);
         } else if constexpr (OP == B_CG1) {
             // p = z + beta p ; w = q + beta w ; x += alpha p ; r -= alpha w
             const T a = (T)sc.alpha.x, b = (T)sc.beta.x;
             cx<T> x[12], rr[12], pp[12], w[12], z[12], q[12];
-            load_site<P>(p.y2, V, nr, s, r, pp);
-            load_site<P>(p.y3, V, nr, s, r, w);
-            load_site<P>(p.a0, V, nr, s, r, z);
-            load_site<P>(p.a1, V, nr, s, r, q);
-            load_site<P>(p.y0, V, nr, s, r, x);
-            load_site<P>(p.y1, V, nr, s, r, rr);
+            load_site<P>(Y2, V, nr, s, r, pp);
+            load_site<P>(Y3, V, nr, s, r, w);
+            load_site<P>(A0, V, nr, s, r, z);
+            load_site<P>(A1, V, nr, s, r, q);
+            load_site<P>(Y0, V, nr, s, r, x);
+            load_site<P>(Y1, V, nr, s, r, rr);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 pp[k] = rfma(b, pp[k], z[k]);
@@ -162,10 +178,10 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
                 rr[k] = rfma(-a, w[k], rr[k]);
             }
             round_if_scaled<P>(rr);
-            store_site<P>(p.y2, V, nr, s, r, pp);
-            store_site<P>(p.y3, V, nr, s, r, w);
-            store_site<P>(p.y0, V, nr, s, r, x);
-            store_site<P>(p.y1, V, nr, s, r, rr);
+            store_site<P>(Y2, V, nr, s, r, pp);
+            store_site<P>(Y3, V, nr, s, r, w);
+            store_site<P>(Y0, V, nr, s, r, x);
+            store_site<P>(Y1, V, nr, s, r, rr);
             red[0] += n2(rr);
         } else if constexpr (OP == B_SR_PV) {
             // p = r + beta (p - omega v) ; v = u + beta (v - omega q) ; then
@@ -173,21 +189,21 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             const cx<T> b{(T)sc.beta.x, (T)sc.beta.y}, om{(T)sc.omega.x, (T)sc.omega.y};
             const cx<T> mom{-om.re, -om.im};
             cx<T> pp[12], v[12], rr[12], u[12], q[12];
-            load_site<P>(p.y0, V, nr, s, r, pp);
-            load_site<P>(p.y1, V, nr, s, r, v);
-            load_site<P>(p.a0, V, nr, s, r, rr);
-            load_site<P>(p.a1, V, nr, s, r, u);
-            load_site<P>(p.a2, V, nr, s, r, q);
+            load_site<P>(Y0, V, nr, s, r, pp);
+            load_site<P>(Y1, V, nr, s, r, v);
+            load_site<P>(A0, V, nr, s, r, rr);
+            load_site<P>(A1, V, nr, s, r, u);
+            load_site<P>(A2, V, nr, s, r, q);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 pp[k] = cfma(b, cfma(mom, v[k], pp[k]), rr[k]);
                 v[k] = cfma(b, cfma(mom, q[k], v[k]), u[k]);
             }
             round_if_scaled<P>(v);
-            store_site<P>(p.y0, V, nr, s, r, pp);
-            store_site<P>(p.y1, V, nr, s, r, v);
+            store_site<P>(Y0, V, nr, s, r, pp);
+            store_site<P>(Y1, V, nr, s, r, v);
             cx<T> rh[12];
-            load_site<P>(p.a3, V, nr, s, r, rh);
+            load_site<P>(A3, V, nr, s, r, rh);
             dot(rh, v, red[0], red[1]);
             dot(rh, u, red[2], red[3]);
             dot(u, rr, red[4], red[5]);
@@ -198,10 +214,10 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
             const cx<T> ma{-a.re, -a.im}, mom{-om.re, -om.im};
             cx<T> x[12], rr[12], pp[12], v[12];
-            load_site<P>(p.y0, V, nr, s, r, x);
-            load_site<P>(p.y1, V, nr, s, r, rr);
-            load_site<P>(p.a0, V, nr, s, r, pp);
-            load_site<P>(p.a1, V, nr, s, r, v);
+            load_site<P>(Y0, V, nr, s, r, x);
+            load_site<P>(Y1, V, nr, s, r, rr);
+            load_site<P>(A0, V, nr, s, r, pp);
+            load_site<P>(A1, V, nr, s, r, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 rr[k] = cfma(ma, v[k], rr[k]);  // s
@@ -209,22 +225,22 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
                 x[k] = cfma(om, rr[k], x[k]);
             }
             cx<T> u[12], q[12];
-            load_site<P>(p.a2, V, nr, s, r, u);
-            load_site<P>(p.a3, V, nr, s, r, q);
+            load_site<P>(A2, V, nr, s, r, u);
+            load_site<P>(A3, V, nr, s, r, q);
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 rr[k] = cfma(mom, cfma(ma, q[k], u[k]), rr[k]);
             round_if_scaled<P>(rr);
-            store_site<P>(p.y0, V, nr, s, r, x);
-            store_site<P>(p.y1, V, nr, s, r, rr);
+            store_site<P>(Y0, V, nr, s, r, x);
+            store_site<P>(Y1, V, nr, s, r, rr);
             red[0] += n2(rr);
         } else if constexpr (OP == B_BI_XR) {  // x += alpha p + omega s ; r = s - omega t
             const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
             cx<T> x[12], pp[12], ss[12], t[12];
-            load_site<P>(p.y0, V, nr, s, r, x);
-            load_site<P>(p.a0, V, nr, s, r, pp);
-            load_site<P>(p.a1, V, nr, s, r, ss);
-            load_site<P>(p.a2, V, nr, s, r, t);
+            load_site<P>(Y0, V, nr, s, r, x);
+            load_site<P>(A0, V, nr, s, r, pp);
+            load_site<P>(A1, V, nr, s, r, ss);
+            load_site<P>(A2, V, nr, s, r, t);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 x[k] = cfma(a, pp[k], x[k]);
@@ -232,11 +248,11 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
                 ss[k] = cfma(cx<T>{-om.re, -om.im}, t[k], ss[k]);
             }
             round_if_scaled<P>(ss);
-            store_site<P>(p.y0, V, nr, s, r, x);
-            store_site<P>(p.y1, V, nr, s, r, ss);
+            store_site<P>(Y0, V, nr, s, r, x);
+            store_site<P>(Y1, V, nr, s, r, ss);
             red[0] += n2(ss);
             cx<T> rh[12];
-            load_site<P>(p.a3, V, nr, s, r, rh);
+            load_site<P>(A3, V, nr, s, r, rh);
             dot(rh, ss, red[1], red[2]);
         } else if constexpr (OP == B_BI_XRP) {
             // B_BI_XR and the next B_BI_P in one pass (beta is known before r
@@ -245,10 +261,10 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             const cx<T> a{(T)sc.alpha.x, (T)sc.alpha.y}, om{(T)sc.omega.x, (T)sc.omega.y};
             const cx<T> b{(T)sc.beta.x, (T)sc.beta.y};
             cx<T> x[12], pp[12], ss[12], t[12];
-            load_site<P>(p.y0, V, nr, s, r, x);
-            load_site<P>(p.y2, V, nr, s, r, pp);
-            load_site<P>(p.a1, V, nr, s, r, ss);
-            load_site<P>(p.a2, V, nr, s, r, t);
+            load_site<P>(Y0, V, nr, s, r, x);
+            load_site<P>(Y2, V, nr, s, r, pp);
+            load_site<P>(A1, V, nr, s, r, ss);
+            load_site<P>(A2, V, nr, s, r, t);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 x[k] = cfma(a, pp[k], x[k]);
@@ -256,39 +272,39 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
                 ss[k] = cfma(cx<T>{-om.re, -om.im}, t[k], ss[k]);
             }
             round_if_scaled<P>(ss);
-            store_site<P>(p.y0, V, nr, s, r, x);
-            store_site<P>(p.y1, V, nr, s, r, ss);
+            store_site<P>(Y0, V, nr, s, r, x);
+            store_site<P>(Y1, V, nr, s, r, ss);
             red[0] += n2(ss);
             cx<T> v[12];
-            load_site<P>(p.a3, V, nr, s, r, v);
+            load_site<P>(A3, V, nr, s, r, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const cx<T> d = cfma(cx<T>{-om.re, -om.im}, v[k], pp[k]);
                 pp[k] = cfma(b, d, ss[k]);
             }
-            store_site<P>(p.y2, V, nr, s, r, pp);
+            store_site<P>(Y2, V, nr, s, r, pp);
         } else if constexpr (OP == B_COPY) {
             cx<T> v[12];
-            load_site<P>(p.a0, V, nr, s, r, v);
-            store_site<P>(p.y0, V, nr, s, r, v);
+            load_site<P>(A0, V, nr, s, r, v);
+            store_site<P>(Y0, V, nr, s, r, v);
         } else if constexpr (OP == B_ZERO) {
             cx<T> v[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 v[k] = cx<T>{T(0), T(0)};
-            store_site<P>(p.y0, V, nr, s, r, v);
+            store_site<P>(Y0, V, nr, s, r, v);
         } else if constexpr (OP == B_NORM) {
             cx<T> v[12];
-            load_site<P>(p.a0, V, nr, s, r, v);
+            load_site<P>(A0, V, nr, s, r, v);
             red[0] += n2(v);
         } else if constexpr (OP == B_CG_RESTART) {  // p = z
             cx<T> v[12];
-            load_site<P>(p.a0, V, nr, s, r, v);
-            store_site<P>(p.y0, V, nr, s, r, v);
+            load_site<P>(A0, V, nr, s, r, v);
+            store_site<P>(Y0, V, nr, s, r, v);
         } else if constexpr (OP == B_DOT_NORM) {
             cx<T> a[12], b[12];
-            load_site<P>(p.a0, V, nr, s, r, a);
-            load_site<P>(p.a1, V, nr, s, r, b);
+            load_site<P>(A0, V, nr, s, r, a);
+            load_site<P>(A1, V, nr, s, r, b);
             dot(a, b, red[0], red[1]);
             red[2] += n2(b);
         }
@@ -299,12 +315,13 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int k = 0; k < NV; ++k)
-                p.partials[((size_t)k * nr + r) * p.nblk + blockIdx.x] = red[k];
+                p.partials[((size_t)k * gridDim.y + col) * p.nblk + blockIdx.x] = red[k];
         }
     }
 }
 
 int blas_nval(int op) { return blas_nv(op); }
+int blas_sites_per_thread(int op) { return blas_spt(op); }
 
 template <int P>
 static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hipStream_t st)
@@ -418,12 +435,12 @@ __device__ __forceinline__ RowRef fin_row(const FinParams &p, int c)
 {
     const int na = p.nvalA * p.nrhs, nb = p.nvalB * p.nrhs;
     if (c < na)
-        return RowRef{p.A + (size_t)c * p.nblkA, p.nblkA};
+        return RowRef{p.A + (size_t)c * p.nblkA, p.lenA ? p.lenA[c % p.nrhs] : p.nblkA};
     c -= na;
     if (c < nb)
-        return RowRef{p.B + (size_t)c * p.nblkB, p.nblkB};
+        return RowRef{p.B + (size_t)c * p.nblkB, p.lenB ? p.lenB[c % p.nrhs] : p.nblkB};
     c -= nb;
-    return RowRef{p.C + (size_t)c * p.nblkC, p.nblkC};
+    return RowRef{p.C + (size_t)c * p.nblkC, p.lenC ? p.lenC[c % p.nrhs] : p.nblkC};
 }
 
 __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinParams p, int op)

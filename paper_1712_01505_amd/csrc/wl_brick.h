@@ -205,7 +205,8 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
             RawHop<P> rb;
             raw_load<P>(p, sb, sb, 3, rhs, rb);
             hop_g<P, 3, -SF, 1>(rb, Cg, one);
-            Cs = (t0 == 0 && anti_t) ? R_(-1) : R_(1);
+            // (enforced halo: the wrapping hop into t = 0 comes from the face buffer)
+            Cs = (t0 == 0 && p.halo_t) ? R_(0) : (t0 == 0 && anti_t) ? R_(-1) : R_(1);
             if constexpr (Traits<P>::SCALED)
                 Cs *= rb.sc;
         }
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
                     r.lk[q] = rf.lk[q];
                 cx<R_> gg[6];
                 hop_g<P, 3, SF, 0>(r, gg, one);
-                R_ gf = (wf && anti_t) ? R_(-1) : R_(1);
+                R_ gf = (wf && p.halo_t) ? R_(0) : (wf && anti_t) ? R_(-1) : R_(1);
                 if constexpr (Traits<P>::SCALED)
                     gf *= nxt.sc;
                 accum<3, SF>(acc, gg, gf);
@@ -438,7 +439,7 @@ template <int P, int DAG>
 inline hipError_t launch_brick(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
 {
     BrickGeom g{};
-    if (!brick_setup(p.L, P, cfg.bx, cfg.by, cfg.bz, cfg.tsteps, g) || cfg.block != g.NB || p.halo_t)
+    if (!brick_setup(p.L, P, cfg.bx, cfg.by, cfg.bz, cfg.tsteps, g) || cfg.block != g.NB)
         return hipErrorInvalidValue;
     const uint32_t units = g.nbrick * (uint32_t)(p.L[3] / g.T);
     set_groups(p, units, (uint32_t)p.nrhs);

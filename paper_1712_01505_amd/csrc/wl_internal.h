@@ -102,6 +102,10 @@ struct StencilParams {
     int halo_t;
     void *halo_send;             // [face 2][rhs][6 complex][Vs], real = double (FP64) or float
     const void *halo_recv;       // same layout, filled by the face copy
+    // multi-lattice solves (multi_item): this lattice's columns start at
+    // pcol0 of pncol; partials [nval][pncol][pstride] indexed by site tile,
+    // and skip[] is indexed by the same global column
+    int pcol0, pncol, pstride;
 };
 
 // ---- even-odd (wl_eo.hip)
@@ -223,7 +227,18 @@ enum BlasOp {
     B_SR_XR = 14      // BiCGStab: s = r - alpha v ; x += alpha p + omega s ; r = s - omega (u - alpha q) ;
                       // |r|^2  (y0 = x, y1 = r, a0 = p, a1 = v, a2 = u, a3 = q)
 };
+// One column of a segmented (multi-lattice) vector: its lattice's fields
+// start `off` bytes into every vector buffer, with V sites and nrhs columns,
+// of which this is column r.
+struct Seg {
+    uint64_t off;
+    uint32_t V;
+    int nrhs;
+    int r;
+    int pad;
+};
 struct BlasParams {
+    const Seg *seg;    // segmented vectors: per-column table (blockIdx.y = global column), or null
     void *y0;          // first output / in-out vector
     void *y1;          // second output / in-out vector
     void *y2;          // third in-out vector (B_BI_XRP, B_CG1: p)
@@ -239,6 +254,7 @@ struct BlasParams {
 hipError_t launch_blas(int prec, int op, const BlasParams &p, int block, hipStream_t st);
 int blas_partials(uint32_t V, int op, int block);  // workgroups (= partial sums per RHS) of one launch
 int blas_nval(int op);
+int blas_sites_per_thread(int op);
 
 // x64 += s[rhs] * e (e in precision pin); s read from device with stride.
 hipError_t launch_accum(int pin, uint32_t V, int nrhs, void *x64, const void *e, const double *s, int sstride,
@@ -278,6 +294,8 @@ struct FinParams {
     double tol2;
     const double *tol2v;  // optional per-column tol2 for the F_INIT_* ops (overrides tol2)
     int group;            // columns per linear system (domain wall: ns); sums are taken per group
+    // segmented vectors: rows of column c hold lenX[c] partials (stride nblkX)
+    const int *lenA, *lenB, *lenC;
 };
 hipError_t launch_finalize(int op, const FinParams &p, hipStream_t st);
 hipError_t launch_scalars_init(Scalars *sc, int nrhs, double tol2, hipStream_t st);

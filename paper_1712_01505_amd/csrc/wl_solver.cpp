@@ -145,6 +145,66 @@ struct HostLease {
     }
 };
 
+// Several lattices solved together (one column per (lattice, right-hand
+// side)): the operators, the columns per lattice and the shape of the
+// multi-lattice stencil launch (one site per thread).
+struct MultiSpec {
+    std::vector<const wl_op *> hi, lo;
+    int nrhs = 1;
+    LaunchCfg cfg, cfg_lo;  // the hi and lo operators' stencil shapes
+};
+constexpr int MAX_TABLES = 10;  // multi-lattice stencil call sites of one engine
+
+// Stencil parameters of one operator (as the single-operator launch sets
+// them up), for the multi-lattice descriptor tables.
+StencilParams op_params(const wl_op *op, void *out, const void *in, int nrhs)
+{
+    StencilParams p{};
+    p.U = op->U;
+    p.in = in;
+    p.out = out;
+    for (int i = 0; i < 4; ++i) {
+        p.L[i] = op->g.dims[i];
+        p.bc[i] = op->g.bc[i];
+    }
+    p.fx = make_fastdiv((uint32_t)p.L[0]);
+    p.fy = make_fastdiv((uint32_t)p.L[1]);
+    p.fz = make_fastdiv((uint32_t)p.L[2]);
+    p.V = op->V;
+    p.nrhs = nrhs;
+    p.kappa = op->kappa;
+    p.apply = 1;
+    p.one = 1.0f;
+    return p;
+}
+
+// Bytes of one segmented vector (every lattice's field, 256-byte aligned).
+size_t seg_vec_bytes(const std::vector<const wl_op *> &ops, int prec, int nrhs)
+{
+    size_t n = 0;
+    for (const wl_op *o : ops)
+        n += align_up(vec_bytes(prec, o->V, nrhs));
+    return n;
+}
+// Partials per column of a multi-lattice engine: the BLAS kernels' (256
+// sites per workgroup) or the stencil's site tiles (at least 64 sites).
+int seg_stride(const std::vector<const wl_op *> &ops, int block)
+{
+    uint32_t vmax = 0;
+    for (const wl_op *o : ops)
+        vmax = std::max(vmax, o->V);
+    return std::max(blas_partials(vmax, B_NORM, BLAS_BLOCK), (int)((vmax + block - 1) / block));
+}
+size_t multi_engine_bytes(int solver, int prec, const std::vector<const wl_op *> &ops, int nrhs)
+{
+    const int nvec = solver == WL_SOLVER_CGNR ? 5 : 6;
+    const int ncol = (int)ops.size() * nrhs;
+    return nvec * seg_vec_bytes(ops, prec, nrhs) +
+           3 * align_up((size_t)RED_NVAL_MAX * ncol * seg_stride(ops, 64) * sizeof(double)) +
+           align_up(sizeof(Scalars) * ncol) + align_up(sizeof(double) * 3 * ncol) + align_up(sizeof(Seg) * ncol) +
+           align_up(sizeof(int) * 3 * ncol) + align_up(sizeof(MultiEntry) * MAX_TABLES * ops.size()) + 8 * ALIGN;
+}
+
 // A Krylov solver instance on one operator (one precision), nrhs columns.
 struct Engine {
     const wl_op *op;
@@ -175,6 +235,146 @@ struct Engine {
     // leaves p alone), and the update itself.
     std::function<bool(int)> rel_decide;
     std::function<int(int)> rel_act;
+
+    // ---- multi-lattice mode (init_multi): vectors are segmented, one
+    // segment per lattice; nrhs counts all columns, lat_nrhs those of a lattice
+    struct Lat {
+        const wl_op *op;
+        uint32_t V;
+        size_t off;
+        int tiles;  // stencil site tiles
+    };
+    std::vector<Lat> lats;
+    int lat_nrhs = 0;
+    size_t seg_bytes = 0;
+    LaunchCfg mcfg;
+    int mstride = 0;             // partials per column
+    Seg *dseg = nullptr;         // device [nrhs]
+    int *dlen = nullptr;         // device [3][nrhs]: partial rows of BLAS, BLAS with 4 sites/thread, stencil
+    MultiEntry *dtab = nullptr;  // device [MAX_TABLES][lattices]
+    std::vector<Seg> hseg;
+    std::vector<int> hlen;
+    struct Table {
+        const void *out, *in, *aux, *aux2, *aux3;
+        int dagger, red, slot;
+        bool loop;
+        uint32_t total;
+        std::vector<MultiEntry> host;
+    };
+    std::vector<Table> tables;
+    const int *lenp[3] = {nullptr, nullptr, nullptr};  // row lengths of each partial set's producer
+
+    int init_multi(Arena &a, const std::vector<const wl_op *> &ops, int solv, int nl, hipStream_t s, HostBufs *h,
+                   const LaunchCfg &mc)
+    {
+        op = ops[0];
+        solver = solv;
+        lat_nrhs = nl;
+        nrhs = (int)ops.size() * nl;
+        prec = op->prec;
+        group = 1;
+        eo = false;
+        st = s;
+        hb = h;
+        sc_host = h->sc;
+        mcfg = mc;
+        size_t off = 0;
+        uint32_t vmax = 0;
+        for (const wl_op *o : ops) {
+            lats.push_back(Lat{o, o->V, off, (int)((o->V + mc.block - 1) / mc.block)});
+            off += align_up(vec_bytes(prec, o->V, nl));
+            vmax = std::max(vmax, o->V);
+        }
+        seg_bytes = off;
+        V = vmax;
+        mstride = seg_stride(ops, mc.block);
+        const int nvec = solver == WL_SOLVER_CGNR ? 5 : 6;
+        for (int i = 0; i < nvec; ++i)
+            if (!(v[i] = a.take(seg_bytes)))
+                return WL_EWORKSPACE;
+        for (int i = 0; i < 3; ++i)
+            if (!(part[i] = (double *)a.take((size_t)RED_NVAL_MAX * nrhs * mstride * sizeof(double))))
+                return WL_EWORKSPACE;
+        if (!(sc = (Scalars *)a.take(sizeof(Scalars) * nrhs)) || !(sums = (double *)a.take(sizeof(double) * 3 * nrhs)))
+            return WL_EWORKSPACE;
+        if (!(dseg = (Seg *)a.take(sizeof(Seg) * nrhs)) || !(dlen = (int *)a.take(sizeof(int) * 3 * nrhs)) ||
+            !(dtab = (MultiEntry *)a.take(sizeof(MultiEntry) * MAX_TABLES * lats.size())))
+            return WL_EWORKSPACE;
+        hseg.resize(nrhs);
+        hlen.resize(3 * nrhs);
+        for (size_t i = 0; i < lats.size(); ++i)
+            for (int r = 0; r < nl; ++r) {
+                const int c = (int)i * nl + r;
+                hseg[c] = Seg{lats[i].off, lats[i].V, nl, r, 0};
+                hlen[c] = blas_partials(lats[i].V, B_NORM, BLAS_BLOCK);
+                hlen[nrhs + c] = blas_partials(lats[i].V, B_SR_PV, BLAS_BLOCK);
+                hlen[2 * nrhs + c] = lats[i].tiles;
+            }
+        WL_TRY(hipMemcpyAsync(dseg, hseg.data(), sizeof(Seg) * nrhs, hipMemcpyHostToDevice, st));
+        WL_TRY(hipMemcpyAsync(dlen, hlen.data(), sizeof(int) * 3 * nrhs, hipMemcpyHostToDevice, st));
+        kernels += 2;
+        return WL_OK;
+    }
+
+    // One multi-lattice launch: every lattice's segment of out = D in (with
+    // the fused reduction into the segmented partials); the descriptor table
+    // of each call site is built and uploaded once.
+    int stencil_multi(void *out, const void *in, int dagger, int red, const void *aux, int slot, bool loop,
+                      const void *aux2, const void *aux3)
+    {
+        const int n = (int)lats.size();
+        int idx = -1;
+        for (size_t i = 0; i < tables.size() && idx < 0; ++i) {
+            const Table &t = tables[i];
+            if (t.out == out && t.in == in && t.aux == aux && t.aux2 == aux2 && t.aux3 == aux3 && t.dagger == dagger &&
+                t.red == red && t.slot == slot && t.loop == loop)
+                idx = (int)i;
+        }
+        if (idx < 0) {
+            if ((int)tables.size() >= MAX_TABLES)
+                return WL_EWORKSPACE;
+            Table t{out, in, aux, aux2, aux3, dagger, red, slot, loop, 0, std::vector<MultiEntry>(n)};
+            uint64_t total = 0;
+            auto at = [](const void *q, size_t off) { return q ? (const char *)q + off : nullptr; };
+            for (int i = 0; i < n; ++i) {
+                const Lat &L = lats[i];
+                StencilParams p = op_params(L.op, (char *)out + L.off, at(in, L.off), lat_nrhs);
+                p.red = red;
+                p.aux = at(aux, L.off);
+                p.aux2 = at(aux2, L.off);
+                p.aux3 = at(aux3, L.off);
+                p.partials = slot >= 0 ? part[slot] : nullptr;
+                p.skip = loop ? sc : nullptr;
+                p.pcol0 = i * lat_nrhs;
+                p.pncol = nrhs;
+                p.pstride = mstride;
+                p.nblk = L.tiles;
+                p.ng = (uint32_t)lat_nrhs;
+                p.f_ng = make_fastdiv((uint32_t)lat_nrhs);
+                t.host[i].p = p;
+                t.host[i].tile_begin = (uint32_t)total;
+                total += (uint64_t)L.tiles * lat_nrhs;
+            }
+            if (total > 0x7fffffffull)
+                return WL_EINVAL;
+            t.total = (uint32_t)total;
+            idx = (int)tables.size();
+            WL_TRY(hipMemcpyAsync(dtab + (size_t)idx * n, t.host.data(), sizeof(MultiEntry) * n, hipMemcpyHostToDevice,
+                                  st));
+            ++kernels;
+            tables.push_back(std::move(t));
+        }
+        if (slot >= 0) {
+            nblk[slot] = mstride;
+            nval[slot] = red_nval(red);
+            lenp[slot] = dlen + 2 * nrhs;
+        }
+        ++stencil_calls;
+        ++kernels;
+        WL_TRY(launch_multi(prec, dagger, 1, mcfg.block, mcfg.var, dtab + (size_t)idx * n, n, tables[idx].total,
+                            nullptr, 0, st));
+        return WL_OK;
+    }
 
     int init(Arena &a, const wl_op *o, int solv, int n, hipStream_t s, HostBufs *h, bool even_odd = false)
     {
@@ -207,6 +407,8 @@ struct Engine {
     int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot, bool loop = false,
                 const void *aux2 = nullptr, const void *aux3 = nullptr)
     {
+        if (!lats.empty())
+            return stencil_multi(out, in, dagger ^ adj, red, aux, slot, loop, aux2, aux3);
         if (eo) {  // out = (1 - kappa^2 H_eo H_oe) in on even half fields
             EoParams a = eo_params(op, 1, nrhs);
             a.in = in;
@@ -284,9 +486,11 @@ struct Engine {
         p.partials = slot >= 0 ? part[slot] : nullptr;
         p.V = V;
         p.nrhs = nrhs;
+        p.seg = lats.empty() ? nullptr : dseg;
         if (slot >= 0) {
             nblk[slot] = blas_partials(V, bop, BLAS_BLOCK);
             nval[slot] = blas_nval(bop);
+            lenp[slot] = lats.empty() ? nullptr : dlen + (blas_sites_per_thread(bop) > 1 ? nrhs : 0);
         }
         ++kernels;
         WL_TRY(launch_blas(prec, bop, p, BLAS_BLOCK, st));
@@ -301,16 +505,19 @@ struct Engine {
             p.A = part[a];
             p.nblkA = nblk[a];
             p.nvalA = nval[a];
+            p.lenA = lenp[a];
         }
         if (b >= 0) {
             p.B = part[b];
             p.nblkB = nblk[b];
             p.nvalB = nval[b];
+            p.lenB = lenp[b];
         }
         if (c >= 0) {
             p.C = part[c];
             p.nblkC = nblk[c];
             p.nvalC = nval[c];
+            p.lenC = lenp[c];
         }
         p.sc = sc;
         p.out = out ? out : sums;
@@ -594,13 +801,15 @@ int status_of(const wl_solve_stats &s, int flag)
 
 // Plain solve in the op's own precision.
 int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, const wl_solve_params *prm,
-                wl_solve_stats *stats, hipStream_t st, Arena &arena, bool eo = false, const double *tolc = nullptr)
+                wl_solve_stats *stats, hipStream_t st, Arena &arena, bool eo = false, const double *tolc = nullptr,
+                const MultiSpec *ms = nullptr)
 {
     HostLease lease;
     if (!lease.b->ok)
         return WL_EHIP;
     Engine E{};
-    int rc = E.init(arena, op, solver, nrhs, st, lease.b, eo);
+    int rc = ms ? E.init_multi(arena, ms->hi, solver, ms->nrhs, st, lease.b, ms->cfg)
+                : E.init(arena, op, solver, nrhs, st, lease.b, eo);
     if (rc)
         return rc;
     // per-column tolerance (even-odd: scaled to the Schur right-hand side)
@@ -687,7 +896,7 @@ int solve_plain(int solver, const wl_op *op, void *x, const void *b, int nrhs, c
 //    confirms it with a last FP64 residual.
 int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *b, int nrhs,
                 const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st, Arena &arena, bool eo = false,
-                const double *tolc = nullptr)
+                const double *tolc = nullptr, const MultiSpec *ms = nullptr)
 {
     HostLease lease;
     if (!lease.b->ok)
@@ -695,16 +904,19 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     Engine H{}, L{};
     int rc;
     // the outer engine only needs r, w and the partial/scalar buffers; it is
-    // initialised as a CGNR engine (4 vectors) for simplicity of layout
-    if ((rc = H.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, lease.b, eo)))
+    // initialised as a CGNR engine for simplicity of layout
+    if ((rc = ms ? H.init_multi(arena, ms->hi, WL_SOLVER_CGNR, ms->nrhs, st, lease.b, ms->cfg)
+                 : H.init(arena, hi, WL_SOLVER_CGNR, nrhs, st, lease.b, eo)))
         return rc;
-    if ((rc = L.init(arena, lo, solver, nrhs, st, lease.b, eo)))
+    if ((rc = ms ? L.init_multi(arena, ms->lo, solver, ms->nrhs, st, lease.b, ms->cfg_lo)
+                 : L.init(arena, lo, solver, nrhs, st, lease.b, eo)))
         return rc;
     H.adj = L.adj = prm->dagger;
     L.form = prm->form;
     int direct = 0;  // accumulate / convert launches issued here
-    void *r_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
-    void *e_lo = arena.take(vec_bytes(lo->prec, L.V, nrhs));
+    const size_t lo_bytes = ms ? L.seg_bytes : vec_bytes(lo->prec, L.V, nrhs);
+    void *r_lo = arena.take(lo_bytes);
+    void *e_lo = arena.take(lo_bytes);
     if (!r_lo || !e_lo)
         return WL_EWORKSPACE;
     H.lookahead = L.lookahead = lookahead_of(prm);
@@ -713,6 +925,36 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
     // (the stream idle after each true-residual check) and read by the kernels
     // through the device view of that host memory
     double *sig_dev = lease.b->dev(sig), *tol2_dev = lease.b->dev(t2);
+    // x64 += sigma e  and  r_lo = r64 / sigma, one launch per lattice segment
+    // in a multi-lattice solve
+    auto accum = [&]() -> hipError_t {
+        if (!ms) {
+            ++direct;
+            return launch_accum(lo->prec, H.V, nrhs, x, e_lo, sig_dev, 1, st);
+        }
+        for (size_t i = 0; i < H.lats.size(); ++i) {
+            ++direct;
+            const hipError_t e = launch_accum(lo->prec, H.lats[i].V, ms->nrhs, (char *)x + H.lats[i].off,
+                                              (char *)e_lo + L.lats[i].off, sig_dev + i * ms->nrhs, 1, st);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    };
+    auto convert = [&](const void *r64, void *rlo) -> hipError_t {
+        if (!ms) {
+            ++direct;
+            return launch_convert(WL_F64, lo->prec, H.V, nrhs, r64, rlo, sig_dev, 1, 2, st);
+        }
+        for (size_t i = 0; i < H.lats.size(); ++i) {
+            ++direct;
+            const hipError_t e = launch_convert(WL_F64, lo->prec, H.lats[i].V, ms->nrhs, (const char *)r64 + H.lats[i].off,
+                                                (char *)rlo + L.lats[i].off, sig_dev + i * ms->nrhs, 1, 2, st);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    };
     if ((rc = H.norm2(b, bb)))
         return rc;
     if (!prm->use_x0)
@@ -768,15 +1010,14 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
             last_update = it;
             int e;
             // x64 += sigma e ; e = 0 ; r64 = b - D64 x ; r_lo = r64 / sigma
-            WL_TRY(launch_accum(lo->prec, H.V, nrhs, x, e_lo, sig_dev, 1, st));
-            direct += 2;  // with the conversion below
+            WL_TRY(accum());
             if ((e = L.blas(B_ZERO, e_lo, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return e;
             if ((e = H.stencil(H.v[1], x, 0, RED_NONE, nullptr, -1)))
                 return e;
             if ((e = H.blas(B_RES, H.v[0], nullptr, b, H.v[1], nullptr, nullptr, 0)))
                 return e;
-            WL_TRY(launch_convert(WL_F64, lo->prec, H.V, nrhs, H.v[0], L.v[0], sig_dev, 1, 2, st));
+            WL_TRY(convert(H.v[0], L.v[0]));
             if (solver == WL_SOLVER_BICGSTAB) {
                 // rho = <rh, r>, |r|^2 of the replaced residual, then beta
                 if ((e = L.blas(B_DOT_NORM, nullptr, nullptr, L.v[1], L.v[0], nullptr, nullptr, 0)))
@@ -836,8 +1077,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         if (all_ok || stagnated || outer >= max_outer || total >= prm->maxiter)
             break;
         // r_lo = r64 / sigma (0 for converged columns)
-        WL_TRY(launch_convert(WL_F64, lo->prec, H.V, nrhs, H.v[0], r_lo, sig_dev, 1, 2, st));
-        ++direct;
+        WL_TRY(convert(H.v[0], r_lo));
         int done = 0;
         next_read = 0;
         last_update = 0;
@@ -857,8 +1097,7 @@ int solve_mixed(int solver, const wl_op *hi, const wl_op *lo, void *x, const voi
         }
         total += done;
         // x64 += sigma e
-        WL_TRY(launch_accum(lo->prec, H.V, nrhs, x, e_lo, sig_dev, 1, st));
-        ++direct;
+        WL_TRY(accum());
         ++outer;
     }
     int worst = WL_OK;
@@ -996,7 +1235,87 @@ int solve_eo(int solver, const wl_op *hi, const wl_op *lo, void *x, const void *
     return worst;
 }
 
+size_t multi_bytes(const MultiSpec &ms, int solver)
+{
+    const int ph = ms.hi[0]->prec;
+    size_t n = 2 * seg_vec_bytes(ms.hi, ph, ms.nrhs) + 16 * ALIGN;  // the segmented x and b
+    if (ms.lo.empty())
+        return n + multi_engine_bytes(solver, ph, ms.hi, ms.nrhs);
+    const int pl = ms.lo[0]->prec;
+    return n + multi_engine_bytes(WL_SOLVER_CGNR, ph, ms.hi, ms.nrhs) + multi_engine_bytes(solver, pl, ms.lo, ms.nrhs) +
+           2 * seg_vec_bytes(ms.lo, pl, ms.nrhs);
+}
+
 }  // namespace
+
+size_t multi_solver_workspace_bytes(const std::vector<const wl_op *> &hi, const std::vector<const wl_op *> &lo,
+                                    int solver, int nrhs)
+{
+    MultiSpec ms;
+    ms.hi = hi;
+    ms.lo = lo;
+    ms.nrhs = nrhs;
+    return multi_bytes(ms, solver);
+}
+
+// Several lattices, nrhs right-hand sides each, solved together: every
+// stencil application of the iteration is one multi-lattice launch (one
+// descriptor table per call site), every vector update one segmented BLAS
+// launch and every reduction one finalize over all columns; each column keeps
+// its own scalars and stops on its own.  The right-hand sides are gathered
+// into segmented buffers in the workspace and the solutions scattered back.
+int solve_multi(int solver, const std::vector<const wl_op *> &hi, const std::vector<const wl_op *> &lo,
+                void *const *x, const void *const *b, int nrhs, const LaunchCfg &cfg, const LaunchCfg &cfg_lo,
+                const wl_solve_params *prm, wl_solve_stats *stats, hipStream_t st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    MultiSpec ms;
+    ms.hi = hi;
+    ms.lo = lo;
+    ms.nrhs = nrhs;
+    ms.cfg = cfg;
+    ms.cfg_lo = cfg_lo;
+    const size_t need = multi_bytes(ms, solver);
+    if (!prm->workspace || prm->workspace_bytes < need)
+        return WL_EWORKSPACE;
+    Arena arena{(char *)prm->workspace, prm->workspace_bytes};
+    const size_t mis = (uintptr_t)arena.base % ALIGN;
+    if (mis)
+        arena.off = ALIGN - mis;
+    wl_solve_params q = *prm;
+    q.tol = prm->tol * (1.0 - 1e-4);  // as for a single lattice
+    const int ph = hi[0]->prec;
+    const size_t sb = seg_vec_bytes(hi, ph, nrhs);
+    char *xs = (char *)arena.take(sb), *bs = (char *)arena.take(sb);
+    if (!xs || !bs)
+        return WL_EWORKSPACE;
+    const int n = (int)hi.size(), ncols = n * nrhs;
+    std::vector<size_t> off(n);
+    size_t o = 0;
+    for (int i = 0; i < n; ++i) {
+        off[i] = o;
+        const size_t bytes = vec_bytes(ph, hi[i]->V, nrhs);
+        WL_TRY(hipMemcpyAsync(bs + o, b[i], bytes, hipMemcpyDeviceToDevice, st));
+        if (prm->use_x0)
+            WL_TRY(hipMemcpyAsync(xs + o, x[i], bytes, hipMemcpyDeviceToDevice, st));
+        o += align_up(bytes);
+    }
+    std::vector<wl_solve_stats> cst(ncols);
+    int rc = lo.empty() ? solve_plain(solver, hi[0], xs, bs, ncols, &q, cst.data(), st, arena, false, nullptr, &ms)
+                        : solve_mixed(solver, hi[0], lo[0], xs, bs, ncols, &q, cst.data(), st, arena, false, nullptr, &ms);
+    if (rc >= 0)
+        for (int i = 0; i < n; ++i)
+            WL_TRY(hipMemcpyAsync(x[i], xs + off[i], vec_bytes(ph, hi[i]->V, nrhs), hipMemcpyDeviceToDevice, st));
+    (void)hipStreamSynchronize(st);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats && rc >= 0)
+        for (int c = 0; c < ncols; ++c) {
+            stats[c] = cst[c];
+            stats[c].kernels += (prm->use_x0 ? 3 : 2) * n;  // gathers and scatters
+            stats[c].seconds = secs;
+        }
+    return rc;
+}
 
 size_t solver_workspace_bytes(const wl_op *hi, const wl_op *lo, int solver, int nrhs)
 {

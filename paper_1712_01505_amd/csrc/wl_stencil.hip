@@ -76,8 +76,6 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
         return hipErrorInvalidValue;
     if (p.apply == 2 && (cfg.rpt != 1 || cfg.var > 2 || p.ns < 1 || p.nrhs % p.ns != 0))
         return hipErrorInvalidValue;  // domain wall: one slice per thread, variants 0..2
-    if (p.halo_t && cfg.rpt == 1 && cfg.var >= 4)
-        return hipErrorInvalidValue;  // the t-walk carries its t hops in registers
     p.lanes_lg = lg;
     const int tile = cfg.block >> lg;
     p.nblk = (int)((p.V + tile - 1) / tile);

@@ -77,7 +77,8 @@ __global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint
             decode<P>(rb, ps, u);
             project<3, -SF>(ps, h, (R_)p.one);
             su3_adj_mv(u, h, g);
-            R_ gb = (t0 == 0 && anti_t) ? R_(-1) : R_(1);
+            // (enforced halo: the wrapping hop into t = 0 comes from the face buffer)
+            R_ gb = (t0 == 0 && p.halo_t) ? R_(0) : (t0 == 0 && anti_t) ? R_(-1) : R_(1);
             if constexpr (Traits<P>::SCALED)
                 gb *= rb.sc;
 #pragma unroll
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint
                 cx<R_> h[6], g[6];
                 project<3, SF>(nxt, h, (R_)p.one);
                 su3_mv(u, h, g);
-                R_ gf = (wf && anti_t) ? R_(-1) : R_(1);
+                R_ gf = (wf && p.halo_t) ? R_(0) : (wf && anti_t) ? R_(-1) : R_(1);
                 if constexpr (Traits<P>::SCALED)
                     gf *= rf.sc;
                 accum<3, SF>(acc, g, gf);
@@ -487,6 +488,13 @@ __device__ __forceinline__ void multi_item(const MultiEntry *E, int n, uint32_t 
     const uint32_t lt = fdiv(local, p.f_ng);
     const int r0 = (int)(local - lt * p.ng) * R;
     const uint32_t s = lt * blockDim.x + threadIdx.x;
+    // a multi-lattice solve (one column per thread): frozen columns are
+    // skipped, and the fused reduction (chosen at run time, uniform over the
+    // item) goes to partial [value][pcol0 + column][site tile]
+    const int red = R == 1 ? p.red : RED_NONE;
+    if (R == 1 && p.skip && p.skip[p.pcol0 + r0].frozen)
+        return;
+    double rv[RED_NVAL_MAX] = {};
     if (s < p.V) {
         cx<T> acc[R][12];
 #pragma unroll
@@ -507,6 +515,40 @@ __device__ __forceinline__ void multi_item(const MultiEntry *E, int n, uint32_t 
             for (int k = 0; k < 12; ++k)
                 o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
             store_site_q<P, true>(p.out, p.V, p.nrhs, s, r0 + r, o);
+            if constexpr (R == 1) {
+                if (red == RED_NORM) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        rv[0] = fma((double)o[k].re, (double)o[k].re, fma((double)o[k].im, (double)o[k].im, rv[0]));
+                } else if (red == RED_DOTV) {
+                    cx<T> v[12];
+                    load_site<P>(p.aux, p.V, p.nrhs, s, r0, v);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        rv[0] = fma((double)v[k].re, (double)o[k].re, fma((double)v[k].im, (double)o[k].im, rv[0]));
+                        rv[1] = fma((double)v[k].re, (double)o[k].im, fma(-(double)v[k].im, (double)o[k].re, rv[1]));
+                    }
+                } else if (red == RED_BICG) {
+                    cx<T> v[12];
+                    load_site<P>(p.aux, p.V, p.nrhs, s, r0, v);
+                    bicg_values(in, o, v, rv);
+                } else if (red == RED_SR) {
+                    cx<T> a[12], b[12], c[12];
+                    load_site<P>(p.aux, p.V, p.nrhs, s, r0, a);
+                    load_site<P>(p.aux2, p.V, p.nrhs, s, r0, b);
+                    load_site<P>(p.aux3, p.V, p.nrhs, s, r0, c);
+                    sr_values(in, o, a, b, c, rv);
+                }
+            }
+        }
+    }
+    if (red != RED_NONE) {  // uniform: every thread of the workgroup takes part
+        __shared__ double lds_mr[RED_NVAL_MAX * 8];
+        block_sum<RED_NVAL_MAX>(rv, lds_mr);
+        if (threadIdx.x == 0) {
+            const int nv = red_nval(red);
+            for (int k = 0; k < nv; ++k)
+                p.partials[((size_t)k * p.pncol + p.pcol0 + r0) * p.pstride + lt] = rv[k];
         }
     }
 }

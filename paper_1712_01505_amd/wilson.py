@@ -39,6 +39,7 @@ EXPORTS = [
     "wl_multi_plan_tune", "wl_multi_plan_get_launch", "wl_multi_plan_set_launch", "wl_multi_plan_destroy",
     "wl_dw_op_create", "dwf_apply", "wl_halo_bytes", "wilson_apply_halo", "wl_eo_split", "wl_eo_merge",
     "wilson_schur_apply", "wl_apply_dot_workspace_bytes", "wilson_apply_dot", "wilson_apply_dot_noalloc",
+    "wl_multi_solver_workspace_bytes", "wilson_solve_multi",
 ]
 
 
@@ -70,6 +71,10 @@ class wl_launch(ctypes.Structure):
 
 class wl_multi_desc(ctypes.Structure):
     _fields_ = [("op", ctypes.c_void_p), ("out", ctypes.c_void_p), ("in_", ctypes.c_void_p)]
+
+
+class wl_multi_system(ctypes.Structure):
+    _fields_ = [("hi", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("x", ctypes.c_void_p), ("b", ctypes.c_void_p)]
 
 
 class WilsonError(RuntimeError):
@@ -137,6 +142,9 @@ def lib():
         "wl_apply_dot_workspace_bytes": [P, I, ctypes.POINTER(SZ)],
         "wilson_apply_dot": [P, P, P, P, I, I, I, P, P, SZ, P],
         "wilson_apply_dot_noalloc": [P, P, P, P, I, I, I, P, P],
+        "wl_multi_solver_workspace_bytes": [ctypes.POINTER(wl_multi_system), I, I, I, ctypes.POINTER(SZ)],
+        "wilson_solve_multi": [ctypes.POINTER(wl_multi_system), I, I, I, ctypes.POINTER(wl_solve_params),
+                               ctypes.POINTER(wl_solve_stats), P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -697,3 +705,30 @@ def solve(U, b, kappa, method="bicgstab", precision="f64", tol=1e-10, maxiter=10
     if return_stats:
         return x, (st[0] if nrhs is None else st)
     return x
+
+
+def solve_multi(systems, nrhs=1, method="bicgstab", tol=1e-10, maxiter=10000, inner_tol=0.0, reliable=False,
+                form=0, return_stats=False):
+    """Several lattices solved together (wilson_solve_multi).  systems: list
+    of (hi Operator, lo Operator or None, b packed in hi's precision with nrhs
+    columns); returns the packed solutions (and the per-column stats, column
+    i * nrhs + r)."""
+    torch = _torch()
+    n = len(systems)
+    xs = [hi.new_field(nrhs) for hi, _, _ in systems]
+    arr = (wl_multi_system * n)(*[wl_multi_system(hi.handle, lo.handle if lo is not None else None, _ptr(x), _ptr(b))
+                                  for (hi, lo, b), x in zip(systems, xs)])
+    ws = ctypes.c_size_t(0)
+    _check(lib().wl_multi_solver_workspace_bytes(arr, n, SOLVER[method], nrhs, ctypes.byref(ws)),
+           "wl_multi_solver_workspace_bytes")
+    work = torch.empty(ws.value, dtype=torch.uint8, device=systems[0][2].device)
+    prm = wl_solve_params(tol=tol, maxiter=maxiter, inner_tol=inner_tol, max_outer=0, reliable=int(reliable),
+                          check_every=0, use_x0=0, dagger=0, workspace=work.data_ptr(), workspace_bytes=ws.value,
+                          eo=0, form=int(form))
+    stats = (wl_solve_stats * (n * nrhs))()
+    code = lib().wilson_solve_multi(arr, n, SOLVER[method], nrhs, ctypes.byref(prm), stats, _stream())
+    _check(code, "wilson_solve_multi", allow_positive=True)
+    st = [s_.as_dict() for s_ in stats]
+    for s_ in st:
+        s_["status"] = code
+    return (xs, st) if return_stats else xs

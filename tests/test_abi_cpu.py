@@ -266,3 +266,41 @@ def test_tune_cache_json_is_read(tmp_path):
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["128", "7", "(8,", "4,", "4)", "8", "2"], out.stdout
+
+
+def test_multi_solve_arguments_rejected():
+    """wilson_solve_multi / wl_multi_solver_workspace_bytes reject bad system
+    lists before touching the GPU."""
+    L = wilson.lib()
+    g1, g2 = wilson.make_geom((4, 4, 4, 4)), wilson.make_geom((6, 6, 6, 6))
+    ops = []
+    try:
+        for g, p in ((g1, wilson.WL_F64), (g2, wilson.WL_F64), (g1, wilson.WL_F32), (g2, wilson.WL_F16S)):
+            h = ctypes.c_void_p()
+            assert L.wl_op_create(ctypes.byref(g), 0.12, p, 256, ctypes.byref(h)) == wilson.WL_OK
+            ops.append(h.value)
+        f64a, f64b, f32a, f16b = ops
+        S = wilson.wl_multi_system
+        n = ctypes.c_size_t()
+        ok = (S * 2)(S(f64a, None, 512, 1024), S(f64b, None, 2048, 4096))
+        assert L.wl_multi_solver_workspace_bytes(ok, 2, 1, 4, ctypes.byref(n)) == wilson.WL_OK and n.value > 0
+        assert L.wl_multi_solver_workspace_bytes(ok, 0, 1, 4, ctypes.byref(n)) == wilson.WL_EINVAL
+        assert L.wl_multi_solver_workspace_bytes(ok, 2, 1, 33, ctypes.byref(n)) == wilson.WL_EINVAL  # 66 columns
+        assert L.wl_multi_solver_workspace_bytes(ok, 2, 2, 1, ctypes.byref(n)) == wilson.WL_EINVAL  # solver id
+        mixed_plain = (S * 2)(S(f64a, f32a, 512, 1024), S(f64b, None, 2048, 4096))
+        assert L.wl_multi_solver_workspace_bytes(mixed_plain, 2, 1, 1, ctypes.byref(n)) == wilson.WL_EINVAL
+        lo_geom = (S * 1)(S(f64b, f32a, 512, 1024))  # lo on another lattice
+        assert L.wl_multi_solver_workspace_bytes(lo_geom, 1, 1, 1, ctypes.byref(n)) == wilson.WL_EINVAL
+        plain16 = (S * 1)(S(f16b, None, 512, 1024))
+        assert L.wl_multi_solver_workspace_bytes(plain16, 1, 1, 1, ctypes.byref(n)) == wilson.WL_EPREC
+        prm = wilson.wl_solve_params(tol=1e-10, maxiter=10, eo=1)
+        assert L.wilson_solve_multi(ok, 2, 1, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL  # no eo
+        prm = wilson.wl_solve_params(tol=1e-10, maxiter=10)
+        same = (S * 1)(S(f64a, None, 512, 512))
+        assert L.wilson_solve_multi(same, 1, 1, 1, ctypes.byref(prm), None, None) == wilson.WL_EINVAL  # x == b
+        odd = (S * 1)(S(f64a, None, 520, 1024))
+        assert L.wilson_solve_multi(odd, 1, 1, 1, ctypes.byref(prm), None, None) == wilson.WL_EALIGN
+        assert L.wilson_solve_multi(ok, 2, 1, 1, ctypes.byref(prm), None, None) == wilson.WL_EWORKSPACE
+    finally:
+        for h in ops:
+            L.wl_op_destroy(h)

@@ -139,3 +139,32 @@ def test_brick_fused_reductions_drive_solves(W, oracle_mod, prec, method):
                     tol=1e-10, ops=(hi, lo), return_stats=True)
     assert st["converged"], st
     assert rel(oracle_mod.apply(U, x.cpu().numpy(), kappa), b) <= 1e-10
+
+
+def test_autotune_writes_json_cache(W, tmp_path):
+    """wl_autotune keeps its choices per (arch, extents, precision, nrhs,
+    dagger, reduction) and writes them to the JSON file named by
+    $WL_TUNE_CACHE; the entries name the shapes the op then launches with."""
+    import json
+    import os
+    dims = (16, 16, 16, 32)
+    op = W.Operator.create(dev(inputs.near_unity_gauge(dims, 0.3, seed=3)), 0.12, W.WL_F32)
+    path = tmp_path / "tune.json"
+    old = os.environ.get("WL_TUNE_CACHE")
+    os.environ["WL_TUNE_CACHE"] = str(path)
+    try:
+        W.wl_autotune(op.handle, 1, 1, W._stream())
+    finally:
+        if old is None:
+            del os.environ["WL_TUNE_CACHE"]
+        else:
+            os.environ["WL_TUNE_CACHE"] = old
+    doc = json.loads(path.read_text())
+    mine = [e for e in doc["entries"] if e.get("dims") == list(dims) and e.get("prec") == W.WL_F32
+            and e.get("nrhs") == 1 and e.get("dagger") == 1]
+    assert sorted(e["reduction"] for e in mine) == [0, 1, 2, 3, 4, 5], mine
+    for e in mine:
+        assert e["key"].endswith(f":16x16x16x32:p1:n1:d1:r{e['reduction']}") and e["us"] > 0
+        assert e["arch"].startswith("gfx")
+        if e["variant"] == W.VAR_BRICK:
+            assert e["block"] == e["brick"][0] * e["brick"][1] * e["brick"][2] and e["t_steps"] > 0
