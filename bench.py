@@ -69,16 +69,18 @@ def measured_traffic(prec, dims):
     tot, n = 0.0, 0
     for k, v in d["kernels"].items():
         # the solver's stencils of this precision: stencil_kernel<prec, dagger,
-        # rhs/thread, reduction, apply, variant> or twalk_kernel<prec, dagger,
-        # reduction, apply>, with a fused reduction (the profiled run does not
-        # autotune, so these are the timed solve's launches)
+        # rhs/thread, reduction, apply, variant>, twalk_kernel<prec, dagger,
+        # reduction, apply> or brick_kernel<prec, dagger, reduction, apply>,
+        # with a fused reduction (the profiled run does not autotune, so
+        # these are the timed solve's launches)
         if k.startswith("wl::stencil_kernel<"):
             red_at = 3
         elif k.startswith("wl::twalk_kernel<") or k.startswith("wl::brick_kernel<"):
             red_at = 2
         else:
             continue
-        targs = [int(a) for a in k[k.index("<") + 1:k.index(">")].split(",")]
+        targs = [int(a) if a.strip().lstrip("-").isdigit() else int(a.strip() == "true")
+                 for a in k[k.index("<") + 1:k.index(">")].split(",")]
         if targs[0] == prec and targs[red_at] != 0:
             tot += v["hbm_bytes"] * v["dispatches"]
             n += v["dispatches"]

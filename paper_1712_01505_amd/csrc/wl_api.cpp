@@ -3,6 +3,7 @@
 // the dispatch into the kernels and solver drivers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -1194,7 +1195,7 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
         e = hipMalloc(&sums, RED_NVAL_MAX * sizeof(double) * (size_t)nrhs);
     // time one shape for one reduction kind (ms per launch, or < 0 when the
     // shape cannot be launched for lack of resources)
-    auto time_shape = [&](const LaunchCfg &c, int red) -> float {
+    auto time_shape = [&](const LaunchCfg &c, int red, int reps) -> float {
         StencilParams p = base_params(op, out, in, nrhs, 1);
         p.red = red;
         p.partials = parts;
@@ -1221,7 +1222,6 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
             e = hipSuccess;
             return -1.f;
         }
-        const int reps = 10;
         if (e == hipSuccess)
             e = hipEventRecord(a, st);
         for (int k = 0; k < reps && e == hipSuccess; ++k)
@@ -1243,13 +1243,23 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
             best_us[red] = best_us[last_red];
             continue;
         }
+        // a short timing of every candidate, then the fastest few again with
+        // four times the repetitions (the first pass's order is noisy where
+        // shapes lie within a few per cent)
+        std::vector<std::pair<float, size_t>> timed;
+        for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
+            const float ms = time_shape(cands[ci], red, 10);
+            if (ms >= 0.f)
+                timed.emplace_back(ms, ci);
+        }
+        std::sort(timed.begin(), timed.end());
         float best_ms = INFINITY;
         LaunchCfg best = default_launch(op, nrhs);
-        for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
-            const float ms = time_shape(cands[ci], red);
+        for (size_t j = 0; j < timed.size() && j < 6 && e == hipSuccess; ++j) {
+            const float ms = time_shape(cands[timed[j].second], red, 40);
             if (ms >= 0.f && ms < best_ms) {
                 best_ms = ms;
-                best = cands[ci];
+                best = cands[timed[j].second];
             }
         }
         // the best brick walk again with its occupancy capped (workgroups per
@@ -1260,7 +1270,7 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
                 c.wpe = wpe;
                 if (!launch_ok(op, nrhs, c))
                     continue;
-                const float ms = time_shape(c, red);
+                const float ms = time_shape(c, red, 40);
                 if (ms >= 0.f && ms < best_ms) {
                     best_ms = ms;
                     best = c;

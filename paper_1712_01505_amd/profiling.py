@@ -69,7 +69,7 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, out_json, co
     kw = copy_kib / cw["wl::stream_copy_kernel"]
     kernels = {}
     for k in sorted(set(f) | set(w)):
-        if k.startswith("wl::") and ("stencil" in k or "twalk" in k or "blas" in k):
+        if k.startswith("wl::") and any(n in k for n in ("stencil", "twalk", "brick", "multi", "blas")):
             fb = f.get(k, 0.0) * kf * 1024
             wb = w.get(k, 0.0) * kw * 1024
             kernels[k] = {"dispatches": nf.get(k, 0), "FETCH_SIZE_KiB": round(f.get(k, 0.0), 1),
