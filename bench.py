@@ -294,7 +294,7 @@ def bench_batching(W, inputs, torch, log, oracle=None):
 def _copy_launch(W, src_op, dst_op, nrhs=1):
     c = W.wl_get_launch(src_op.handle, nrhs)
     W.wl_set_launch(dst_op.handle, nrhs, c[0], c[1], c[2], c[3], c[4],
-                    brick=c[5:8] if c[3] == W.VAR_BRICK else None, t_steps=c[8], wg_per_cu=c[9])
+                    brick=c[5:8] if c[3] == W.VAR_BRICK else None, t_steps=c[8], wg_per_cu=c[9], rhs_major=c[10])
 
 
 def bench_multi_solve(W, inputs, torch, log, oracle, lattices, kappa):

@@ -174,7 +174,8 @@ int wilson_schur_apply(const wl_op *op, void *out_e, const void *in_e, void *tmp
  * The op borrows U_packed like wl_op_create; Ns in [1, 64].  Such an op
  * takes dwf_apply, solve_cgnr (CG on D_DW^dag D_DW, Sec. II-C and VI-B; nrhs there
  * counts 5-d vectors, nrhs * Ns <= 64), wl_autotune / wl_get_launch /
- * wl_set_launch (nrhs = 5-d vectors; one slice per thread, variants 0..2)
+ * wl_set_launch (nrhs = 5-d vectors; one slice per thread, variants 0..2
+ * and the t-walks 4..6, slices across lanes allowed)
  * and wl_op_destroy; the Wilson entry points, solve_bicgstab (its spectrum
  * reaches Re < 0), the force and multi-lattice plans reject it with
  * WL_EINVAL. */
@@ -370,10 +371,11 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
  *                 dividing nrhs, at most 2 for WL_F64 and 4 otherwise;
  * rhs_lanes       right-hand sides interleaved across the lanes of every
  *                 wavefront (1, 2, 4 or 8, dividing nrhs; > 1 needs
- *                 rhs_per_thread = 1, variant <= 3 and block / rhs_lanes
- *                 >= 64): the links of a site are fetched once per load
- *                 instruction for all of them, and a workgroup covers
- *                 block / rhs_lanes sites;
+ *                 rhs_per_thread = 1, a variant other than 7, and
+ *                 block / rhs_lanes >= 64, or >= 32 for the t-walks): the
+ *                 links of a site are fetched once per load instruction
+ *                 for all of them, and a workgroup covers
+ *                 block / rhs_lanes sites (t-walk: columns of sites);
  * xcd_remap       0 natural tile order, 1 one contiguous site range per XCD,
  *                 2..5 one z-slab per XCD, walked in y-chunks of
  *                 Ly >> (xcd_remap - 2) rows, each chunk t-major (needs
@@ -397,6 +399,13 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
  *                 workgroup reserves 1/wg_per_cu of the CU's 160 KB of LDS,
  *                 so at most that many workgroups (wg_per_cu x block / 256
  *                 waves per SIMD) share a CU; the slices must fit the share.
+ * rhs_major       with several groups of right-hand sides (nrhs larger than
+ *                 rhs_per_thread x rhs_lanes): 0 runs the groups of a site
+ *                 tile back to back on one XCD (they share its links and
+ *                 neighbours in L2 while they are resident), 1 runs one
+ *                 group after the other over the whole lattice (each group
+ *                 streams like a one-group launch and fetches the links
+ *                 again); 0 or 1.
  * Results do not depend on the configuration (16-bit t-walk and brick walk:
  * to rounding). */
 typedef struct {
@@ -408,6 +417,7 @@ typedef struct {
     int brick[3];
     int t_steps;
     int wg_per_cu;
+    int rhs_major;
 } wl_launch;
 int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg);
 /* Force a configuration (WL_EINVAL if it breaks a rule above).  Used by

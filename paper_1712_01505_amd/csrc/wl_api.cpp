@@ -228,6 +228,8 @@ static void load_tune_cache_locked()
             c.tsteps = 0;
         if (!json_int(line, "wg_per_cu", &c.wpe))
             c.wpe = 0;
+        if (!json_int(line, "rhs_major", &c.gmaj))
+            c.gmaj = 0;
         (void)json_num(line, "us", &t.us);
         // the key's fields: everything between the key and the launch shape
         const size_t fs = line.find(',', ke), fe = line.find(", \"block\":");
@@ -250,8 +252,8 @@ static void save_tune_cache_locked()
         char buf[512];
         snprintf(buf, sizeof buf,
                  "\"block\": %d, \"rhs_per_thread\": %d, \"rhs_lanes\": %d, \"xcd_remap\": %d, \"variant\": %d, "
-                 "\"brick\": [%d, %d, %d], \"t_steps\": %d, \"wg_per_cu\": %d, \"us\": %.3f",
-                 c.block, c.rpt, c.lanes, c.xcd, c.var, c.bx, c.by, c.bz, c.tsteps, c.wpe, kv.second.us);
+                 "\"brick\": [%d, %d, %d], \"t_steps\": %d, \"wg_per_cu\": %d, \"rhs_major\": %d, \"us\": %.3f",
+                 c.block, c.rpt, c.lanes, c.xcd, c.var, c.bx, c.by, c.bz, c.tsteps, c.wpe, c.gmaj, kv.second.us);
         f << "{\"key\": \"" << kv.first << "\", ";
         if (!kv.second.fields.empty())
             f << kv.second.fields << ", ";
@@ -293,10 +295,12 @@ static LaunchCfg default_launch(const wl_op *op, int nrhs)
 static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
 {
     const int prec = op->prec;
-    if (op->ns > 0 && (c.rpt != 1 || c.var > 2 || nrhs % op->ns != 0))
-        return false;  // domain wall: one slice per thread, variants 0..2
+    if (op->ns > 0 && (c.rpt != 1 || c.var == 3 || c.var > 6 || nrhs % op->ns != 0))
+        return false;  // domain wall: one slice per thread, variants 0..2 and the t-walks
+    // columns across lanes: at least 64 sites per workgroup, 32 for the t-walks
     const bool lanes_ok = c.lanes == 1 || ((c.lanes == 2 || c.lanes == 4 || c.lanes == 8) && c.rpt == 1 &&
-                                           c.var < 4 && nrhs % c.lanes == 0 && c.block / c.lanes >= 64);
+                                           c.var != VAR_BRICK && nrhs % c.lanes == 0 &&
+                                           c.block / c.lanes >= (c.var >= 4 ? 32 : 64));
     return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
            nrhs % c.rpt == 0 && lanes_ok && c.xcd >= 0 && c.xcd <= 5 &&
            (c.xcd < 2 || slab_ok(op->g.dims, c.block / c.lanes, c.xcd)) && c.var >= 0 && c.var <= max_var(prec) &&
@@ -305,7 +309,7 @@ static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
             (c.block <= 256 && op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0)) &&
            (c.var != VAR_BRICK || (op->ns == 0 && c.lanes == 1 && c.bx * c.by * c.bz == c.block &&
                                    brick_ok(op->g.dims, prec, c.bx, c.by, c.bz, c.tsteps, c.wpe))) &&
-           (c.wpe == 0 || c.var == VAR_BRICK);
+           (c.wpe == 0 || c.var == VAR_BRICK) && (c.gmaj == 0 || c.gmaj == 1);
 }
 
 // Brick shapes (variant 7) for extents L: x extent 8, 16 or 32, the rest
@@ -1111,6 +1115,7 @@ int wl_get_launch(const wl_op *op, int nrhs, wl_launch *cfg)
     cfg->brick[2] = c.bz;
     cfg->t_steps = c.tsteps;
     cfg->wg_per_cu = c.wpe;
+    cfg->rhs_major = c.gmaj;
     return WL_OK;
 }
 
@@ -1134,6 +1139,7 @@ int wl_set_launch(wl_op *op, int nrhs, const wl_launch *cfg)
     } else if (cfg->wg_per_cu != 0) {
         return WL_EINVAL;
     }
+    c.gmaj = cfg->rhs_major;
     if (!launch_ok(op, nrhs, c))
         return WL_EINVAL;
     std::lock_guard<std::mutex> lk(op->mu);
@@ -1184,6 +1190,13 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
             if (launch_ok(op, nrhs, c))
                 cands.push_back(c);
     }
+    // several right-hand-side groups: each shape also in group-major order
+    for (size_t i = 0, n0 = cands.size(); i < n0; ++i)
+        if (nrhs / (cands[i].rpt * cands[i].lanes) > 1) {
+            LaunchCfg c = cands[i];
+            c.gmaj = 1;
+            cands.push_back(c);
+        }
     // the plain apply, then each fused reduction of the solvers (partials
     // and the <v, out> operands in scratch)
     LaunchCfg bests[RED_LAST + 1];

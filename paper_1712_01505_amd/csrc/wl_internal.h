@@ -28,6 +28,9 @@ struct LaunchCfg {
     // variant 7: cap of workgroups per CU (0 = none): each workgroup reserves
     // 1/wpe of the CU's LDS, which bounds the waves per SIMD
     int wpe = 0;
+    // several right-hand-side groups: 0 = the groups of a tile back to back
+    // on one XCD, 1 = one group after the other over the whole lattice
+    int gmaj = 0;
 };
 
 }  // namespace wl
@@ -93,6 +96,8 @@ struct StencilParams {
     // to a multiple of 8 when ng > 1
     uint32_t ng, ntile;
     FastDiv f_ng;
+    int gmaj;      // 1: group-major block order (see tile_group)
+    FastDiv f_ntile;
     int lanes_lg;  // log2 of the right-hand sides interleaved across lanes
     SlabOrder slab;  // xcd >= 2
     const struct Scalars *skip;  // in a solver loop: skip a workgroup whose columns are all frozen

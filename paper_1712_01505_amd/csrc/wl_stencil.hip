@@ -60,7 +60,7 @@ int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V, int nrhs)
         n = (uint32_t)((L[0] / cfg.bx) * (L[1] / cfg.by) * (L[2] / cfg.bz)) * (uint32_t)(L[3] / cfg.tsteps);
     } else if (cfg.rpt == 1 && cfg.var >= 4) {
         const uint32_t nxyz = (uint32_t)L[0] * L[1] * L[2];
-        n = ((nxyz + cfg.block - 1) / cfg.block) * (uint32_t)(L[3] / twalk_T(cfg.var));
+        n = ((nxyz + tile - 1) / tile) * (uint32_t)(L[3] / twalk_T(cfg.var));
     }
     return (int)(nrhs / (cfg.rpt * cfg.lanes) > 1 ? pad8(n) : n);
 }
@@ -72,11 +72,15 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
     const int lg = cfg.lanes == 1 ? 0 : cfg.lanes == 2 ? 1 : cfg.lanes == 4 ? 2 : cfg.lanes == 8 ? 3 : -1;
     if (cfg.rpt < 1 || cfg.rpt > 4 || p.nrhs % cfg.rpt != 0 || cfg.block < 64 || cfg.block > 512 ||
         cfg.block % 64 != 0 || lg < 0 ||
-        (lg > 0 && (cfg.rpt != 1 || cfg.var >= 4 || p.nrhs % cfg.lanes != 0 || (cfg.block >> lg) < 64)))
+        (lg > 0 && (cfg.rpt != 1 || cfg.var == VAR_BRICK || p.nrhs % cfg.lanes != 0 ||
+                    (cfg.block >> lg) < (cfg.var >= 4 ? 32 : 64))))
         return hipErrorInvalidValue;
-    if (p.apply == 2 && (cfg.rpt != 1 || cfg.var > 2 || p.ns < 1 || p.nrhs % p.ns != 0))
-        return hipErrorInvalidValue;  // domain wall: one slice per thread, variants 0..2
+    if (p.apply == 2 && (cfg.rpt != 1 || (cfg.var > 2 && cfg.var < 4) || cfg.var > 6 || p.ns < 1 || p.nrhs % p.ns != 0))
+        return hipErrorInvalidValue;  // domain wall: one slice per thread, variants 0..2 and the t-walks
+    if (cfg.gmaj != 0 && cfg.gmaj != 1)
+        return hipErrorInvalidValue;
     p.lanes_lg = lg;
+    p.gmaj = cfg.gmaj;
     const int tile = cfg.block >> lg;
     p.nblk = (int)((p.V + tile - 1) / tile);
     p.xcd = cfg.xcd;

@@ -390,12 +390,21 @@ __device__ __forceinline__ void scale_site(cx<typename Traits<P>::real> (&v)[12]
 // spinors they share are re-read from that XCD's L2 instead of HBM.  The
 // tile keeps b's XCD (bt = b mod 8), so the per-XCD tile orders below still
 // apply; ntile is a multiple of 8 there, which makes the map a bijection.
+// Group-major order (gmaj = 1) runs one group after the other over all
+// tiles instead: each group then streams the lattice as a one-group launch
+// does (its neighbour spinors stay in L2 as there), at the price of fetching
+// the links once per group; b mod 8 = bt mod 8 again keeps the tile orders.
 __device__ __forceinline__ uint32_t tile_group(const StencilParams &p, int &g)
 {
     const uint32_t b = blockIdx.x;
     if (p.ng == 1) {
         g = 0;
         return b;
+    }
+    if (p.gmaj) {
+        const uint32_t q = fdiv(b, p.f_ntile);
+        g = (int)q;
+        return b - q * p.ntile;
     }
     const uint32_t k = b >> 3;
     const uint32_t q = fdiv(k, p.f_ng);
@@ -473,6 +482,7 @@ inline void set_groups(StencilParams &p, uint32_t tiles, uint32_t ng)
     p.ng = ng;
     p.f_ng = make_fastdiv(ng);
     p.ntile = ng > 1 ? (tiles + 7u) & ~7u : tiles;
+    p.f_ntile = make_fastdiv(p.ntile);
     p.nblk = (int)p.ntile;
 }
 

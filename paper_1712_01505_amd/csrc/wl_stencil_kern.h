@@ -16,6 +16,10 @@ namespace wl {
 // link is therefore read from memory once per column instead of three and
 // two times, and the accesses of the co-resident workgroups (the same t
 // steps of neighbouring (x, y, z) blocks) stay close in time.
+// Columns across lanes (lanes_lg = lg > 0): segment j of the 64 >> lg lanes
+// of every wavefront walks column grp 2^lg + j of the same sites, so one
+// link fetch per instruction serves 2^lg right-hand sides or domain-wall
+// slices (whose s +- 1 neighbours the slice's own wavefront loaded).
 template <int P, int DAG, int RED, int APPLY>
 // At most 256 threads per workgroup: the walk's live state (carried spinor,
 // t-term, pipelined hops) needs more than the 256 registers a 512-thread
@@ -28,14 +32,23 @@ __global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint
     constexpr int SF = DAG ? 1 : -1;  // forward hops use (1 + SF g), backward (1 - SF g)
     constexpr int G = TwalkG<P>::G;
     constexpr bool CARRY = TwalkG<P>::CARRY_SELF;
-    __shared__ double lds[(NV > 0 ? NV : 1) * 8];
-    int rhs;
-    const uint32_t bt = tile_group(p, rhs);
-    if (p.skip && p.skip[rhs].frozen)
-        return;
+    __shared__ double lds[(NV > 0 ? NV : 1) * 8 * 4];
+    int grp;
+    const uint32_t bt = tile_group(p, grp);
+    const int lg = p.lanes_lg;
+    const uint32_t lane = threadIdx.x & 63u, seg = 64u >> lg;
+    const uint32_t tsite = ((threadIdx.x >> 6) << (6 - lg)) + (lane & (seg - 1u));
+    const int rhs = (grp << lg) + (int)(lane >> (6 - lg));
+    if (p.skip) {  // solver loop: every column of this workgroup has stopped
+        bool all = true;
+        for (int r = 0; r < (1 << lg); ++r)
+            all = all && p.skip[(grp << lg) + r].frozen;
+        if (all)
+            return;
+    }
     const uint32_t unit = tile_of(bt, p.ntile, p.xcd ? 1 : 0);
     const uint32_t chunk = unit / nbxyz;
-    const uint32_t sx = (unit - chunk * nbxyz) * blockDim.x + threadIdx.x;
+    const uint32_t sx = (unit - chunk * nbxyz) * (blockDim.x >> lg) + tsite;
     double red[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < (NV > 0 ? NV : 1); ++i)
@@ -145,7 +158,9 @@ __global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint
             }
             // epilogue for site s
             cx<R_> o[12];
-            if constexpr (APPLY) {
+            if constexpr (APPLY == 2) {
+                dw_epilogue<P, DAG>(p, s, rhs, self, acc, o);
+            } else if constexpr (APPLY) {
 #pragma unroll
                 for (int i = 0; i < 12; ++i)
                     o[i] = cx<R_>{fma(-kap, acc[i].re, self[i].re), fma(-kap, acc[i].im, self[i].im)};
@@ -198,11 +213,20 @@ __global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint
         }
     }
     if constexpr (NV > 0) {
-        block_sum<NV>(red, lds);
-        if (threadIdx.x == 0) {
+        if (lg == 0) {
+            block_sum<NV>(red, lds);
+            if (threadIdx.x == 0) {
 #pragma unroll
-            for (int k = 0; k < NV; ++k)
-                p.partials[((size_t)k * p.nrhs + rhs) * p.nblk + bt] = red[k];
+                for (int k = 0; k < NV; ++k)
+                    p.partials[((size_t)k * p.nrhs + rhs) * p.nblk + bt] = red[k];
+            }
+        } else {
+            block_sum_lanes<NV>(red, lds, lg);
+            if ((int)threadIdx.x < (1 << lg)) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k)
+                    p.partials[((size_t)k * p.nrhs + (grp << lg) + threadIdx.x) * p.nblk + bt] = red[k];
+            }
         }
     }
 }
@@ -382,12 +406,21 @@ inline hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_
     if (p.L[3] % T != 0 || cfg.block > 256)
         return hipErrorInvalidValue;
     const uint32_t nxyz = (uint32_t)p.L[0] * p.L[1] * p.L[2];
-    const uint32_t nbxyz = (nxyz + cfg.block - 1) / cfg.block;
+    const uint32_t tile = (uint32_t)cfg.block >> p.lanes_lg;
+    const uint32_t nbxyz = (nxyz + tile - 1) / tile;
     const uint32_t units = nbxyz * (uint32_t)(p.L[3] / T);
-    set_groups(p, units, (uint32_t)p.nrhs);
+    set_groups(p, units, (uint32_t)p.nrhs >> p.lanes_lg);
     if ((uint64_t)p.ntile * p.ng > 0x7fffffffull)
         return hipErrorInvalidValue;
     dim3 grid(p.ntile * p.ng), block(cfg.block);
+    if (p.apply == 2) {  // domain wall: the reductions CG on the normal equations needs
+        switch (p.red) {
+        case RED_NONE: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NONE, 2>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
+        case RED_NORM: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NORM, 2>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (!p.apply) {
         if (p.red != RED_NONE)
             return hipErrorInvalidValue;

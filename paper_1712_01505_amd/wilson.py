@@ -66,7 +66,7 @@ class wl_solve_stats(ctypes.Structure):
 class wl_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("rhs_per_thread", ctypes.c_int), ("rhs_lanes", ctypes.c_int),
                 ("xcd_remap", ctypes.c_int), ("variant", ctypes.c_int), ("brick", ctypes.c_int * 3),
-                ("t_steps", ctypes.c_int), ("wg_per_cu", ctypes.c_int)]
+                ("t_steps", ctypes.c_int), ("wg_per_cu", ctypes.c_int), ("rhs_major", ctypes.c_int)]
 
 
 class wl_multi_desc(ctypes.Structure):
@@ -287,24 +287,26 @@ def wl_autotune(op, nrhs, dagger, stream):
 
 def wl_get_launch(op, nrhs):
     """(block, rhs_per_thread, xcd_remap, variant, rhs_lanes, brick_x, brick_y, brick_z, t_steps,
-    wg_per_cu) used for nrhs right-hand sides (the brick fields are 0 unless variant is 7)."""
+    wg_per_cu, rhs_major) used for nrhs right-hand sides (the brick fields are 0 unless variant
+    is 7)."""
     c = wl_launch()
     _check(lib().wl_get_launch(op, nrhs, ctypes.byref(c)), "wl_get_launch")
     return (c.block, c.rhs_per_thread, c.xcd_remap, c.variant, c.rhs_lanes, c.brick[0], c.brick[1], c.brick[2],
-            c.t_steps, c.wg_per_cu)
+            c.t_steps, c.wg_per_cu, c.rhs_major)
 
 
-def _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu=0):
+def _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu=0, rhs_major=0):
     c = wl_launch(block=block, rhs_per_thread=rpt, rhs_lanes=lanes, xcd_remap=xcd, variant=variant)
     if brick is not None:
         c.brick[0], c.brick[1], c.brick[2] = (int(b) for b in brick)
         c.t_steps = int(t_steps)
     c.wg_per_cu = int(wg_per_cu)
+    c.rhs_major = int(rhs_major)
     return c
 
 
-def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0, wg_per_cu=0):
-    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu)
+def wl_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0, wg_per_cu=0, rhs_major=0):
+    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu, rhs_major)
     return _check(lib().wl_set_launch(op, nrhs, ctypes.byref(c)), "wl_set_launch")
 
 
@@ -317,10 +319,11 @@ VAR_BRICK = 7
 MAX_VARIANT = {k: VAR_BRICK for k in VARIANTS}
 
 
-def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0, wg_per_cu=0):
+def try_set_launch(op, nrhs, block, rpt, xcd, variant=0, lanes=1, brick=None, t_steps=0, wg_per_cu=0,
+                   rhs_major=0):
     """wl_set_launch that returns False (instead of raising) for a configuration
     the library rejects."""
-    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu)
+    c = _launch(block, rpt, xcd, variant, lanes, brick, t_steps, wg_per_cu, rhs_major)
     return lib().wl_set_launch(op, nrhs, ctypes.byref(c)) == WL_OK
 MAX_RPT = {WL_F64: 2, WL_F32: 4, WL_BF16S: 4, WL_F16S: 4}
 

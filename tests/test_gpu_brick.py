@@ -91,7 +91,7 @@ def test_brick_rejects_shapes_that_do_not_tile(W):
     assert not W.try_set_launch(op.handle, 2, 128, 1, 0, W.VAR_BRICK, lanes=2, brick=(8, 4, 4), t_steps=8)
     assert W.try_set_launch(op.handle, 1, 128, 1, 0, W.VAR_BRICK, brick=(8, 4, 4), t_steps=8)
     got = W.wl_get_launch(op.handle, 1)
-    assert got[3] == W.VAR_BRICK and tuple(got[5:]) == (8, 4, 4, 8, 0)
+    assert got[3] == W.VAR_BRICK and tuple(got[5:10]) == (8, 4, 4, 8, 0)
     # an occupancy cap: the staged slices must fit the LDS share
     assert W.try_set_launch(op.handle, 1, 128, 1, 0, W.VAR_BRICK, brick=(8, 4, 4), t_steps=8, wg_per_cu=4)
     assert W.wl_get_launch(op.handle, 1)[9] == 4

@@ -36,7 +36,8 @@ def W():
 @pytest.mark.parametrize("dims,Ns", [((4, 4, 4, 8), 8), ((3, 5, 2, 7), 4), ((8, 8, 8, 8), 6)])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
 def test_dw_apply_matches_oracle(W, oracle_mod, dims, Ns, prec):
-    """Every launch shape the operator offers (variants, RHS lanes, tile orders), both D_DW and D_DW^dag."""
+    """Every launch shape the operator offers (variants, the t-walks, slices
+    across lanes, tile orders), both D_DW and D_DW^dag."""
     U = inputs.near_unity_gauge(dims, 0.3, seed=1) if dims[0] == 8 else inputs.haar_gauge(dims, seed=1)
     psi = field5(dims, Ns, 10)
     p = W.PREC[prec]
@@ -45,9 +46,9 @@ def test_dw_apply_matches_oracle(W, oracle_mod, dims, Ns, prec):
     for dagger in (False, True):
         ref = oracle_mod.dw_apply(U, psi, M0, MQ, dagger=dagger)
         n = 0
-        for var in (0, 1, 2):
+        for var in (0, 1, 2, 4, 5):
             for lanes in (1, 2, 4, 8):
-                for block, xcd in ((64, 0), (256, 1), (512, 2)):
+                for block, xcd in ((64, 0), (256, 1), (512, 2), (128, 0)):
                     if not W.try_set_launch(op.handle, 1, block, 1, xcd, var, lanes):
                         continue
                     dst = op.new_field()
@@ -67,9 +68,9 @@ def test_dw_launch_shapes_agree_bitwise(W):
         op = W.DWOperator.create(dev(U), M0, MQ, Ns, W.PREC[prec])
         src = op.pack(dev(psi))
         outs = []
-        for var in (0, 1, 2):
+        for var in (0, 1, 2, 4, 5):
             for lanes in (1, 4, 8):
-                for block, xcd in ((512, 0), (512, 2), (256, 5)):
+                for block, xcd in ((512, 0), (512, 2), (256, 5), (256, 0)):
                     if W.try_set_launch(op.handle, 1, block, 1, xcd, var, lanes):
                         dst = op.new_field()
                         op.apply_packed(dst, src)

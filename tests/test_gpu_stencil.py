@@ -134,12 +134,13 @@ def test_multi_rhs_columns_equal_single_rhs(W, prec, dims):
             for block in (64, 256, 512):
                 for xcd in (0, 1, 2, 4, 5):
                     for var in (W.VARIANTS[p] if rpt == 1 else (0,)):
-                        if not W.try_set_launch(op.handle, 12, block, rpt, xcd, var, lanes):
-                            continue
-                        dst = op.new_field(12)
-                        op.apply_packed(dst, src, 12)
-                        outs.append(op.unpack(dst, 12).cpu().numpy())
-                        cfgs.append((block, rpt, xcd, var, lanes))
+                        for gm in ((0, 1) if block == 256 else (0,)):  # group-major order
+                            if not W.try_set_launch(op.handle, 12, block, rpt, xcd, var, lanes, rhs_major=gm):
+                                continue
+                            dst = op.new_field(12)
+                            op.apply_packed(dst, src, 12)
+                            outs.append(op.unpack(dst, 12).cpu().numpy())
+                            cfgs.append((block, rpt, xcd, var, lanes, gm))
     for o, cfg in zip(outs[1:], cfgs[1:]):
         if p in (W.WL_BF16S, W.WL_F16S) and cfg[3] >= 4:
             # t-walk applies a neighbour's 16-bit scale in a different place: equal to rounding
