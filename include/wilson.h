@@ -371,11 +371,14 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
  *                 dividing nrhs, at most 2 for WL_F64 and 4 otherwise;
  * rhs_lanes       right-hand sides interleaved across the lanes of every
  *                 wavefront (1, 2, 4 or 8, dividing nrhs; > 1 needs
- *                 rhs_per_thread = 1, a variant other than 7, and
- *                 block / rhs_lanes >= 64, or >= 32 for the t-walks): the
- *                 links of a site are fetched once per load instruction
- *                 for all of them, and a workgroup covers
- *                 block / rhs_lanes sites (t-walk: columns of sites);
+ *                 rhs_per_thread = 1 and block / rhs_lanes >= 64, or >= 32
+ *                 for the t-walks): the links of a site are fetched once
+ *                 per load instruction for all of them, and a workgroup
+ *                 covers block / rhs_lanes sites (t-walk: columns of
+ *                 sites).  Variant 7: right-hand sides per workgroup, each
+ *                 in wavefronts of its own with its own LDS stage, passing
+ *                 the same barriers (so their link loads of a slice hit
+ *                 the caches after the first);
  * xcd_remap       0 natural tile order, 1 one contiguous site range per XCD,
  *                 2..5 one z-slab per XCD, walked in y-chunks of
  *                 Ly >> (xcd_remap - 2) rows, each chunk t-major (needs
@@ -387,13 +390,16 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream);
  *                 WL_F64), 3 (16-bit formats only), or a t-walk 4, 5, 6
  *                 (columns of 4, 8, 16 sites along t; Lt divisible by that;
  *                 block <= 256), or 7, the LDS-staged brick walk: a
- *                 workgroup of brick[0] x brick[1] x brick[2] = block
- *                 threads (64..256) owns that brick of (x, y, z) sites and
+ *                 workgroup of brick[0] x brick[1] x brick[2] (64..256,
+ *                 a multiple of 64) threads per right-hand side owns that
+ *                 brick of (x, y, z) sites and
  *                 walks t_steps t-slices; each slice's spinors of the brick
  *                 and of its face halos are staged in LDS (the halo by
  *                 direct-to-LDS copies) and the spatial neighbours are read
  *                 from there (brick extents dividing Lx, Ly, Lz; t_steps
- *                 dividing Lt; rhs_per_thread = rhs_lanes = 1; Wilson ops).
+ *                 dividing Lt; block = brick sites x rhs_lanes <= 256,
+ *                 rhs_lanes 1, 2 or 4, the stages of all of them within
+ *                 the LDS; rhs_per_thread = 1; Wilson ops).
  * brick, t_steps  variant 7 only (ignored otherwise).
  * wg_per_cu       variant 7 only (else 0): 0 no cap, or 1, 2, 4, 8 -- each
  *                 workgroup reserves 1/wg_per_cu of the CU's 160 KB of LDS,

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwilson.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["wl_stencil_f64.hip", "wl_stencil_f32.hip", "wl_stencil_bf16.hip", "wl_stencil_f16.hip", "wl_stencil.hip", "wl_eo.hip", "wl_pack.hip", "wl_blas.hip", "wl_solver.cpp", "wl_api.cpp"]
+SOURCES = ["wl_stencil_f64.hip", "wl_stencil_f32.hip", "wl_stencil_bf16.hip", "wl_stencil_f16.hip", "wl_brick_multi.hip",
+           "wl_stencil.hip", "wl_eo.hip", "wl_pack.hip", "wl_blas.hip", "wl_solver.cpp", "wl_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -297,53 +297,62 @@ static bool launch_ok(const wl_op *op, int nrhs, const LaunchCfg &c)
     const int prec = op->prec;
     if (op->ns > 0 && (c.rpt != 1 || c.var == 3 || c.var > 6 || nrhs % op->ns != 0))
         return false;  // domain wall: one slice per thread, variants 0..2 and the t-walks
-    // columns across lanes: at least 64 sites per workgroup, 32 for the t-walks
+    // columns across lanes: at least 64 sites per workgroup, 32 for the
+    // t-walks; the brick walk takes rhs_lanes right-hand sides per workgroup
     const bool lanes_ok = c.lanes == 1 || ((c.lanes == 2 || c.lanes == 4 || c.lanes == 8) && c.rpt == 1 &&
-                                           c.var != VAR_BRICK && nrhs % c.lanes == 0 &&
-                                           c.block / c.lanes >= (c.var >= 4 ? 32 : 64));
+                                           nrhs % c.lanes == 0 &&
+                                           (c.var == VAR_BRICK || c.block / c.lanes >= (c.var >= 4 ? 32 : 64)));
     return c.block >= 64 && c.block <= 512 && c.block % 64 == 0 && c.rpt >= 1 && c.rpt <= max_rpt(prec) &&
            nrhs % c.rpt == 0 && lanes_ok && c.xcd >= 0 && c.xcd <= 5 &&
            (c.xcd < 2 || slab_ok(op->g.dims, c.block / c.lanes, c.xcd)) && c.var >= 0 && c.var <= max_var(prec) &&
            var_ok(prec, c.var) && (c.var == 0 || c.rpt == 1) &&
            (c.var < 4 || c.var == VAR_BRICK ||
             (c.block <= 256 && op->g.dims[3] % (c.var == 4 ? 4 : c.var == 5 ? 8 : 16) == 0)) &&
-           (c.var != VAR_BRICK || (op->ns == 0 && c.lanes == 1 && c.bx * c.by * c.bz == c.block &&
-                                   brick_ok(op->g.dims, prec, c.bx, c.by, c.bz, c.tsteps, c.wpe))) &&
+           (c.var != VAR_BRICK || (op->ns == 0 && c.bx * c.by * c.bz * c.lanes == c.block &&
+                                   brick_ok(op->g.dims, prec, c.bx, c.by, c.bz, c.tsteps, c.wpe, c.lanes))) &&
            (c.wpe == 0 || c.var == VAR_BRICK) && (c.gmaj == 0 || c.gmaj == 1);
 }
 
 // Brick shapes (variant 7) for extents L: x extent 8, 16 or 32, the rest
 // as close to cubic as the divisors allow, 128 or 256 sites; walks of 4, 8
-// or 16 t-slices.
-static void brick_candidates(const wl_op *op, std::vector<LaunchCfg> &out)
+// or 16 t-slices.  With several right-hand sides also 64- and 128-site
+// bricks (x extent 4 too) holding 2 or 4 of them per workgroup.
+static void brick_candidates(const wl_op *op, int nrhs, std::vector<LaunchCfg> &out)
 {
     const int *L = op->g.dims;
     if (op->ns > 0)
         return;
-    const int blocks[] = {128, 256};
-    const int bxs[] = {8, 16, 32};
+    const int sites[] = {64, 128, 256};
+    const int bxs[] = {4, 8, 16, 32};
     const int ts[] = {4, 8, 16};
-    for (int block : blocks)
-        for (int bx : bxs) {
-            if (block % bx != 0)
+    for (int rw = 1; rw <= 4; rw *= 2) {
+        if (nrhs % rw != 0)
+            continue;
+        for (int nb : sites) {
+            if ((rw == 1 && nb == 64) || nb * rw > 256)
                 continue;
-            const int rest = block / bx;
-            for (int by = 1; by <= rest; by *= 2) {
-                const int bz = rest / by;
-                if (by * bz != rest || by > 4 * bz || bz > 4 * by)
+            for (int bx : bxs) {
+                if (nb % bx != 0 || (bx == 4 && rw == 1))
                     continue;
-                for (int T : ts)
-                    for (int xcd = 0; xcd <= 1; ++xcd) {
-                        LaunchCfg c{block, 1, xcd, VAR_BRICK, 1};
-                        c.bx = bx;
-                        c.by = by;
-                        c.bz = bz;
-                        c.tsteps = T;
-                        if (brick_ok(L, op->prec, bx, by, bz, T))
-                            out.push_back(c);
-                    }
+                const int rest = nb / bx;
+                for (int by = 1; by <= rest; by *= 2) {
+                    const int bz = rest / by;
+                    if (by * bz != rest || by > 4 * bz || bz > 4 * by)
+                        continue;
+                    for (int T : ts)
+                        for (int xcd = 0; xcd <= 1; ++xcd) {
+                            LaunchCfg c{nb * rw, 1, xcd, VAR_BRICK, rw};
+                            c.bx = bx;
+                            c.by = by;
+                            c.bz = bz;
+                            c.tsteps = T;
+                            if (brick_ok(L, op->prec, bx, by, bz, T, 0, rw))
+                                out.push_back(c);
+                        }
+                }
             }
         }
+    }
 }
 
 // Launch configurations are kept per (nrhs, fused reduction, dagger): the
@@ -1185,7 +1194,7 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
                     }
     {
         std::vector<LaunchCfg> bc;
-        brick_candidates(op, bc);
+        brick_candidates(op, nrhs, bc);
         for (const LaunchCfg &c : bc)
             if (launch_ok(op, nrhs, c))
                 cands.push_back(c);

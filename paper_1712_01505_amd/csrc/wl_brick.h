@@ -21,6 +21,13 @@
 // early and carried.  Links are read by the threads that use them, straight
 // into registers.
 //
+// Several right-hand sides per workgroup (RW > 1): the workgroup is RW
+// copies of the brick's threads, copy r serving right-hand side
+// group x RW + r with its own LDS stage; all copies pass the same barriers,
+// so they load the links of a slice within one step of each other (served
+// once from HBM, the rest from L1 / L2) -- the gauge field is common to every
+// right-hand side (Sec. II-B).
+//
 // The hops are accumulated in the order +x, -x, +y, -y, +z, -z, +t, -t as in
 // every other variant, so FP64 and FP32 results are bit-identical to them
 // (16-bit storage: equal to rounding, as for the t-walk).
@@ -41,6 +48,8 @@ struct BrickGeom {
     int NH;           // halo slots in use
     int NHG;          // halo slot groups of 64 (one direct-to-LDS load per group and chunk)
     int NSP;          // slots per chunk in LDS: NB + 64 NHG
+    int RW;           // right-hand sides per workgroup (workgroup = RW NB threads)
+    uint32_t stage;   // LDS bytes of one right-hand side's stage
     int hoff[7];      // first halo slot of face -x, +x, -y, +y, -z, +z (hoff[6] = NH)
     uint32_t nxyz;    // Lx Ly Lz
     uint32_t nbrick;  // bricks per t-slice
@@ -122,7 +131,7 @@ __device__ __forceinline__ uint32_t halo_site(const StencilParams &p, const Bric
     return (uint32_t)c[0] + (uint32_t)p.L[0] * ((uint32_t)c[1] + (uint32_t)p.L[1] * (uint32_t)c[2]);
 }
 
-template <int P, int DAG, int RED, int APPLY>
+template <int P, int DAG, int RED, int APPLY, int MULTI>
 __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g)
 {
     using R_ = typename Traits<P>::real;
@@ -131,16 +140,27 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
     constexpr int NV = red_nval(RED);
     constexpr int SF = DAG ? 1 : -1;  // forward hops use (1 + SF g), backward (1 - SF g)
     constexpr bool LINKS_EARLY = Traits<P>::SCALED;  // FP32 and FP64 load each hop's link where it is used (registers)
-    extern __shared__ __align__(16) char smem[];
+    extern __shared__ __align__(16) char smem_all[];
     __shared__ double lds_red[(NV > 0 ? NV : 1) * 4];
-    int rhs;
-    const uint32_t bt = tile_group(p, rhs);
-    if (p.skip && p.skip[rhs].frozen)
-        return;
+    int grp;
+    const uint32_t bt = tile_group(p, grp);
+    // this thread's right-hand side within the workgroup: uniform per
+    // wavefront (NB is a multiple of 64), kept in a scalar register so that
+    // the address arithmetic that depends on it stays scalar
+    const int rl = MULTI ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) / (g.NB >> 6)) : 0;
+    const int rhs = MULTI ? grp * g.RW + rl : grp;
+    if (p.skip) {
+        bool all = true;
+        for (int r = 0; r < (MULTI ? g.RW : 1); ++r)
+            all = all && p.skip[(MULTI ? grp * g.RW : grp) + r].frozen;
+        if (all)
+            return;
+    }
+    char *smem = smem_all + (size_t)rl * g.stage;
     const uint32_t unit = tile_of(bt, p.ntile, p.xcd ? 1 : 0);
     const uint32_t chunk = fdiv(unit, g.f_nbrick);
     const uint32_t brick = unit - chunk * g.nbrick;
-    const int tid = (int)threadIdx.x;
+    const int tid = (int)threadIdx.x - rl * g.NB;
     double red[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < (NV > 0 ? NV : 1); ++i)
@@ -183,7 +203,7 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
             }
         }
         // halo slots this wavefront copies: groups w, w + nw, ... (at most 4)
-        const int lane = tid & 63, w = tid >> 6, nw = (int)(blockDim.x >> 6);
+        const int lane = tid & 63, w = tid >> 6, nw = g.NB >> 6;
         uint32_t hsite[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -360,11 +380,36 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
         }
     }
     if constexpr (NV > 0) {
-        block_sum<NV>(red, lds_red);
-        if (threadIdx.x == 0) {
+        if constexpr (!MULTI) {
+            block_sum<NV>(red, lds_red);
+            if (threadIdx.x == 0) {
 #pragma unroll
-            for (int k = 0; k < NV; ++k)
-                p.partials[((size_t)k * p.nrhs + rhs) * p.nblk + bt] = red[k];
+                for (int k = 0; k < NV; ++k)
+                    p.partials[((size_t)k * p.nrhs + rhs) * p.nblk + bt] = red[k];
+            }
+        } else {
+            // per right-hand side: wavefront sums, then thread r adds the
+            // wavefronts of copy r in order
+            const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6, nwv = (int)blockDim.x >> 6;
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                red[i] = wave_sum(red[i]);
+            if (lane == 0) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    lds_red[i * nwv + wv] = red[i];
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < g.RW) {
+                const int per = g.NB >> 6, r = (int)threadIdx.x;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    double a = 0.0;
+                    for (int j = 0; j < per; ++j)
+                        a += lds_red[k * nwv + r * per + j];
+                    p.partials[((size_t)k * p.nrhs + grp * g.RW + r) * p.nblk + bt] = a;
+                }
+            }
         }
     }
 }
@@ -375,9 +420,10 @@ inline size_t brick_lds_bytes(int prec, int nsp)
     return (size_t)nsp * (prec == F64 ? 192 : prec == F32 ? 96 : 52);
 }
 
-// Brick geometry for launch shape (bx, by, bz, T) on extents L; false if the
-// shape does not tile the lattice or exceeds the kernel's limits.
-inline bool brick_setup(const int *L, int prec, int bx, int by, int bz, int T, BrickGeom &g)
+// Brick geometry for launch shape (bx, by, bz, T) with rw right-hand sides
+// per workgroup on extents L; false if the shape does not tile the lattice
+// or exceeds the kernel's limits.
+inline bool brick_setup(const int *L, int prec, int bx, int by, int bz, int T, BrickGeom &g, int rw = 1)
 {
     const int B[3] = {bx, by, bz};
     const int nbk = bx * by * bz;
@@ -404,7 +450,11 @@ inline bool brick_setup(const int *L, int prec, int bx, int by, int bz, int T, B
     if (g.NHG > 4 * (nbk / 64))
         return false;  // at most four halo groups per wavefront
     g.NSP = nbk + 64 * g.NHG;
-    if (brick_lds_bytes(prec, g.NSP) > 160 * 1024 - 1024)
+    if ((rw != 1 && rw != 2 && rw != 4) || nbk * rw > 256)
+        return false;  // at most 256 threads: the walk's registers need the 256-thread budget
+    g.RW = rw;
+    g.stage = (uint32_t)brick_lds_bytes(prec, g.NSP);
+    if ((size_t)g.stage * rw > 160 * 1024 - 1024)
         return false;
     g.nxyz = (uint32_t)L[0] * L[1] * L[2];
     g.nbrick = (uint32_t)(g.nb[0] * g.nb[1] * g.nb[2]);
@@ -416,40 +466,59 @@ inline bool brick_setup(const int *L, int prec, int bx, int by, int bz, int T, B
     return true;
 }
 
-template <int P, int DAG, int RED, int APPLY>
-inline hipError_t brick_go(dim3 grid, dim3 block, size_t smem, const StencilParams &p, const BrickGeom &g,
-                           hipStream_t st)
+template <int P, int DAG, int RED, int APPLY, int MULTI>
+inline hipError_t brick_go1(dim3 grid, dim3 block, size_t smem, const StencilParams &p, const BrickGeom &g,
+                            hipStream_t st)
 {
     // dynamic LDS beyond the default 64 KB: raise this kernel's limit to what
     // the launch needs (the kernel's static LDS counts against the same
     // 160 KB, so the limit is set to the size asked for, not to the maximum)
     static size_t granted = 65536;
     if (smem > granted) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brick_kernel<P, DAG, RED, APPLY>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&brick_kernel<P, DAG, RED, APPLY, MULTI>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess)
             return e;
         granted = smem;
     }
-    hipLaunchKernelGGL((brick_kernel<P, DAG, RED, APPLY>), grid, block, smem, st, p, g);
+    hipLaunchKernelGGL((brick_kernel<P, DAG, RED, APPLY, MULTI>), grid, block, smem, st, p, g);
     return hipGetLastError();
 }
+
+template <int P, int DAG, int RED, int APPLY>
+inline hipError_t brick_go(dim3 grid, dim3 block, size_t smem, const StencilParams &p, const BrickGeom &g,
+                           hipStream_t st)
+{
+    return brick_go1<P, DAG, RED, APPLY, 0>(grid, block, smem, p, g, st);
+}
+
+// The form with several right-hand sides per workgroup, launched from its
+// own translation unit (wl_brick_multi.hip): compiled next to it, the
+// one-right-hand-side kernels came out with more registers (FP16 with the
+// <r, D p> reduction: 188 instead of 167, one wave per SIMD fewer).
+template <int P>
+hipError_t brick_multi_dispatch(int dagger, const StencilParams &p, const BrickGeom &g, dim3 grid, dim3 block,
+                                size_t smem, hipStream_t st);
 
 template <int P, int DAG>
 inline hipError_t launch_brick(const LaunchCfg &cfg, StencilParams p, hipStream_t st)
 {
     BrickGeom g{};
-    if (!brick_setup(p.L, P, cfg.bx, cfg.by, cfg.bz, cfg.tsteps, g) || cfg.block != g.NB)
+    if (!brick_setup(p.L, P, cfg.bx, cfg.by, cfg.bz, cfg.tsteps, g, cfg.lanes) || cfg.block != g.NB * g.RW ||
+        p.nrhs % g.RW != 0)
         return hipErrorInvalidValue;
     const uint32_t units = g.nbrick * (uint32_t)(p.L[3] / g.T);
-    set_groups(p, units, (uint32_t)p.nrhs);
+    set_groups(p, units, (uint32_t)(p.nrhs / g.RW));
     if ((uint64_t)p.ntile * p.ng > 0x7fffffffull)
         return hipErrorInvalidValue;
     const dim3 grid(p.ntile * p.ng), block(cfg.block);
-    const size_t need = brick_lds_bytes(P, g.NSP), cap = brick_reserve(cfg.wpe);
+    const size_t need = (size_t)g.stage * g.RW, cap = brick_reserve(cfg.wpe);
     if (cap && need > cap)
         return hipErrorInvalidValue;
     const size_t smem = cap ? cap : need;  // a cap reserves more LDS than the slices need
+    if (g.RW > 1)
+        return brick_multi_dispatch<P>(DAG, p, g, grid, block, smem, st);
     if (!p.apply) {
         if (p.red != RED_NONE)
             return hipErrorInvalidValue;

@@ -157,7 +157,7 @@ bool var_ok(int prec, int var);  // variant exists for this precision
 int stencil_partials(const LaunchCfg &cfg, const int *L, uint32_t V, int nrhs);  // partials per RHS of one launch
 bool slab_ok(const int *L, int block, int mode);  // slab order `mode` usable for these extents and block size
 // variant 7: the brick (bx, by, bz) and walk length T tile extents L and fit the kernel's LDS and halo limits
-bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T, int wpe = 0);
+bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T, int wpe = 0, int rw = 1);
 constexpr size_t LDS_PER_CU = 160 * 1024;
 // dynamic LDS a brick launch reserves for its occupancy cap (0: none)
 inline size_t brick_reserve(int wpe) { return wpe > 0 ? (LDS_PER_CU / (size_t)wpe - 512) / 256 * 256 : 0; }

@@ -30,12 +30,13 @@ namespace wl {
 int max_var(int prec) { return VAR_BRICK; }
 bool var_ok(int prec, int var) { return var <= 1 || var >= 4 || (var == 2 && prec != F64) || (var == 3 && prec >= BF16S); }
 
-bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T, int wpe)
+bool brick_ok(const int *L, int prec, int bx, int by, int bz, int T, int wpe, int rw)
 {
     BrickGeom g{};
-    if (!brick_setup(L, prec, bx, by, bz, T, g))
+    if (!brick_setup(L, prec, bx, by, bz, T, g, rw))
         return false;
-    return wpe == 0 || ((wpe == 1 || wpe == 2 || wpe == 4 || wpe == 8) && brick_lds_bytes(prec, g.NSP) <= brick_reserve(wpe));
+    return wpe == 0 ||
+           ((wpe == 1 || wpe == 2 || wpe == 4 || wpe == 8) && (size_t)g.stage * rw <= brick_reserve(wpe));
 }
 
 bool slab_ok(const int *L, int block, int mode)
@@ -72,8 +73,8 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
     const int lg = cfg.lanes == 1 ? 0 : cfg.lanes == 2 ? 1 : cfg.lanes == 4 ? 2 : cfg.lanes == 8 ? 3 : -1;
     if (cfg.rpt < 1 || cfg.rpt > 4 || p.nrhs % cfg.rpt != 0 || cfg.block < 64 || cfg.block > 512 ||
         cfg.block % 64 != 0 || lg < 0 ||
-        (lg > 0 && (cfg.rpt != 1 || cfg.var == VAR_BRICK || p.nrhs % cfg.lanes != 0 ||
-                    (cfg.block >> lg) < (cfg.var >= 4 ? 32 : 64))))
+        (lg > 0 && (cfg.rpt != 1 || p.nrhs % cfg.lanes != 0 ||
+                    (cfg.var != VAR_BRICK && (cfg.block >> lg) < (cfg.var >= 4 ? 32 : 64)))))
         return hipErrorInvalidValue;
     if (p.apply == 2 && (cfg.rpt != 1 || (cfg.var > 2 && cfg.var < 4) || cfg.var > 6 || p.ns < 1 || p.nrhs % p.ns != 0))
         return hipErrorInvalidValue;  // domain wall: one slice per thread, variants 0..2 and the t-walks

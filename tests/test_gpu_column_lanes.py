@@ -1,10 +1,11 @@
-"""The t-walks (variants 4, 5) with several right-hand sides interleaved
-across the lanes of each wavefront: the link of a site is fetched once per
-load instruction for all of them (Sec. II-B: the gauge field is common to
-every column).  Outputs equal the one-column-per-lane walk bit for bit in
-FP64 and FP32, the fused reductions of the solvers equal the inner products
-of the stored vectors column by column, and the tile counts include grids
-with idle units (nxyz not a multiple of the tile)."""
+"""Launch shapes in which several columns share the gauge field (Sec. II-B:
+it is common to every right-hand side): the t-walks (variants 4, 5) with
+right-hand sides interleaved across the lanes of each wavefront, and the
+brick walk (variant 7) with several right-hand sides per workgroup.
+Outputs equal the one-column shapes bit for bit in FP64 and FP32, the fused
+reductions of the solvers equal the inner products of the stored vectors
+column by column, and the t-walk tile counts include grids with idle units
+(nxyz not a multiple of the tile)."""
 import numpy as np
 import pytest
 
@@ -132,6 +133,93 @@ def test_group_major_brick_and_solver_columns(W, oracle_mod):
     assert W.try_set_launch(op64.handle, 4, 128, 1, 1, 4, 2, rhs_major=1)
     x, st = W.solve(None, torch.from_numpy(b).cuda(), KAPPA, method="cgnr", tol=1e-10, return_stats=True,
                     ops=(op64, None))
+    xs = x.cpu().numpy()
+    for r in range(4):
+        assert st[r]["status"] == 0, st[r]
+        res = b[r] - oracle_mod.apply(U, xs[r], KAPPA)
+        assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(b[r]), r
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
+def test_brick_several_rhs_per_workgroup(W, oracle_mod, prec):
+    """The brick walk holding 2 or 4 right-hand sides per workgroup (each
+    with its own LDS stage, all behind the same barriers): every column equals
+    the one-right-hand-side brick (bit for bit in FP64 / FP32), in both group
+    orders, for the plain apply and every fused reduction of the solvers,
+    whose inner products equal those of the stored vectors."""
+    dims = (8, 8, 8, 8)
+    nrhs = 8
+    U = inputs.near_unity_gauge(dims, 0.3, seed=31)
+    psi = inputs.gaussian_spinor(dims, seed=32, nrhs=nrhs)
+    vv = inputs.gaussian_spinor(dims, seed=33, nrhs=nrhs)
+    p = W.PREC[prec]
+    op = W.Operator.create(torch.from_numpy(U).cuda(), KAPPA, p)
+    src = op.pack(torch.from_numpy(psi).cuda())
+    vsrc = op.pack(torch.from_numpy(vv).cuda())
+    inq = op.unpack(src, nrhs).cpu().numpy()
+    vq = op.unpack(vsrc, nrhs).cpu().numpy()
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "f16": 3e-3}[prec]
+    for dagger in (False, True):
+        ref = np.stack([oracle_mod.apply(U, psi[r], KAPPA, dagger=dagger) for r in range(nrhs)])
+        assert W.try_set_launch(op.handle, nrhs, 128, 1, 1, W.VAR_BRICK, 1, brick=(8, 4, 4), t_steps=4)
+        base = op.new_field(nrhs)
+        op.apply_packed(base, src, nrhs, dagger)
+        base = op.unpack(base, nrhs)
+        n = 0
+        for rw, brick, T, gm, xcd in ((2, (8, 4, 4), 4, 0, 1), (4, (4, 4, 4), 8, 0, 0), (4, (4, 4, 4), 4, 1, 1),
+                                      (2, (4, 4, 4), 8, 1, 0)):
+            block = brick[0] * brick[1] * brick[2] * rw
+            assert W.try_set_launch(op.handle, nrhs, block, 1, xcd, W.VAR_BRICK, rw, brick=brick, t_steps=T,
+                                    rhs_major=gm), (rw, brick, T)
+            cfg = (dagger, rw, brick, T, gm, xcd)
+            dst = op.new_field(nrhs)
+            op.apply_packed(dst, src, nrhs, dagger)
+            out = op.unpack(dst, nrhs)
+            if prec in ("f64", "f32"):
+                assert torch.equal(out, base), cfg
+            else:
+                assert np.linalg.norm((out - base).cpu().numpy()) <= 1e-6 * torch.linalg.norm(base).item(), cfg
+            oc = out.cpu().numpy()
+            for r in range(nrhs):
+                assert np.linalg.norm(oc[r] - ref[r]) <= tol * np.linalg.norm(ref[r]), cfg + (r,)
+            for kind in (W.WL_DOT_BICG, W.WL_DOT_V, W.WL_DOT_NORM):
+                d2 = op.new_field(nrhs)
+                dots = W.apply_dot(op, d2, src, vsrc, dagger=dagger, nrhs=nrhs, kind=kind).cpu().numpy()
+                oq = op.unpack(d2, nrhs).cpu().numpy()
+                for r in range(nrhs):
+                    for g_, w_ in zip(_got(kind, W, dots[:, r]), _want(kind, W, inq[r], oq[r], vq[r])):
+                        assert abs(g_ - w_) <= 1e-12 * max(abs(w_), 1e-300) + 1e-9, cfg + (kind, r, g_, w_)
+            n += 1
+        assert n == 4
+
+
+def test_brick_several_rhs_rejected_shapes(W):
+    """More than 256 threads, 8 right-hand sides per workgroup, a count not
+    dividing the columns, stages beyond the LDS: rejected."""
+    dims = (8, 8, 8, 8)
+    U = inputs.near_unity_gauge(dims, 0.3, seed=1)
+    op = W.Operator.create(torch.from_numpy(U).cuda(), KAPPA, W.WL_F64)
+    B = W.VAR_BRICK
+    assert W.try_set_launch(op.handle, 4, 256, 1, 0, B, 4, brick=(4, 4, 4), t_steps=4)
+    assert not W.try_set_launch(op.handle, 4, 512, 1, 0, B, 4, brick=(8, 4, 4), t_steps=4)   # 512 threads
+    assert not W.try_set_launch(op.handle, 8, 512, 1, 0, B, 8, brick=(4, 4, 4), t_steps=4)   # 8 per workgroup
+    assert not W.try_set_launch(op.handle, 6, 256, 1, 0, B, 4, brick=(4, 4, 4), t_steps=4)   # 4 does not divide 6
+    assert not W.try_set_launch(op.handle, 4, 256, 1, 0, B, 4, brick=(8, 4, 4), t_steps=4)   # block != sites x 4
+    assert W.wl_get_launch(op.handle, 4)[4] == 4
+
+
+def test_brick_several_rhs_in_a_solve(W, oracle_mod):
+    """A 4-column mixed FP32 BiCGStab whose inner stencils run the brick with
+    two right-hand sides per workgroup reaches the oracle's residual."""
+    dims = (8, 8, 8, 8)
+    U = inputs.near_unity_gauge(dims, 0.3, seed=41)
+    b = inputs.gaussian_spinor(dims, seed=42, nrhs=4)
+    Ud = torch.from_numpy(U).cuda()
+    hi = W.Operator.create(Ud, KAPPA, W.WL_F64)
+    lo = W.Operator.create(Ud, KAPPA, W.WL_F32)
+    assert W.try_set_launch(lo.handle, 4, 256, 1, 1, W.VAR_BRICK, 2, brick=(8, 4, 4), t_steps=4)
+    x, st = W.solve(None, torch.from_numpy(b).cuda(), KAPPA, method="bicgstab", tol=1e-10, return_stats=True,
+                    ops=(hi, lo))
     xs = x.cpu().numpy()
     for r in range(4):
         assert st[r]["status"] == 0, st[r]
