@@ -109,9 +109,24 @@ def test_bad_arguments_rejected_before_launch():
         assert setb(64, (4, 4, 4), 3) == wilson.WL_EINVAL  # 3 does not divide Lt = 4
         assert setb(128, (4, 4, 4), 4) == wilson.WL_EINVAL  # block != brick sites
         assert setb(64, (8, 4, 2), 4) == wilson.WL_EINVAL  # 8 does not divide Lx = 4
-        assert setb(64, (4, 4, 4), 4, nrhs=2, lanes=2) == wilson.WL_EINVAL  # one right-hand side per lane
+        # several right-hand sides per brick workgroup: block = brick sites x count, at most 256 threads
+        assert setb(64, (4, 4, 4), 4, nrhs=2, lanes=2) == wilson.WL_EINVAL  # block != 64 sites x 2
+        assert setb(512, (4, 4, 4), 4, nrhs=8, lanes=8) == wilson.WL_EINVAL  # at most 4 per workgroup
+        assert setb(256, (4, 4, 4), 4, nrhs=6, lanes=4) == wilson.WL_EINVAL  # 4 does not divide 6
+        assert setb(128, (4, 4, 4), 4, nrhs=2, lanes=2) == wilson.WL_OK
+        assert L.wl_get_launch(op, 2, ctypes.byref(got)) == wilson.WL_OK
+        assert (got.block, got.rhs_lanes, got.variant) == (128, 2, 7)
         assert L.wl_get_launch(op, 1, ctypes.byref(got)) == wilson.WL_OK
         assert (got.variant, tuple(got.brick), got.t_steps) == (7, (4, 4, 4), 4)
+        # t-walks with right-hand sides across lanes (at least 32 sites per workgroup) and the group order
+        assert setl(8, 256, 1, 0, 4, lanes=8) == wilson.WL_OK
+        assert setl(8, 128, 1, 0, 4, lanes=8) == wilson.WL_EINVAL
+        c = wilson.wl_launch(block=256, rhs_per_thread=1, rhs_lanes=2, xcd_remap=1, variant=4, rhs_major=2)
+        assert L.wl_set_launch(op, 8, ctypes.byref(c)) == wilson.WL_EINVAL  # group order 0 or 1
+        c.rhs_major = 1
+        assert L.wl_set_launch(op, 8, ctypes.byref(c)) == wilson.WL_OK
+        assert L.wl_get_launch(op, 8, ctypes.byref(got)) == wilson.WL_OK
+        assert (got.rhs_lanes, got.variant, got.rhs_major) == (2, 4, 1)
         # fused apply + inner products: argument checks happen before any launch
         wb = ctypes.c_size_t(0)
         assert L.wl_apply_dot_workspace_bytes(op, 1, ctypes.byref(wb)) == wilson.WL_OK and wb.value % 256 == 0
@@ -304,3 +319,51 @@ def test_multi_solve_arguments_rejected():
     finally:
         for h in ops:
             L.wl_op_destroy(h)
+
+
+def test_profiling_shapes_summary(tmp_path):
+    """The per-launch-shape summary pairs dispatches three by three with the
+    printed shapes, sums counter rows per dispatch and scales them by the
+    copy calibration; a count mismatch is refused."""
+    import csv
+    import json
+    from paper_1712_01505_amd import profiling
+
+    def write(path, rows, fields):
+        path.parent.mkdir(parents=True, exist_ok=True)
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=fields)
+            w.writeheader()
+            for r in rows:
+                w.writerow(r)
+
+    k = "void wl::stencil_kernel<1, 0, 1, 0, 2, 2>(wl::StencilParams)"
+    write(tmp_path / "t" / "s_kernel_trace.csv",
+          [{"Dispatch_Id": i, "Kernel_Name": k, "Start_Timestamp": 1000 * i, "End_Timestamp": 1000 * i + 2000}
+           for i in range(1, 7)], ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+    cf = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    for d, c, v in (("f", "FETCH_SIZE", 500.0), ("w", "WRITE_SIZE", 1000.0)):
+        # two rows per dispatch (one per XCD, say): summed
+        write(tmp_path / d / "s_counter_collection.csv",
+              [{"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v} for i in range(1, 7)
+               for _ in range(2)], cf)
+    for d, c, v in (("cf", "FETCH_SIZE", 512.0), ("cw", "WRITE_SIZE", 1024.0)):
+        write(tmp_path / d / "s_counter_collection.csv",
+              [{"Dispatch_Id": 1, "Kernel_Name": "void wl::stream_copy_kernel(x)", "Counter_Name": c,
+                "Counter_Value": v}], cf)
+    log = tmp_path / "case.log"
+    log.write_text("".join(json.dumps({"case": f"c{j}", "launch": [256, 1, 1, 2, 1, 0, 0, 0, 0, 0, 0],
+                                       "compulsory_read": 1024000, "compulsory_write": 2048000}) + "\n"
+                           for j in range(2)))
+    out = tmp_path / "out.md"
+    profiling.shapes(str(tmp_path / "t"), str(tmp_path / "f"), str(tmp_path / "w"), str(log), str(tmp_path / "cf"),
+                     str(tmp_path / "cw"), "1", str(out), "cmd")
+    rows = [l for l in out.read_text().splitlines() if l.startswith("| c") and not l.startswith("| case")]
+    assert len(rows) == 2
+    cells = [x.strip() for x in rows[0].split("|")]
+    # 2 us per dispatch; read = 2 x 500 KiB x (1024 / 512) = 2048000 B; write = 2 x 1000 KiB x 1 = 2048000 B
+    assert cells[4] == "2.0" and cells[5] == "2" and cells[6] == "2.00" and cells[7] == "2" and cells[8] == "1.00"
+    log.write_text(log.read_text().splitlines()[0] + "\n")
+    with pytest.raises(SystemExit):
+        profiling.shapes(str(tmp_path / "t"), str(tmp_path / "f"), str(tmp_path / "w"), str(log),
+                         str(tmp_path / "cf"), str(tmp_path / "cw"), "1", str(out), "cmd")
