@@ -56,7 +56,8 @@ __device__ __forceinline__ void round_if_scaled(cx<typename Traits<P>::real> (&v
 // partial sums)
 __host__ __device__ constexpr int blas_nv(int op)
 {
-    return (op == B_RES || op == B_CG_XR || op == B_NORM || op == B_BI_XRP || op == B_CG1 || op == B_SR_XR) ? 1
+    return (op == B_RES || op == B_CG_XR || op == B_NORM || op == B_BI_XRP || op == B_CG1 || op == B_SR_XR ||
+            op == B_INIT)                                                                                   ? 1
            : (op == B_BI_XR || op == B_DOT_NORM)                                                           ? 3
            : op == B_SR_PV                                                                                 ? 9
                                                                                                            : 0;
@@ -293,6 +294,19 @@ __global__ __launch_bounds__(256) void blas_kernel(BlasParams p)
             for (int k = 0; k < 12; ++k)
                 v[k] = cx<T>{T(0), T(0)};
             store_site<P>(Y0, V, nr, s, r, v);
+        } else if constexpr (OP == B_INIT) {  // x = 0 ; r (and y2, y3) = b ; |b|^2
+            cx<T> v[12], z[12];
+            load_site<P>(A0, V, nr, s, r, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                z[k] = cx<T>{T(0), T(0)};
+            store_site<P>(Y0, V, nr, s, r, z);
+            store_site<P>(Y1, V, nr, s, r, v);
+            if (Y2)
+                store_site<P>(Y2, V, nr, s, r, v);
+            if (Y3)
+                store_site<P>(Y3, V, nr, s, r, v);
+            red[0] += n2(v);
         } else if constexpr (OP == B_NORM) {
             cx<T> v[12];
             load_site<P>(A0, V, nr, s, r, v);
@@ -342,6 +356,7 @@ static hipError_t launch_blas_p(int op, const BlasParams &p, dim3 g, dim3 b, hip
     case B_CG1: hipLaunchKernelGGL((blas_kernel<P, B_CG1>), g, b, 0, st, p); break;
     case B_SR_PV: hipLaunchKernelGGL((blas_kernel<P, B_SR_PV>), g, b, 0, st, p); break;
     case B_SR_XR: hipLaunchKernelGGL((blas_kernel<P, B_SR_XR>), g, b, 0, st, p); break;
+    case B_INIT: hipLaunchKernelGGL((blas_kernel<P, B_INIT>), g, b, 0, st, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -342,6 +342,8 @@ __global__ __launch_bounds__(256) void brick_kernel(StencilParams p, BrickGeom g
                 for (int i = 0; i < 12; ++i)
                     o[i] = acc[i];
             }
+            if constexpr (APPLY == 3)
+                residual_epilogue<P>(p, s, rhs, o);
             store_site_q<P, true>(p.out, p.V, p.nrhs, s, rhs, o);
             if constexpr (RED == RED_NORM || RED == RED_DOTIN_NORM) {
 #pragma unroll
@@ -519,6 +521,15 @@ inline hipError_t launch_brick(const LaunchCfg &cfg, StencilParams p, hipStream_
     const size_t smem = cap ? cap : need;  // a cap reserves more LDS than the slices need
     if (g.RW > 1)
         return brick_multi_dispatch<P>(DAG, p, g, grid, block, smem, st);
+    if (p.apply == 3) {  // the residual aux - D in (FP64 / FP32)
+        if constexpr (P == F64 || P == F32) {
+            if (p.red == RED_NONE)
+                return brick_go<P, DAG, RED_NONE, 3>(grid, block, smem, p, g, st);
+            if (p.red == RED_NORM)
+                return brick_go<P, DAG, RED_NORM, 3>(grid, block, smem, p, g, st);
+        }
+        return hipErrorInvalidValue;
+    }
     if (!p.apply) {
         if (p.red != RED_NONE)
             return hipErrorInvalidValue;

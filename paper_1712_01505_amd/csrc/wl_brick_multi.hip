@@ -14,6 +14,15 @@ static hipError_t brick_multi_d(const StencilParams &p, const BrickGeom &g, dim3
             return hipErrorInvalidValue;
         return brick_go1<P, DAG, RED_NONE, 0, 1>(grid, block, smem, p, g, st);
     }
+    if (p.apply == 3) {  // the residual aux - D in (FP64 / FP32)
+        if constexpr (P == F64 || P == F32) {
+            if (p.red == RED_NONE)
+                return brick_go1<P, DAG, RED_NONE, 3, 1>(grid, block, smem, p, g, st);
+            if (p.red == RED_NORM)
+                return brick_go1<P, DAG, RED_NORM, 3, 1>(grid, block, smem, p, g, st);
+        }
+        return hipErrorInvalidValue;
+    }
     if (p.apply != 1)
         return hipErrorInvalidValue;
     switch (p.red) {

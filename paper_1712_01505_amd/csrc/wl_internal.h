@@ -84,7 +84,8 @@ struct StencilParams {
     uint32_t V;
     int nrhs;
     double kappa;
-    int apply;  // 1: out = in - kappa H in; 0: out = H in; 2: domain wall (ns, dw_diag, dw_m)
+    int apply;  // 1: out = in - kappa H in; 0: out = H in; 2: domain wall (ns, dw_diag, dw_m);
+                // 3: out = aux - (in - kappa H in), the residual of D in = aux (FP64 / FP32)
     int ns;          // apply 2: columns r form 5-d vectors of ns slices (s = r mod ns)
     double dw_diag;  // apply 2: m0 + 5 (the diagonal of D_W + 1); the hop enters with -1/2
     double dw_m;     // apply 2: quark mass m of the corner blocks
@@ -229,8 +230,10 @@ enum BlasOp {
     B_SR_PV = 13,     // BiCGStab: p = r + beta (p - omega v) ; v = u + beta (v - omega q) ;
                       // <rh, v>, <rh, u>, <u, r>, <u, v>, |u|^2  (9 values;
                       // y0 = p, y1 = v, a0 = r, a1 = u, a2 = q, a3 = rh)
-    B_SR_XR = 14      // BiCGStab: s = r - alpha v ; x += alpha p + omega s ; r = s - omega (u - alpha q) ;
+    B_SR_XR = 14,     // BiCGStab: s = r - alpha v ; x += alpha p + omega s ; r = s - omega (u - alpha q) ;
                       // |r|^2  (y0 = x, y1 = r, a0 = p, a1 = v, a2 = u, a3 = q)
+    B_INIT = 15       // start of a run from x = 0: x = 0 ; r = b, and y2, y3 = b where given ; |b|^2
+                      // (y0 = x, y1 = r, a0 = b)
 };
 // One column of a segmented (multi-lattice) vector: its lattice's fields
 // start `off` bytes into every vector buffer, with V sites and nrhs columns,

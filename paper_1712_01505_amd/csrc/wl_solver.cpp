@@ -405,7 +405,7 @@ struct Engine {
     }
 
     int stencil(void *out, const void *in, int dagger, int red, const void *aux, int slot, bool loop = false,
-                const void *aux2 = nullptr, const void *aux3 = nullptr)
+                const void *aux2 = nullptr, const void *aux3 = nullptr, int apply = 1)
     {
         if (!lats.empty())
             return stencil_multi(out, in, dagger ^ adj, red, aux, slot, loop, aux2, aux3);
@@ -455,7 +455,7 @@ struct Engine {
         p.V = V;
         p.nrhs = nrhs;
         p.kappa = op->kappa;
-        p.apply = 1;
+        p.apply = apply;
         p.red = red;
         op_apply_params(op, p);
         LaunchCfg cfg = launch_for(op, nrhs, red, dagger ^ adj);
@@ -587,7 +587,13 @@ struct Engine {
         const double tol2 = tol * tol;
         int rc;
         void *r = v[0];
-        if (zero_x) {
+        // the merged BiCGStab from x = 0: one pass sets x, r, rh and p and
+        // sums |b|^2 (= |r|^2), which the start finalize then reads twice
+        const bool one_pass = zero_x && solver == WL_SOLVER_BICGSTAB && form == 0;
+        if (one_pass) {
+            if ((rc = blas(B_INIT, x, r, b, nullptr, nullptr, nullptr, 0, false, v[1], v[2])))
+                return rc;
+        } else if (zero_x) {
             if ((rc = blas(B_ZERO, x, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return rc;
             if ((rc = blas(B_COPY, r, nullptr, b, nullptr, nullptr, nullptr, -1)))
@@ -601,8 +607,9 @@ struct Engine {
             if ((rc = blas(B_RES, r, nullptr, b, w, nullptr, nullptr, 0)))
                 return rc;
         }
-        if ((rc = blas(B_NORM, nullptr, nullptr, b, nullptr, nullptr, nullptr, 2)))
-            return rc;
+        if (!one_pass)
+            if ((rc = blas(B_NORM, nullptr, nullptr, b, nullptr, nullptr, nullptr, 2)))
+                return rc;
         int it = 0;
         if (solver == WL_SOLVER_CGNR && form == 1) {
             // one reduction phase per iteration: z = D^dag r (|z|^2), q = D z
@@ -702,13 +709,15 @@ struct Engine {
             if (op->ns > 0)
                 return WL_EINVAL;  // BiCGStab is offered for the Wilson operator only
             bool pending_p = false;  // a reliable update replaced r: p is formed from it next
-            if ((rc = blas(B_COPY, rh, nullptr, r, nullptr, nullptr, nullptr, -1)))
-                return rc;
-            if ((rc = blas(B_COPY, p, nullptr, r, nullptr, nullptr, nullptr, -1)))
-                return rc;
+            if (!one_pass) {
+                if ((rc = blas(B_COPY, rh, nullptr, r, nullptr, nullptr, nullptr, -1)))
+                    return rc;
+                if ((rc = blas(B_COPY, p, nullptr, r, nullptr, nullptr, nullptr, -1)))
+                    return rc;
+            }
             if ((rc = blas(B_ZERO, vv, nullptr, nullptr, nullptr, nullptr, nullptr, -1)))
                 return rc;
-            if ((rc = fin(F_INIT_BI, 0, -1, 2, 0, tol2)))
+            if ((rc = fin(F_INIT_BI, 0, -1, one_pass ? 0 : 2, 0, tol2)))
                 return rc;
             WL_TRY(hipStreamSynchronize(st));
             bool stop = host_all_done();
@@ -760,10 +769,16 @@ struct Engine {
     {
         int rc;
         void *w = v[1], *r = v[0];
-        if ((rc = stencil(w, x, 0, RED_NONE, nullptr, -1)))
-            return rc;
-        if ((rc = blas(B_RES, r, nullptr, b, w, nullptr, nullptr, 0)))
-            return rc;
+        if (lats.empty() && !eo && op->ns == 0 && (prec == WL_F64 || prec == WL_F32)) {
+            // one pass: r = b - D x with |r|^2 in the stencil's epilogue
+            if ((rc = stencil(r, x, 0, RED_NORM, b, 0, false, nullptr, nullptr, 3)))
+                return rc;
+        } else {
+            if ((rc = stencil(w, x, 0, RED_NONE, nullptr, -1)))
+                return rc;
+            if ((rc = blas(B_RES, r, nullptr, b, w, nullptr, nullptr, 0)))
+                return rc;
+        }
         if ((rc = fin(F_SUM, 0, -1, -1, 0, 0.0, hb->dev(out_host))))
             return rc;
         WL_TRY(hipStreamSynchronize(st));

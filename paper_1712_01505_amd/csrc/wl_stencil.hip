@@ -78,6 +78,8 @@ hipError_t launch_stencil(int prec, int dagger, const LaunchCfg &cfg, StencilPar
         return hipErrorInvalidValue;
     if (p.apply == 2 && (cfg.rpt != 1 || (cfg.var > 2 && cfg.var < 4) || cfg.var > 6 || p.ns < 1 || p.nrhs % p.ns != 0))
         return hipErrorInvalidValue;  // domain wall: one slice per thread, variants 0..2 and the t-walks
+    if (p.apply == 3 && (!p.aux || (prec != F64 && prec != F32) || (p.red != RED_NONE && p.red != RED_NORM)))
+        return hipErrorInvalidValue;  // residual: FP64 / FP32, with |r|^2 or without
     if (cfg.gmaj != 0 && cfg.gmaj != 1)
         return hipErrorInvalidValue;
     p.lanes_lg = lg;

@@ -476,6 +476,19 @@ __device__ __forceinline__ void dw_epilogue(const StencilParams &p, uint32_t s, 
     }
 }
 
+// Residual epilogue (apply 3): o = aux - o, o holding D in at this site,
+// exactly as a separate pass r = b - w over the stored w would form it.
+template <int P>
+__device__ __forceinline__ void residual_epilogue(const StencilParams &p, uint32_t s, int col,
+                                                  cx<typename Traits<P>::real> (&o)[12])
+{
+    cx<typename Traits<P>::real> b[12];
+    load_site<P>(p.aux, p.V, p.nrhs, s, col, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        o[k] = cx<typename Traits<P>::real>{b[k].re - o[k].re, b[k].im - o[k].im};
+}
+
 // Tile count and right-hand-side groups of a launch (see tile_group).
 inline void set_groups(StencilParams &p, uint32_t tiles, uint32_t ng)
 {

@@ -169,6 +169,8 @@ __global__ __launch_bounds__(256) void twalk_kernel(StencilParams p, int T, uint
                 for (int i = 0; i < 12; ++i)
                     o[i] = acc[i];
             }
+            if constexpr (APPLY == 3)
+                residual_epilogue<P>(p, s, rhs, o);
             store_site_q<P, true>(p.out, p.V, p.nrhs, s, rhs, o);
             if constexpr (RED == RED_NORM || RED == RED_DOTIN_NORM) {
 #pragma unroll
@@ -286,6 +288,8 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 #pragma unroll
                     for (int k = 0; k < 12; ++k)
                         o[k] = cx<T>{fma(-kap, acc[r][k].re, in[k].re), fma(-kap, acc[r][k].im, in[k].im)};
+                    if constexpr (APPLY == 3)
+                        residual_epilogue<P>(p, s, r0 + r, o);
                 } else {
 #pragma unroll
                     for (int k = 0; k < 12; ++k)
@@ -368,6 +372,18 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilParams p)
 template <int P, int DAG, int R, int VAR>
 inline hipError_t launch_v(dim3 grid, dim3 block, const StencilParams &p, hipStream_t st)
 {
+    if (p.apply == 3) {  // the residual aux - D in (FP64 / FP32)
+        if constexpr (P == F64 || P == F32) {
+            if (p.red == RED_NONE)
+                hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NONE, 3, VAR>), grid, block, 0, st, p);
+            else if (p.red == RED_NORM)
+                hipLaunchKernelGGL((stencil_kernel<P, DAG, R, RED_NORM, 3, VAR>), grid, block, 0, st, p);
+            else
+                return hipErrorInvalidValue;
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (p.apply == 2) {  // domain wall: R = 1, variants 0..2, the reductions CG needs
         if constexpr (R == 1 && VAR <= 2) {
             switch (p.red) {
@@ -413,6 +429,18 @@ inline hipError_t launch_twalk(const LaunchCfg &cfg, StencilParams p, hipStream_
     if ((uint64_t)p.ntile * p.ng > 0x7fffffffull)
         return hipErrorInvalidValue;
     dim3 grid(p.ntile * p.ng), block(cfg.block);
+    if (p.apply == 3) {  // the residual aux - D in (FP64 / FP32)
+        if constexpr (P == F64 || P == F32) {
+            if (p.red == RED_NONE)
+                hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NONE, 3>), grid, block, 0, st, p, T, nxyz, nbxyz);
+            else if (p.red == RED_NORM)
+                hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NORM, 3>), grid, block, 0, st, p, T, nxyz, nbxyz);
+            else
+                return hipErrorInvalidValue;
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (p.apply == 2) {  // domain wall: the reductions CG on the normal equations needs
         switch (p.red) {
         case RED_NONE: hipLaunchKernelGGL((twalk_kernel<P, DAG, RED_NONE, 2>), grid, block, 0, st, p, T, nxyz, nbxyz); break;
