@@ -192,7 +192,8 @@ typedef struct {
     int maxiter;          /* Krylov iterations (summed over inner solves when mixed) */
     double inner_tol;     /* mixed: defect correction: relative tolerance of each inner solve;
                              reliable updates: residual drop that triggers an FP64 update
-                             (0 = default: 1e-5 FP32 / 3e-2 16-bit; 0.1 for reliable updates) */
+                             (0 = default: 1e-5 FP32, 3e-2 16-bit, FP16 BiCGStab 0.1;
+                             reliable updates 0.1, FP16 BiCGStab 0.01) */
     int max_outer;        /* mixed: maximum outer (refinement) cycles (0 = default 50) */
     int reliable;         /* mixed: 0 = defect correction (restart the inner solve per cycle),
                              1 = reliable updates (one inner run, FP64 solution and residual
