@@ -1284,11 +1284,16 @@ int wl_autotune(const wl_op *op, int nrhs, int dagger, void *stream)
                 best = cands[timed[j].second];
             }
         }
-        // the best brick walk again with its occupancy capped (workgroups per
-        // CU, i.e. waves per SIMD), which trades latency hiding for L2 reuse
-        if (best.var == VAR_BRICK)
+        // the fastest brick walk of the first pass again with its occupancy
+        // capped (workgroups per CU, i.e. waves per SIMD), which trades latency
+        // hiding for L2 reuse -- also when another variant won uncapped
+        const LaunchCfg *brick0 = nullptr;
+        for (size_t j = 0; j < timed.size() && !brick0; ++j)
+            if (cands[timed[j].second].var == VAR_BRICK)
+                brick0 = &cands[timed[j].second];
+        if (brick0)
             for (int wpe = 1; wpe <= 8 && e == hipSuccess; wpe *= 2) {
-                LaunchCfg c = best;
+                LaunchCfg c = *brick0;
                 c.wpe = wpe;
                 if (!launch_ok(op, nrhs, c))
                     continue;
